@@ -1,0 +1,179 @@
+/*
+ * slicq.h - C ABI of the MI355X (gfx950) sliCQ library.
+ *
+ * The sliced constant-Q nonstationary Gabor transform (sliCQ) of Holighaus,
+ * Doerfler, Velasco and Grill, "A framework for invertible, real-time
+ * constant-Q transforms": a real signal is cut into Tukey-windowed slices of
+ * length 2N at hop N (Section 4, Algorithm 3); each slice is transformed by the
+ * painless constant-Q NSG frame (Section 3, Table 1; Algorithm 1):
+ *
+ *     c^m_{n,k} = <F x_m, M_{-n a_k} g_k> = sum_{j in J_k} X_m[j] g_k[j] e^{2 pi i j n / M_k}
+ *
+ * (equation CQ_coeff with the unitary DFT of Section 2.1), and synthesis
+ * (Algorithm 2 per slice, Algorithm 4 across slices) reconstructs the signal
+ * exactly with the canonical dual windows g~_k = g_k / sum_l M_l g_l^2
+ * (Proposition 2) and the dual slicing window (equation dualwincond).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every int-returning call returns SLICQ_OK (0) or a negative
+ *   slicq_status; slicq_last_error() then gives a message (thread-local).
+ *   No exception crosses the ABI.
+ * - Memory: all device buffers (signals, coefficients, outputs, workspace,
+ *   tables) are owned by the caller and must be device memory of the current
+ *   HIP device (coarse-grained, e.g. hipMalloc). The library allocates no
+ *   device memory in any transform call.
+ * - Streams: transform calls only enqueue work on `hip_stream` (a hipStream_t,
+ *   NULL for the default stream) and never synchronise; launch failures are
+ *   reported as SLICQ_EHIP.
+ * - Plans are immutable after nsgt_plan_upload and may be shared between
+ *   threads; concurrent calls must use distinct output and workspace buffers.
+ * - Real signals: bands 0..K+1 (DC, K constant-Q bands, Nyquist) are stored.
+ *   Bands K+2..2K+1 mirror bands K..1 and carry conjugate coefficients.
+ * - Coefficient layout (band-major, complex interleaved re/im of the dtype):
+ *   band k, slice m, index n < M_k lives at element S * off_k + m * M_k + n,
+ *   off_k = sum_{k' < k} M_k', S = number of slices of the signal.
+ */
+#ifndef SLICQ_H
+#define SLICQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slicq_plan_s* slicq_plan;
+
+typedef enum {
+  SLICQ_OK = 0,
+  SLICQ_EINVAL = -1, /* invalid parameter or plan design (message says which) */
+  SLICQ_ENOMEM = -2, /* host allocation failed */
+  SLICQ_EHIP = -3,   /* a HIP runtime call or kernel launch failed */
+  SLICQ_ESIZE = -4,  /* a caller buffer is too small */
+  SLICQ_EBUSY = -5,  /* streaming server: admission refused (memory budget) */
+  SLICQ_ESTATE = -6  /* call not valid in the current state (e.g. tables not uploaded) */
+} slicq_status;
+
+typedef enum { SLICQ_F32 = 0, SLICQ_F64 = 1 } slicq_dtype;
+
+/* Plan parameters (Section 3: xi_min, xi_max, xi_s, B; Section 4.3: N, M). */
+typedef struct {
+  double fs;                /* sampling rate xi_s in Hz, > 0 */
+  double fmin;              /* xi_min in Hz, 0 < fmin < fs/2 */
+  double fmax;              /* xi_max in Hz, > fmin; >= fs/2 is clamped below Nyquist */
+  int32_t bins_per_octave;  /* B >= 1 */
+  int64_t slice_len;        /* 2N, a power of two in [16, 2^20] */
+  int64_t transition_len;   /* Tukey transition M, 0 < M < N, N - M even */
+  double min_win;           /* minimal band support in bins (Section 5.3), default 16 */
+  int32_t dual_slice;       /* 0: canonical dual h_0 / sum_m T_mN h_0^2, 1: indicator of supp h_0 */
+  int32_t group_cap;        /* tuning: coefficients per analysis work item (power of two), default 4096 */
+  int32_t lds_cap;          /* tuning: complex values per synthesis work item, default 9216 */
+  int32_t pass_cap;         /* tuning: complex values per slice-FFT work item (power of two), default 4096 */
+} slicq_plan_opts;
+
+typedef struct {
+  int32_t K;                /* constant-Q bands 1..K */
+  int32_t nbands;           /* stored bands K + 2 */
+  int64_t slice_len;        /* 2N */
+  int64_t transition_len;   /* M */
+  int64_t coefs_per_slice;  /* sum_k M_k over stored bands */
+  double Q;                 /* Q = (2^{1/B} - 2^{-1/B})^{-1} */
+  int32_t max_M;            /* largest M_k */
+  int32_t n_ana_items;      /* analysis work items per slice */
+  int32_t n_syn_items;      /* synthesis work items per slice */
+  int32_t pad_;
+} slicq_plan_info;
+
+/* Design a plan from the paper's parameters (Section 3, Table 1; Section
+ * 4.3), with min_win = 16 and the canonical dual slicing window. Host only.
+ * Returns SLICQ_EINVAL for parameters outside the ranges in slicq_plan_opts
+ * or a frame that fails Proposition 2's condition. *out receives the plan,
+ * owned by the caller (nsgt_plan_destroy). */
+int nsgt_plan(double fs, double fmin, double fmax, int bins_per_octave, int64_t slice_len_2N,
+              int64_t transition_len, slicq_plan* out);
+
+/* As nsgt_plan with every option explicit; zero tuning fields take defaults. */
+int nsgt_plan_ex(const slicq_plan_opts* opts, slicq_plan* out);
+
+/* Frees the plan's host memory. The caller still owns the device tables. */
+void nsgt_plan_destroy(slicq_plan plan);
+
+int nsgt_plan_info(slicq_plan plan, slicq_plan_info* info);
+
+/* Per stored band k (arrays of nbands entries, any may be NULL): M_k, packing
+ * offset off_k, signed first bin of J_k, |J_k|, centre and bandwidth in Hz
+ * (Table 1). */
+int nsgt_plan_bands(slicq_plan plan, int32_t* M, int64_t* off, int64_t* start, int32_t* len,
+                    double* fc_hz, double* bw_hz);
+
+/* The plan's FP64 tables (any may be NULL): g_k and g~_k over each J_k
+ * concatenated in band order (sum_k |J_k| values each), h_0 and h~_0 over
+ * j = t + N, t in [-N, N) (2N values each), frame-operator diagonal D (2N). */
+int nsgt_plan_windows(slicq_plan plan, double* g, double* gd, double* h0, double* hd, double* D);
+
+/* Bytes of device tables for dtype. */
+int nsgt_plan_table_bytes(slicq_plan plan, slicq_dtype dtype, size_t* bytes);
+
+/* Copies the tables for dtype into caller-owned device memory `dev_tables`
+ * (at least nsgt_plan_table_bytes bytes, 256-byte aligned) on hip_stream and
+ * records the address in the plan. The memory must stay valid while the plan
+ * is used with this dtype. */
+int nsgt_plan_upload(slicq_plan plan, slicq_dtype dtype, void* dev_tables, size_t bytes, void* hip_stream);
+
+/* S = 2 ceil(T / 2N): slices of a signal of T samples (Algorithm 3, L = 2N ceil(T/2N)). */
+int64_t slicq_num_slices(slicq_plan plan, int64_t T);
+
+/* Workspace bytes to process n_slices slices in one pass. Any workspace of at
+ * least the size for one slice (plus the task table of all slices) is
+ * accepted; smaller ones are processed in several passes. */
+int slicq_workspace_size(slicq_plan plan, slicq_dtype dtype, int64_t n_slices, size_t* bytes);
+
+/* Analysis (Algorithm 3 with Algorithm 1 per slice) of x: T real samples of
+ * dtype. coef: coef_count complex values of dtype, band-major (see above),
+ * needs coef_count >= S * coefs_per_slice (else SLICQ_ESIZE). The signal is
+ * zero padded to L = 2N ceil(T/2N) and sliced circularly. */
+int slicq_analyze(slicq_plan plan, slicq_dtype dtype, const void* x, int64_t T, void* coef,
+                  int64_t coef_count, void* work, size_t work_bytes, void* hip_stream);
+
+/* Synthesis (Algorithm 4 with Algorithm 2 per slice, canonical duals) from
+ * coef (S = slicq_num_slices(T) slices, band-major) into y: T real samples.
+ * For real signals the mirrored bands take conjugate coefficients and y is
+ * the real part of the full synthesis. Overwrites all of y. */
+int slicq_synthesize(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t coef_count, void* y,
+                     int64_t T, void* work, size_t work_bytes, void* hip_stream);
+
+/* Adjoint of the real-input analysis: y = Re(A^H coef), the transpose of
+ * slicq_analyze for the real inner product. Same arguments as synthesis. */
+int slicq_adjoint(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t coef_count, void* y,
+                  int64_t T, void* work, size_t work_bytes, void* hip_stream);
+
+/* Ragged batches. Signal b holds samples x_off[b] .. x_off[b+1]-1 of the
+ * packed x (x_off: nsig + 1 int64 in device memory, x_len = packed length)
+ * and its coefficients start at coef_off[b] (nsig int64, device memory) with
+ * the single-signal layout. total_slices must equal sum_b S_b; signals whose
+ * ranges fall outside the buffers are skipped. Every slice of every signal is
+ * processed by the same launches (one per kernel). Per-signal results are
+ * identical to the single-signal calls. */
+int slicq_analyze_batched(slicq_plan plan, slicq_dtype dtype, const void* x, int64_t x_len,
+                          const int64_t* x_off, int32_t nsig, int64_t total_slices, void* coef,
+                          int64_t coef_len, const int64_t* coef_off, void* work, size_t work_bytes,
+                          void* hip_stream);
+int slicq_synthesize_batched(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t coef_len,
+                             const int64_t* coef_off, void* y, int64_t y_len, const int64_t* y_off,
+                             int32_t nsig, int64_t total_slices, void* work, size_t work_bytes,
+                             void* hip_stream);
+int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t coef_len,
+                          const int64_t* coef_off, void* y, int64_t y_len, const int64_t* y_off,
+                          int32_t nsig, int64_t total_slices, void* work, size_t work_bytes,
+                          void* hip_stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* slicq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLICQ_H */

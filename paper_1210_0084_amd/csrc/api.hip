@@ -1,0 +1,366 @@
+// C ABI of the sliCQ library (include/slicq.h): plan management, table
+// upload and the enqueue-only transform calls.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/slicq.h"
+#include "pipeline.hpp"
+
+struct slicq_plan_s {
+  slicq::Plan p;
+  std::vector<unsigned char> blob[2];   // packed tables, kept alive for async uploads
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  char b[256];
+  std::snprintf(b, sizeof b, "%s: %s", what, hipGetErrorString(e));
+  return fail(SLICQ_EHIP, b);
+}
+
+struct HipLaunch {
+  hipStream_t st;
+  template <class K, class... A>
+  void launch(K kernel, int64_t grid, int block, size_t shmem, A... args) {
+    if (grid <= 0) return;
+    if (shmem > 65536) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    }
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3((unsigned)block), shmem, st, args...);
+  }
+};
+
+int check_plan(slicq_plan plan, slicq_dtype dt) {
+  if (!plan) return fail(SLICQ_EINVAL, "null plan");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "dtype must be SLICQ_F32 or SLICQ_F64");
+  if (!plan->p.dev[dt]) return fail(SLICQ_ESTATE, "plan tables not uploaded for this dtype (nsgt_plan_upload)");
+  return SLICQ_OK;
+}
+
+int64_t slices_of(const slicq::Plan& p, int64_t T) {
+  if (T <= 0) return 0;
+  return 2 * ((T + p.two_n - 1) / p.two_n);
+}
+
+int layout_or_fail(const slicq::Plan& p, int dt, int64_t ntasks, size_t bytes, slicq::WorkLayout& w) {
+  if (!slicq::work_layout(p, dt, ntasks, bytes, w)) {
+    char b[200];
+    const size_t need = slicq::tasks_bytes(ntasks) + 256 + 2 * 256 + slicq::slice_scratch_bytes(p, dt);
+    std::snprintf(b, sizeof b, "workspace of %zu bytes is below the minimum %zu for %lld slices", bytes, need,
+                  (long long)ntasks);
+    return fail(SLICQ_ESIZE, b);
+  }
+  return SLICQ_OK;
+}
+
+template <class T>
+int run_analysis(slicq::Plan& p, int dt, const slicq::SliceTask* tasks, int64_t ntasks, const void* x,
+                 void* coef, const slicq::WorkLayout& w, char* work, hipStream_t st) {
+  using namespace slicq;
+  KArgs<T> a = make_args<T>(p, dt, false);
+  a.zero_ola = 0;
+  const Geometry<T> g = geometry<T>(p);
+  HipLaunch L{st};
+  C2<T>* W1 = reinterpret_cast<C2<T>*>(work + w.w1_off);
+  C2<T>* W2 = reinterpret_cast<C2<T>*>(work + w.w2_off);
+  for (int64_t t0 = 0; t0 < ntasks; t0 += w.chunk) {
+    const int64_t cnt = std::min<int64_t>(w.chunk, ntasks - t0);
+    launch_analysis<T>(p, a, g, tasks + t0, cnt, static_cast<const T*>(x), static_cast<C2<T>*>(coef), W1, W2, L);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "analysis launch");
+}
+
+template <class T>
+int run_synthesis(slicq::Plan& p, int dt, bool adjoint, const slicq::SliceTask* tasks, int64_t ntasks,
+                  const void* coef, void* y, const slicq::WorkLayout& w, char* work, hipStream_t st) {
+  using namespace slicq;
+  KArgs<T> a = make_args<T>(p, dt, adjoint);
+  const bool chunked = w.chunk < ntasks;
+  a.zero_ola = chunked ? 0 : 1;
+  const Geometry<T> g = geometry<T>(p);
+  HipLaunch L{st};
+  if (chunked) {
+    const int64_t per = (p.Mt - 1 + 255) / 256;
+    L.launch(k_zero_overlaps<T>, ntasks * per, 256, 0, tasks, ntasks, (int32_t)p.N, (int32_t)p.Mt,
+             static_cast<T*>(y));
+  }
+  C2<T>* W1 = reinterpret_cast<C2<T>*>(work + w.w1_off);
+  C2<T>* W2 = reinterpret_cast<C2<T>*>(work + w.w2_off);
+  for (int64_t t0 = 0; t0 < ntasks; t0 += w.chunk) {
+    const int64_t cnt = std::min<int64_t>(w.chunk, ntasks - t0);
+    launch_synthesis<T>(p, a, g, tasks + t0, cnt, static_cast<const C2<T>*>(coef), static_cast<T*>(y), W1, W2, L);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, adjoint ? "adjoint launch" : "synthesis launch");
+}
+
+int plain_tasks(const slicq::Plan& p, int64_t T, int64_t S, slicq::SliceTask* tasks, hipStream_t st) {
+  HipLaunch L{st};
+  L.launch(slicq::k_tasks_plain, (S + 255) / 256, 256, 0, tasks, (int64_t)0, S, T, (int64_t)p.N, S);
+  return SLICQ_OK;
+}
+
+int synth_common(slicq_plan plan, slicq_dtype dt, bool adjoint, const void* coef, int64_t coef_count, void* y,
+                 int64_t T, void* work, size_t work_bytes, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (T < 0) return fail(SLICQ_EINVAL, "T must be >= 0");
+  const int64_t S = slices_of(p, T);
+  if (S == 0) return SLICQ_OK;
+  if (!coef || !y || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (coef_count < S * p.coefs_per_slice) return fail(SLICQ_ESIZE, "coef_count < S * coefs_per_slice");
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, S, work_bytes, w))) return rc;
+  char* wk = static_cast<char*>(work);
+  auto* tasks = reinterpret_cast<slicq::SliceTask*>(wk + w.tasks_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  plain_tasks(p, T, S, tasks, st);
+  return dt == SLICQ_F32 ? run_synthesis<float>(p, dt, adjoint, tasks, S, coef, y, w, wk, st)
+                         : run_synthesis<double>(p, dt, adjoint, tasks, S, coef, y, w, wk, st);
+}
+
+int batched_tasks(const slicq::Plan& p, const int64_t* x_off, int32_t nsig, int64_t total, int64_t x_len,
+                  const int64_t* coef_off, int64_t coef_len, slicq::SliceTask* tasks, int32_t* status,
+                  hipStream_t st) {
+  HipLaunch L{st};
+  L.launch(slicq::k_tasks_batched, 1, 1024, 1026 * sizeof(int64_t), tasks, x_off, coef_off, nsig, (int64_t)p.N, total, x_len,
+           coef_len, (int64_t)p.coefs_per_slice, status);
+  return SLICQ_OK;
+}
+
+int synth_batched_common(slicq_plan plan, slicq_dtype dt, bool adjoint, const void* coef, int64_t coef_len,
+                         const int64_t* coef_off, void* y, int64_t y_len, const int64_t* y_off, int32_t nsig,
+                         int64_t total, void* work, size_t work_bytes, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (nsig < 0 || total < 0) return fail(SLICQ_EINVAL, "nsig and total_slices must be >= 0");
+  if (nsig == 0 || total == 0) return SLICQ_OK;
+  if (!coef || !coef_off || !y || !y_off || !work) return fail(SLICQ_EINVAL, "null buffer");
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, total, work_bytes, w))) return rc;
+  char* wk = static_cast<char*>(work);
+  auto* tasks = reinterpret_cast<slicq::SliceTask*>(wk + w.tasks_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  batched_tasks(p, y_off, nsig, total, y_len, coef_off, coef_len, tasks,
+                reinterpret_cast<int32_t*>(wk + w.status_off), st);
+  return dt == SLICQ_F32 ? run_synthesis<float>(p, dt, adjoint, tasks, total, coef, y, w, wk, st)
+                         : run_synthesis<double>(p, dt, adjoint, tasks, total, coef, y, w, wk, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int nsgt_plan_ex(const slicq_plan_opts* o, slicq_plan* out) {
+  if (!o || !out) return fail(SLICQ_EINVAL, "null argument");
+  *out = nullptr;
+  slicq::PlanParams pp;
+  pp.fs = o->fs;
+  pp.fmin = o->fmin;
+  pp.fmax = o->fmax;
+  pp.bins_per_octave = o->bins_per_octave;
+  pp.slice_len = o->slice_len;
+  pp.transition = o->transition_len;
+  pp.min_win = o->min_win;
+  pp.dual_kind = o->dual_slice;
+  if (o->group_cap) pp.group_cap = o->group_cap;
+  if (o->lds_cap) pp.lds_cap = o->lds_cap;
+  if (o->pass_cap) pp.pass_cap = o->pass_cap;
+  slicq_plan h = new (std::nothrow) slicq_plan_s;
+  if (!h) return fail(SLICQ_ENOMEM, "out of host memory");
+  std::string err;
+  int rc;
+  try {
+    rc = slicq::build_plan(pp, h->p, err);
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return fail(SLICQ_ENOMEM, "out of host memory");
+  }
+  if (rc) {
+    delete h;
+    return fail(SLICQ_EINVAL, err);
+  }
+  *out = h;
+  return SLICQ_OK;
+}
+
+int nsgt_plan(double fs, double fmin, double fmax, int bins_per_octave, int64_t slice_len_2N,
+              int64_t transition_len, slicq_plan* out) {
+  slicq_plan_opts o{};
+  o.fs = fs;
+  o.fmin = fmin;
+  o.fmax = fmax;
+  o.bins_per_octave = bins_per_octave;
+  o.slice_len = slice_len_2N;
+  o.transition_len = transition_len;
+  o.min_win = 16.0;
+  o.dual_slice = 0;
+  return nsgt_plan_ex(&o, out);
+}
+
+void nsgt_plan_destroy(slicq_plan plan) { delete plan; }
+
+int nsgt_plan_info(slicq_plan plan, slicq_plan_info* info) {
+  if (!plan || !info) return fail(SLICQ_EINVAL, "null argument");
+  const slicq::Plan& p = plan->p;
+  std::memset(info, 0, sizeof *info);
+  info->K = p.K;
+  info->nbands = p.nb;
+  info->slice_len = p.two_n;
+  info->transition_len = p.Mt;
+  info->coefs_per_slice = p.coefs_per_slice;
+  info->Q = p.Q;
+  info->max_M = p.max_M;
+  info->n_ana_items = (int32_t)p.ana.size();
+  info->n_syn_items = (int32_t)p.syn.size();
+  return SLICQ_OK;
+}
+
+int nsgt_plan_bands(slicq_plan plan, int32_t* M, int64_t* off, int64_t* start, int32_t* len, double* fc_hz,
+                    double* bw_hz) {
+  if (!plan) return fail(SLICQ_EINVAL, "null plan");
+  const auto& b = plan->p.bands;
+  for (size_t k = 0; k < b.size(); ++k) {
+    if (M) M[k] = b[k].M;
+    if (off) off[k] = b[k].off;
+    if (start) start[k] = b[k].start;
+    if (len) len[k] = b[k].len;
+    if (fc_hz) fc_hz[k] = b[k].xi;
+    if (bw_hz) bw_hz[k] = b[k].omega;
+  }
+  return SLICQ_OK;
+}
+
+int nsgt_plan_windows(slicq_plan plan, double* g, double* gd, double* h0, double* hd, double* D) {
+  if (!plan) return fail(SLICQ_EINVAL, "null plan");
+  const slicq::Plan& p = plan->p;
+  if (g) std::memcpy(g, p.g.data(), p.g.size() * sizeof(double));
+  if (gd) std::memcpy(gd, p.gd.data(), p.gd.size() * sizeof(double));
+  if (h0) std::memcpy(h0, p.h0.data(), p.h0.size() * sizeof(double));
+  if (hd) std::memcpy(hd, p.hd.data(), p.hd.size() * sizeof(double));
+  if (D) std::memcpy(D, p.D.data(), p.D.size() * sizeof(double));
+  return SLICQ_OK;
+}
+
+int nsgt_plan_table_bytes(slicq_plan plan, slicq_dtype dt, size_t* bytes) {
+  if (!plan || !bytes) return fail(SLICQ_EINVAL, "null argument");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "bad dtype");
+  std::lock_guard<std::mutex> lk(plan->p.mu);
+  if (plan->blob[dt].empty()) slicq::pack_tables(plan->p, dt, plan->blob[dt], plan->p.layout[dt]);
+  *bytes = plan->blob[dt].size();
+  return SLICQ_OK;
+}
+
+int nsgt_plan_upload(slicq_plan plan, slicq_dtype dt, void* dev, size_t bytes, void* stream) {
+  size_t need = 0;
+  int rc = nsgt_plan_table_bytes(plan, dt, &need);
+  if (rc) return rc;
+  if (!dev) return fail(SLICQ_EINVAL, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(SLICQ_EINVAL, "device tables must be 256-byte aligned");
+  if (bytes < need) return fail(SLICQ_ESIZE, "device table buffer too small");
+  std::lock_guard<std::mutex> lk(plan->p.mu);
+  hipError_t e = hipMemcpyAsync(dev, plan->blob[dt].data(), need, hipMemcpyHostToDevice,
+                                static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  plan->p.dev[dt] = dev;
+  plan->p.dev_bytes[dt] = bytes;
+  return SLICQ_OK;
+}
+
+int64_t slicq_num_slices(slicq_plan plan, int64_t T) {
+  if (!plan) return fail(SLICQ_EINVAL, "null plan");
+  return slices_of(plan->p, T);
+}
+
+int slicq_workspace_size(slicq_plan plan, slicq_dtype dt, int64_t n_slices, size_t* bytes) {
+  if (!plan || !bytes) return fail(SLICQ_EINVAL, "null argument");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "bad dtype");
+  if (n_slices < 0) return fail(SLICQ_EINVAL, "n_slices must be >= 0");
+  *bytes = slicq::workspace_bytes(plan->p, dt, n_slices);
+  return SLICQ_OK;
+}
+
+int slicq_analyze(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, void* coef, int64_t coef_count,
+                  void* work, size_t work_bytes, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (T < 0) return fail(SLICQ_EINVAL, "T must be >= 0");
+  const int64_t S = slices_of(p, T);
+  if (S == 0) return SLICQ_OK;
+  if (!x || !coef || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (coef_count < S * p.coefs_per_slice) return fail(SLICQ_ESIZE, "coef_count < S * coefs_per_slice");
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, S, work_bytes, w))) return rc;
+  char* wk = static_cast<char*>(work);
+  auto* tasks = reinterpret_cast<slicq::SliceTask*>(wk + w.tasks_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  plain_tasks(p, T, S, tasks, st);
+  return dt == SLICQ_F32 ? run_analysis<float>(p, dt, tasks, S, x, coef, w, wk, st)
+                         : run_analysis<double>(p, dt, tasks, S, x, coef, w, wk, st);
+}
+
+int slicq_synthesize(slicq_plan plan, slicq_dtype dt, const void* coef, int64_t coef_count, void* y, int64_t T,
+                     void* work, size_t work_bytes, void* stream) {
+  return synth_common(plan, dt, false, coef, coef_count, y, T, work, work_bytes, stream);
+}
+
+int slicq_adjoint(slicq_plan plan, slicq_dtype dt, const void* coef, int64_t coef_count, void* y, int64_t T,
+                  void* work, size_t work_bytes, void* stream) {
+  return synth_common(plan, dt, true, coef, coef_count, y, T, work, work_bytes, stream);
+}
+
+int slicq_analyze_batched(slicq_plan plan, slicq_dtype dt, const void* x, int64_t x_len, const int64_t* x_off,
+                          int32_t nsig, int64_t total, void* coef, int64_t coef_len, const int64_t* coef_off,
+                          void* work, size_t work_bytes, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (nsig < 0 || total < 0) return fail(SLICQ_EINVAL, "nsig and total_slices must be >= 0");
+  if (nsig == 0 || total == 0) return SLICQ_OK;
+  if (!x || !x_off || !coef || !coef_off || !work) return fail(SLICQ_EINVAL, "null buffer");
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, total, work_bytes, w))) return rc;
+  char* wk = static_cast<char*>(work);
+  auto* tasks = reinterpret_cast<slicq::SliceTask*>(wk + w.tasks_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  batched_tasks(p, x_off, nsig, total, x_len, coef_off, coef_len, tasks,
+                reinterpret_cast<int32_t*>(wk + w.status_off), st);
+  return dt == SLICQ_F32 ? run_analysis<float>(p, dt, tasks, total, x, coef, w, wk, st)
+                         : run_analysis<double>(p, dt, tasks, total, x, coef, w, wk, st);
+}
+
+int slicq_synthesize_batched(slicq_plan plan, slicq_dtype dt, const void* coef, int64_t coef_len,
+                             const int64_t* coef_off, void* y, int64_t y_len, const int64_t* y_off, int32_t nsig,
+                             int64_t total, void* work, size_t work_bytes, void* stream) {
+  return synth_batched_common(plan, dt, false, coef, coef_len, coef_off, y, y_len, y_off, nsig, total, work,
+                              work_bytes, stream);
+}
+
+int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dt, const void* coef, int64_t coef_len,
+                          const int64_t* coef_off, void* y, int64_t y_len, const int64_t* y_off, int32_t nsig,
+                          int64_t total, void* work, size_t work_bytes, void* stream) {
+  return synth_batched_common(plan, dt, true, coef, coef_len, coef_off, y, y_len, y_off, nsig, total, work,
+                              work_bytes, stream);
+}
+
+const char* slicq_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

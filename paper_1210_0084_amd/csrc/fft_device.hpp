@@ -1,0 +1,192 @@
+// Device building blocks for the sliCQ kernels on gfx950: complex values,
+// radix-2/4/8/16 DFTs in registers, and batched power-of-two FFTs in LDS
+// (Stockham autosort, in place, every thread holding at most E values).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace slicq {
+
+template <class T>
+struct alignas(2 * sizeof(T)) C2 {
+  T x, y;
+};
+
+template <class T>
+__device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T>
+__device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class T>
+__device__ __forceinline__ C2<T> cconj(C2<T> a) { return {a.x, -a.y}; }
+template <class T>
+__device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <class T, int DIR>
+__device__ __forceinline__ C2<T> mul_mi(C2<T> a) {
+  if constexpr (DIR < 0) return {a.y, -a.x};
+  else return {-a.y, a.x};
+}
+
+// LDS index with one pad slot every 16 complex values (bank spreading for the
+// strided Stockham stores).
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 4) + 1; }
+
+// e^{DIR 2 pi i k / R} for small constant R, as constants.
+template <class T, int R, int DIR>
+__device__ __forceinline__ C2<T> wconst(int k) {
+  // cos(2 pi k / 16) for k = 0..4
+  constexpr double c16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                             0.38268343236508977173, 0.0};
+  int q = k * (16 / R);            // angle in sixteenths of a turn, q in [0, 16)
+  // cos and sin of 2 pi q / 16
+  int qc = q & 15;
+  double c, s;
+  int m = qc & 3, quad = qc >> 2;
+  double cc = c16[m], ss = c16[4 - m];
+  switch (quad) {
+    case 0: c = cc; s = ss; break;
+    case 1: c = -ss; s = cc; break;
+    case 2: c = -cc; s = -ss; break;
+    default: c = ss; s = -cc; break;
+  }
+  return {(T)c, (T)(DIR < 0 ? -s : s)};
+}
+
+// In-register DFT of size R (power of two <= 16), natural order in and out.
+// DIR < 0: e^{-2 pi i jk/R} (forward), DIR > 0: e^{+} (inverse), unnormalised.
+template <class T, int R, int DIR>
+__device__ __forceinline__ void dft_reg(C2<T>* v) {
+  // radix-2 decimation in frequency, output in bit-reversed order
+#pragma unroll
+  for (int span = R / 2; span >= 1; span >>= 1) {
+#pragma unroll
+    for (int b = 0; b < R; b += 2 * span) {
+#pragma unroll
+      for (int q = 0; q < span; ++q) {
+        C2<T> a = v[b + q], c = v[b + q + span];
+        v[b + q] = cadd(a, c);
+        C2<T> d = csub(a, c);
+        // twiddle e^{DIR 2 pi i q / (2 span)} = w_R^{q R / (2 span)}
+        const int e = q * (R / (2 * span));
+        if (e == 0) {
+          v[b + q + span] = d;
+        } else if (4 * e == R) {
+          v[b + q + span] = mul_mi<T, DIR>(d);    // e^{DIR i pi/2}: -i forward, +i inverse
+        } else {
+          v[b + q + span] = cmul(d, wconst<T, R, DIR>(e));
+        }
+      }
+    }
+  }
+  // undo the bit reversal (register renaming once unrolled)
+  C2<T> t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[i] = v[i];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int bit = 1, rb = R / 2; bit < R; bit <<= 1, rb >>= 1)
+      if (i & bit) r |= rb;
+    v[r] = t[i];
+  }
+}
+
+// Twiddle e^{DIR 2 pi i k / n} from the pyramid (entry n + k holds e^{-2 pi i k / n}).
+template <class T, int DIR>
+__device__ __forceinline__ C2<T> twiddle(const C2<T>* __restrict__ tw, int n, int k) {
+  C2<T> w = tw[n + k];
+  if constexpr (DIR > 0) w.y = -w.y;
+  return w;
+}
+
+// Batch layouts of `nseq` sequences of length n in LDS (padded indices):
+// CONTIG puts element i of sequence s at s*n + i, INTERLEAVED at i*nseq + s.
+enum Layout { CONTIG = 0, INTERLEAVED = 1 };
+
+// One in-place Stockham pass of radix R. Ns is the product of the radices of
+// earlier passes. Every thread reads all of its units into registers, the
+// block synchronises, then every thread writes back.
+template <class T, int DIR, int R, int LAY, int E>
+__device__ __forceinline__ void stockham_pass(C2<T>* buf, int base, int logn, int Ns, int logNs,
+                                              int nseq, int lognseq, const C2<T>* __restrict__ tw,
+                                              int tid, int nthr) {
+  constexpr int U = E / R;
+  constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  C2<T> v[U][R];
+  const int lunits = logn - LR;            // log2 of units per sequence
+  const int total = (LAY == CONTIG) ? (nseq << lunits) : (1 << (lognseq + lunits));
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = tid + i * nthr;
+    if (u < total) {
+      int s, j;
+      if constexpr (LAY == CONTIG) { s = u >> lunits; j = u & ((1 << lunits) - 1); }
+      else { s = u & ((1 << lognseq) - 1); j = u >> lognseq; }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = j + (r << lunits);
+        const int pos = (LAY == CONTIG) ? (s << logn) + e : (e << lognseq) + s;
+        v[i][r] = buf[pidx(base + pos)];
+      }
+      if (Ns > 1) {
+        const int k = j & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twiddle<T, DIR>(tw, Ns * R, r * k));
+      }
+      dft_reg<T, R, DIR>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = tid + i * nthr;
+    if (u < total) {
+      int s, j;
+      if constexpr (LAY == CONTIG) { s = u >> lunits; j = u & ((1 << lunits) - 1); }
+      else { s = u & ((1 << lognseq) - 1); j = u >> lognseq; }
+      const int idxD = ((j >> logNs) << (logNs + LR)) + (j & (Ns - 1));
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = idxD + r * Ns;
+        const int pos = (LAY == CONTIG) ? (s << logn) + e : (e << lognseq) + s;
+        buf[pidx(base + pos)] = v[i][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Batched FFT of `nseq` sequences of length 2^logn held in LDS at padded
+// positions pidx(base + pos); INTERLEAVED needs nseq = 2^lognseq. Needs
+// nseq * n <= E * nthr. Unnormalised, DIR < 0 forward (e^-), DIR > 0
+// inverse (e^+). The caller synchronises the data in; the routine ends with a
+// barrier.
+template <class T, int DIR, int LAY, int E = 16>
+__device__ void lds_fft(C2<T>* buf, int base, int logn, int nseq, int lognseq,
+                        const C2<T>* __restrict__ tw, int tid, int nthr) {
+  int Ns = 1, logNs = 0, rem = logn;
+  while (rem > 0) {
+    if (rem >= 4) {
+      stockham_pass<T, DIR, 16, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+      Ns <<= 4; logNs += 4; rem -= 4;
+    } else if (rem == 3) {
+      stockham_pass<T, DIR, 8, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+      Ns <<= 3; logNs += 3; rem -= 3;
+    } else if (rem == 2) {
+      stockham_pass<T, DIR, 4, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+      Ns <<= 2; logNs += 2; rem -= 2;
+    } else {
+      stockham_pass<T, DIR, 2, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+      Ns <<= 1; logNs += 1; rem -= 1;
+    }
+  }
+}
+
+}  // namespace slicq

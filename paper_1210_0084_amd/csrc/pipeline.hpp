@@ -1,0 +1,151 @@
+// Host orchestration of the sliCQ kernels: argument packing, workspace
+// layout, launch geometry and the per-call launch sequences. Templated on the
+// launcher so the same sequence drives the device (hipLaunchKernelGGL).
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace slicq {
+
+inline int threads_for(int64_t values, int E = 16) {
+  int64_t t = (values + E - 1) / E;
+  t = (t + 63) / 64 * 64;
+  return (int)std::min<int64_t>(1024, std::max<int64_t>(64, t));
+}
+
+inline int ilog2i(int64_t n) {
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l;
+}
+
+inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Workspace: [slice tasks][status words][W1: chunk x N][W2: chunk x (N + 64)]
+struct WorkLayout {
+  size_t tasks_off = 0, status_off = 0, w1_off = 0, w2_off = 0, total = 0;
+  int64_t chunk = 0;
+};
+
+inline int64_t ws1_len(const Plan& p) { return p.N; }
+inline int64_t ws2_len(const Plan& p) { return p.N + 64; }
+
+inline size_t slice_scratch_bytes(const Plan& p, int dtype) {
+  const size_t cb = dtype ? 16 : 8;
+  return (size_t)(ws1_len(p) + ws2_len(p)) * cb;
+}
+
+inline size_t tasks_bytes(int64_t ntasks) { return align256((size_t)std::max<int64_t>(ntasks, 1) * sizeof(SliceTask)); }
+
+inline size_t workspace_bytes(const Plan& p, int dtype, int64_t ntasks) {
+  return tasks_bytes(ntasks) + 256 + 2 * 256 + (size_t)std::max<int64_t>(ntasks, 1) * slice_scratch_bytes(p, dtype);
+}
+
+// Lays out `bytes` of workspace for ntasks slices; chunk = slices per pass.
+inline bool work_layout(const Plan& p, int dtype, int64_t ntasks, size_t bytes, WorkLayout& w) {
+  const size_t cb = dtype ? 16 : 8;
+  w.tasks_off = 0;
+  w.status_off = tasks_bytes(ntasks);
+  const size_t fixed = w.status_off + 256;
+  const size_t per = slice_scratch_bytes(p, dtype);
+  if (bytes < fixed + 2 * 256 + per) return false;
+  int64_t chunk = (int64_t)((bytes - fixed - 2 * 256) / per);
+  chunk = std::min<int64_t>(chunk, std::max<int64_t>(ntasks, 1));
+  w.chunk = chunk;
+  w.w1_off = fixed;
+  w.w2_off = align256(w.w1_off + (size_t)chunk * ws1_len(p) * cb);
+  w.total = align256(w.w2_off + (size_t)chunk * ws2_len(p) * cb);
+  return w.total <= bytes;
+}
+
+template <class T>
+KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
+  const TableLayout& L = p.layout[dtype];
+  const char* base = static_cast<const char*>(p.dev[dtype]);
+  KArgs<T> a{};
+  a.tw = reinterpret_cast<const C2<T>*>(base + L.tw);
+  a.h0 = reinterpret_cast<const T*>(base + L.h0);
+  a.hsyn = reinterpret_cast<const T*>(base + (adjoint ? L.h0 : L.hd));
+  a.g = reinterpret_cast<const T*>(base + L.g);
+  a.gsyn = reinterpret_cast<const T*>(base + (adjoint ? L.g : L.gd));
+  a.bands = reinterpret_cast<const BandDev*>(base + L.bands);
+  a.ana = reinterpret_cast<const AnaGroupDev*>(base + L.ana);
+  a.syn = reinterpret_cast<const SynGroupDev*>(base + L.syn);
+  a.runs = reinterpret_cast<const SynRunDev*>(base + L.runs);
+  a.bin_k0 = reinterpret_cast<const int32_t*>(base + L.bin_k0);
+  a.bin_nk = reinterpret_cast<const int32_t*>(base + L.bin_nk);
+  a.N = (int32_t)p.N;
+  a.Mt = (int32_t)p.Mt;
+  a.K = p.K;
+  a.n_ana = (int32_t)p.ana.size();
+  a.n_syn = (int32_t)p.syn.size();
+  a.N1 = p.N1;
+  a.N2 = p.N2;
+  a.logN1 = p.logN1;
+  a.logN2 = p.logN2;
+  a.C = p.C;
+  a.logC = ilog2i(p.C);
+  a.P = p.P;
+  a.logP = ilog2i(p.P);
+  a.ws1 = ws1_len(p);
+  a.ws2 = ws2_len(p);
+  a.scale = (T)(1.0 / std::sqrt((double)p.two_n));
+  a.inner_w = adjoint ? T(0.5) : T(1.0);
+  return a;
+}
+
+template <class T>
+struct Geometry {
+  int g1, b1; size_t s1;      // forward pass 1 / inverse pass B: items per slice, threads, LDS bytes
+  int g2, b2; size_t s2;      // forward pass 2 / inverse pass A
+  int ga, ba; size_t sa;      // band analysis
+  int gs, bs, Es; size_t ss;  // band synthesis (Es values per thread)
+};
+
+template <class T>
+Geometry<T> geometry(const Plan& p) {
+  Geometry<T> g{};
+  const size_t cb = sizeof(C2<T>);
+  g.g1 = p.N1 / p.C;
+  g.b1 = threads_for((int64_t)p.C * p.N2);
+  g.s1 = padded(p.C * p.N2) * cb;
+  g.g2 = (p.N2 / 2) / p.P;
+  g.b2 = threads_for((int64_t)2 * p.P * p.N1);
+  g.s2 = padded(2 * p.P * p.N1) * cb;
+  g.ga = (int)p.ana.size();
+  g.ba = threads_for(p.ana_cap);
+  g.sa = padded(p.ana_cap) * cb;
+  g.gs = (int)p.syn.size();
+  g.Es = p.syn_cap > 16 * 512 ? 32 : 16;
+  g.bs = threads_for(p.syn_cap, g.Es);
+  g.ss = padded(p.syn_cap) * cb;
+  return g;
+}
+
+// Analysis of tasks [t0, t0 + cnt) (Algorithm 3): slice FFT, band transforms.
+template <class T, class Launch>
+void launch_analysis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks,
+                     int64_t cnt, const T* x, C2<T>* coef, C2<T>* W1, C2<T>* W2, Launch& L) {
+  L.launch(k_fwd_pass1<T>, cnt * g.g1, g.b1, g.s1, a, tasks, x, W1);
+  L.launch(k_fwd_pass2<T>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2);
+  L.launch(k_band_ana<T>, cnt * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, coef);
+  (void)p;
+}
+
+// Synthesis (or adjoint) of tasks [t0, t0 + cnt) (Algorithm 4).
+template <class T, class Launch>
+void launch_synthesis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks,
+                      int64_t cnt, const C2<T>* coef, T* y, C2<T>* W1, C2<T>* W2, Launch& L) {
+  if (g.Es == 16) L.launch(k_band_syn<T, 16>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y);
+  else L.launch(k_band_syn<T, 32>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y);
+  L.launch(k_inv_passA<T>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1);
+  L.launch(k_inv_passB<T>, cnt * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, y);
+  (void)p;
+}
+
+}  // namespace slicq

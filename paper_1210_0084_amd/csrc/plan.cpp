@@ -1,0 +1,452 @@
+// FP64 plan: constant-Q band design (Section 3, Table 1), lattice M_k = L/a_k
+// (equation framecond1), diagonal frame operator and canonical dual windows
+// (Proposition 2), Tukey slicing window and its dual (Section 4.3, equations
+// BUPU and dualwincond), and the kernel work schedule.
+//
+// Readings where the paper is silent: Hann H; bandwidths widened to a
+// minimal filter length (Section 5.3); K reduced until xi_K + Omega_K/2 stays
+// below Nyquist; plateau DC/Nyquist bands with raised-cosine flanks of width
+// Omega_1/2 and Omega_K/2 measured in whole bins from 0 and N; M_k the
+// smallest power of two >= |J_k| (and >= 2); canonical slice dual
+// h_0 / sum_m T_{mN} h_0^2.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+
+namespace slicq {
+
+namespace {
+
+int64_t next_pow2(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+int ilog2(int64_t n) {
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l;
+}
+
+// Integer interval on which pred holds, located from guesses and settled by
+// pred itself (pred must hold on an interval). Returns false if empty.
+bool find_interval(const std::function<bool(int64_t)>& pred, int64_t glo, int64_t ghi,
+                   int64_t& a, int64_t& b) {
+  const int64_t margin = 3;
+  bool found = false;
+  for (int64_t j = glo - margin; j <= ghi + margin; ++j) {
+    if (pred(j)) {
+      if (!found) a = j;
+      b = j;
+      found = true;
+    }
+  }
+  if (!found) return false;
+  while (pred(a - 1)) --a;
+  while (pred(b + 1)) ++b;
+  return true;
+}
+
+struct RawBand {
+  int64_t start = 0;
+  std::vector<double> g;
+  int64_t M = 0;
+  double xi = 0, omega = 0;
+};
+
+RawBand hann_band(double fs, int64_t two_n, double xi, double om) {
+  auto x_of = [&](int64_t j) { return ((double)j * fs / (double)two_n - xi) / om; };
+  auto inside = [&](int64_t j) {
+    double x = x_of(j);
+    return -0.5 < x && x < 0.5;
+  };
+  RawBand r;
+  r.xi = xi;
+  r.omega = om;
+  int64_t glo = (int64_t)std::floor((xi - om / 2) * (double)two_n / fs);
+  int64_t ghi = (int64_t)std::ceil((xi + om / 2) * (double)two_n / fs);
+  int64_t a = 0, b = -1;
+  if (!find_interval(inside, glo, ghi, a, b)) {
+    r.M = 2;
+    return r;
+  }
+  r.start = a;
+  for (int64_t j = a; j <= b; ++j) r.g.push_back(0.5 + 0.5 * std::cos(2.0 * M_PI * x_of(j)));
+  r.M = std::max<int64_t>(2, next_pow2(b - a + 1));
+  return r;
+}
+
+// Plateau P(d; R, w) in the distance d (Hz) from centre_bin.
+RawBand plateau_band(double fs, int64_t two_n, int64_t centre_bin, double R, double w,
+                     double xi, double om) {
+  RawBand r;
+  r.xi = xi;
+  r.omega = om;
+  int64_t e = 0;
+  while ((double)(e + 1) * fs / (double)two_n < R) ++e;
+  r.start = centre_bin - e;
+  for (int64_t j = centre_bin - e; j <= centre_bin + e; ++j) {
+    int64_t dj = j - centre_bin;
+    if (dj < 0) dj = -dj;
+    double d = (double)dj * fs / (double)two_n;
+    r.g.push_back(d <= R - w ? 1.0 : 0.5 + 0.5 * std::cos(M_PI * (d - R + w) / w));
+  }
+  r.M = std::max<int64_t>(2, next_pow2(2 * e + 1));
+  return r;
+}
+
+template <class T>
+size_t append(std::vector<unsigned char>& blob, const T* data, size_t n) {
+  size_t off = (blob.size() + 255) & ~size_t(255);
+  blob.resize(off + n * sizeof(T));
+  if (n) std::memcpy(blob.data() + off, data, n * sizeof(T));
+  return off;
+}
+
+}  // namespace
+
+int build_plan(const PlanParams& p, Plan& out, std::string& err) {
+  const double fs = p.fs, fmin = p.fmin, fmax = p.fmax;
+  const int B = p.bins_per_octave;
+  const int64_t two_n = p.slice_len, Mt = p.transition;
+  char msg[256];
+  if (!(fs > 0 && fmin > 0 && fmin < fmax && fmin < fs / 2 && B >= 1)) {
+    err = "need fs > 0, 0 < fmin < fmax, fmin < fs/2 and bins_per_octave >= 1";
+    return -1;
+  }
+  if (two_n < 16 || two_n > (int64_t(1) << 20) || (two_n & (two_n - 1))) {
+    err = "slice length 2N must be a power of two in [16, 2^20]";
+    return -1;
+  }
+  const int64_t N = two_n / 2;
+  if (!(Mt > 0 && Mt < N) || ((N - Mt) & 1)) {
+    err = "transition length M needs 0 < M < N and N - M even";
+    return -1;
+  }
+  if (!(p.min_win >= 0) || p.dual_kind < 0 || p.dual_kind > 1) {
+    err = "min_win must be >= 0 and dual_kind 0 or 1";
+    return -1;
+  }
+  if (p.group_cap < 16 || p.group_cap > 4096 || p.lds_cap < p.group_cap || p.lds_cap > 16384 ||
+      p.pass_cap < 64 || p.pass_cap > 4096 ||
+      (p.group_cap & (p.group_cap - 1)) || (p.pass_cap & (p.pass_cap - 1))) {
+    err = "group_cap and pass_cap must be powers of two in [16, 4096] and [64, 4096], "
+          "lds_cap in [group_cap, 16384]";
+    return -1;
+  }
+  out.prm = p;
+  out.two_n = two_n;
+  out.N = N;
+  out.Mt = Mt;
+  const double Q = 1.0 / (std::pow(2.0, 1.0 / B) - std::pow(2.0, -1.0 / B));
+  out.Q = Q;
+
+  // centres and bandwidths (Table 1)
+  const int K0 = 1 + (int)std::ceil((double)B * std::log2(fmax / fmin) - 1e-12);
+  const double bw_min = p.min_win * fs / (double)two_n;
+  std::vector<double> xi(K0), om(K0);
+  for (int k = 1; k <= K0; ++k) {
+    xi[k - 1] = fmin * std::pow(2.0, (double)(k - 1) / (double)B);
+    om[k - 1] = std::max(xi[k - 1] / Q, bw_min);
+  }
+  int K = K0;
+  while (K >= 1 && !(xi[K - 1] + om[K - 1] / 2 < fs / 2)) --K;
+  if (K < 1) {
+    err = "no constant-Q band fits below Nyquist";
+    return -1;
+  }
+  out.K0 = K0;
+  out.K = K;
+  out.nb = K + 2;
+
+  std::vector<RawBand> raw;
+  {
+    const double R0 = xi[0];
+    const double w0 = std::min(om[0] / 2, R0);
+    raw.push_back(plateau_band(fs, two_n, 0, R0, w0, 0.0, 2.0 * xi[0]));
+    for (int k = 1; k <= K; ++k) raw.push_back(hann_band(fs, two_n, xi[k - 1], om[k - 1]));
+    const double RN = fs / 2 - xi[K - 1];
+    const double wN = std::min(om[K - 1] / 2, RN);
+    raw.push_back(plateau_band(fs, two_n, N, RN, wN, fs / 2, fs - 2 * xi[K - 1]));
+  }
+  for (int k = 0; k < K + 2; ++k) {
+    if (raw[k].g.empty()) {
+      std::snprintf(msg, sizeof msg, "band %d has empty support; raise min_win", k);
+      err = msg;
+      return -1;
+    }
+  }
+  for (int k = 1; k <= K; ++k) {
+    const RawBand& r = raw[k];
+    if (r.start < 1 || r.start + (int64_t)r.g.size() - 1 > N - 1) {
+      err = "a constant-Q band reaches bin 0 or bin N; raise fmin or lower min_win";
+      return -1;
+    }
+  }
+
+  // frame-operator diagonal over all 2K+2 bands (mirrors g_{2K+2-k}[j] = g_k[2N-j])
+  out.D.assign(two_n, 0.0);
+  auto add_band = [&](int64_t start, const std::vector<double>& g, int64_t M, bool mirror) {
+    const int64_t len = (int64_t)g.size();
+    for (int64_t t = 0; t < len; ++t) {
+      int64_t j, src;
+      if (!mirror) {
+        j = start + t;
+        src = t;
+      } else {
+        j = -(start + len - 1) + t;
+        src = len - 1 - t;
+      }
+      j %= two_n;
+      if (j < 0) j += two_n;
+      out.D[j] += (double)M * g[src] * g[src];
+    }
+  };
+  for (int k = 0; k < K + 2; ++k) add_band(raw[k].start, raw[k].g, raw[k].M, false);
+  for (int k = K + 2; k < 2 * K + 2; ++k) {
+    const RawBand& s = raw[2 * K + 2 - k];
+    add_band(s.start, s.g, s.M, true);
+  }
+  for (int64_t j = 0; j < two_n; ++j) {
+    if (!(out.D[j] > 0)) {
+      err = "frame condition fails: the frame-operator diagonal has a zero (Proposition 2)";
+      return -1;
+    }
+  }
+
+  // stored bands, windows and duals
+  out.bands.clear();
+  out.g.clear();
+  out.gd.clear();
+  int64_t off = 0, goff = 0;
+  out.max_M = 0;
+  for (int k = 0; k < K + 2; ++k) {
+    const RawBand& r = raw[k];
+    BandInfo b;
+    b.k = k;
+    b.start = r.start;
+    b.len = (int32_t)r.g.size();
+    b.M = (int32_t)r.M;
+    b.logM = ilog2(r.M);
+    b.off = off;
+    b.goff = goff;
+    b.xi = r.xi;
+    b.omega = r.omega;
+    b.hlo = (int32_t)std::max<int64_t>(0, r.start);
+    b.hhi = (int32_t)std::min<int64_t>(N, r.start + b.len - 1);
+    off += r.M;
+    goff += b.len;
+    out.max_M = std::max(out.max_M, b.M);
+    for (int64_t t = 0; t < b.len; ++t) {
+      int64_t j = (r.start + t) % two_n;
+      if (j < 0) j += two_n;
+      out.g.push_back(r.g[t]);
+      out.gd.push_back(r.g[t] / out.D[j]);
+    }
+    out.bands.push_back(b);
+  }
+  out.coefs_per_slice = off;
+  if (out.max_M > p.lds_cap - 2 * 256 || out.max_M > 8192) {
+    std::snprintf(msg, sizeof msg, "a band needs M_k = %d coefficients per slice; "
+                  "the single-workgroup band transforms support up to %d", out.max_M,
+                  std::min(8192, p.lds_cap - 512));
+    err = msg;
+    return -1;
+  }
+
+  // half-spectrum coverage must be monotone in k for the per-bin gather
+  for (int k = 1; k < K + 2; ++k) {
+    if (out.bands[k].hlo < out.bands[k - 1].hlo || out.bands[k].hhi < out.bands[k - 1].hhi) {
+      err = "band supports are not ordered by frequency";
+      return -1;
+    }
+  }
+  out.bin_k0.assign(N + 1, 0);
+  out.bin_nk.assign(N + 1, 0);
+  {
+    int kfirst = 0;
+    for (int64_t j = 0; j <= N; ++j) {
+      while (kfirst < K + 2 && out.bands[kfirst].hhi < j) ++kfirst;
+      int k = kfirst, n = 0;
+      while (k + n < K + 2 && out.bands[k + n].hlo <= j) ++n;
+      out.bin_k0[j] = k;
+      out.bin_nk[j] = n;
+      if (n == 0) {
+        err = "a bin of [0, N] is covered by no band";
+        return -1;
+      }
+    }
+  }
+
+  // Tukey slicing window on t in [-N, N), index j = t + N
+  out.h0.assign(two_n, 0.0);
+  out.hd.assign(two_n, 0.0);
+  const int64_t flat = (N - Mt) / 2;
+  for (int64_t j = 0; j < two_n; ++j) {
+    int64_t a = j - N;
+    if (a < 0) a = -a;
+    double h = 0.0;
+    if (a <= flat) h = 1.0;
+    else if ((double)a < (double)(N + Mt) / 2) h = 0.5 + 0.5 * std::cos(M_PI * (double)(a - flat) / (double)Mt);
+    out.h0[j] = h;
+  }
+  for (int64_t j = 0; j < two_n; ++j) {
+    const double h = out.h0[j];
+    if (h == 0.0) continue;
+    if (p.dual_kind == 1) {
+      out.hd[j] = 1.0;
+    } else {
+      double den = h * h;
+      if (j >= N) den += out.h0[j - N] * out.h0[j - N];
+      else den += out.h0[j + N] * out.h0[j + N];
+      out.hd[j] = h / den;
+    }
+  }
+
+  // four-step factorisation of the N-point complex FFT of a slice
+  out.logN1 = ilog2(N) / 2;
+  out.logN2 = ilog2(N) - out.logN1;
+  out.N1 = 1 << out.logN1;
+  out.N2 = 1 << out.logN2;
+  out.C = (int32_t)std::min<int64_t>(out.N1, std::max<int64_t>(1, p.pass_cap / out.N2));
+  out.P = (int32_t)std::min<int64_t>(out.N2 / 2, std::max<int64_t>(1, p.pass_cap / (2 * out.N1)));
+
+  // analysis work items: consecutive bands of equal M_k, at most group_cap values
+  out.ana.clear();
+  out.ana_cap = 0;
+  for (int k = 0; k < K + 2;) {
+    AnaGroupDev gdv{};
+    gdv.k0 = k;
+    gdv.M = out.bands[k].M;
+    gdv.logM = out.bands[k].logM;
+    int cnt = 1;
+    while (k + cnt < K + 2 && out.bands[k + cnt].M == gdv.M && (cnt + 1) * gdv.M <= p.group_cap) ++cnt;
+    gdv.cnt = cnt;
+    out.ana.push_back(gdv);
+    out.ana_cap = std::max(out.ana_cap, cnt * gdv.M);
+    k += cnt;
+  }
+
+  // synthesis work items: own bands ka..kb (equal M_k), owned bins [lo, hi),
+  // plus the earlier bands ke..ka-1 that reach into [lo, hi)
+  out.syn.clear();
+  out.runs.clear();
+  out.syn_cap = 0;
+  {
+    std::vector<std::pair<int, int>> own;   // (ka, kb)
+    for (int k = 0; k < K + 2;) {
+      const int lo = (k == 0) ? 0 : out.bands[k].hlo;
+      int ke = k;
+      while (ke > 0 && out.bands[ke - 1].hhi >= lo) --ke;
+      int64_t extra = out.bands[k].off - out.bands[ke].off;
+      int cnt = 1;
+      const int M = out.bands[k].M;
+      while (k + cnt < K + 2 && out.bands[k + cnt].M == M && (cnt + 1) * M <= p.group_cap &&
+             extra + (int64_t)(cnt + 1) * M <= p.lds_cap)
+        ++cnt;
+      if (extra + (int64_t)cnt * M > p.lds_cap) {
+        std::snprintf(msg, sizeof msg, "bins near band %d need more than %d coefficients in one "
+                      "synthesis work item; raise lds_cap", k, p.lds_cap);
+        err = msg;
+        return -1;
+      }
+      own.push_back({k, k + cnt - 1});
+      k += cnt;
+    }
+    for (size_t i = 0; i < own.size(); ++i) {
+      const int ka = own[i].first, kb = own[i].second;
+      SynGroupDev s{};
+      s.lo = (i == 0) ? 0 : out.bands[ka].hlo;
+      s.hi = (i + 1 < own.size()) ? out.bands[own[i + 1].first].hlo : (int32_t)(N + 1);
+      int ke = ka;
+      while (ke > 0 && out.bands[ke - 1].hhi >= s.lo) --ke;
+      s.ke = ke;
+      s.kb = kb;
+      s.run0 = (int32_t)out.runs.size();
+      for (int k = ke; k <= kb;) {
+        SynRunDev r{};
+        r.k0 = k;
+        r.M = out.bands[k].M;
+        r.logM = out.bands[k].logM;
+        r.lds_off = (int32_t)(out.bands[k].off - out.bands[ke].off);
+        int c = 1;
+        while (k + c <= kb && out.bands[k + c].M == r.M) ++c;
+        r.cnt = c;
+        out.runs.push_back(r);
+        k += c;
+      }
+      s.nrun = (int32_t)out.runs.size() - s.run0;
+      s.total = (int32_t)(out.bands[kb].off + out.bands[kb].M - out.bands[ke].off);
+      out.syn_cap = std::max(out.syn_cap, s.total);
+      out.syn.push_back(s);
+    }
+  }
+  return 0;
+}
+
+void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, TableLayout& lay) {
+  blob.clear();
+  const int64_t two_n = p.two_n;
+  // twiddle pyramid: entry n + k holds e^{-2 pi i k / n} for n = 1, 2, 4, ..., 2N
+  std::vector<double> tw(2 * 2 * two_n, 0.0);
+  for (int64_t n = 1; n <= two_n; n <<= 1) {
+    for (int64_t k = 0; k < n; ++k) {
+      // reduce the angle exactly to the first octant before calling cos/sin
+      const double a = 2.0 * M_PI * (double)k / (double)n;
+      double c = std::cos(a), s = -std::sin(a);
+      if (4 * k == n) { c = 0.0; s = -1.0; }
+      if (2 * k == n) { c = -1.0; s = 0.0; }
+      if (4 * k == 3 * n) { c = 0.0; s = 1.0; }
+      if (8 * k == n) { c = std::sqrt(0.5); s = -std::sqrt(0.5); }
+      tw[2 * (n + k)] = c;
+      tw[2 * (n + k) + 1] = s;
+    }
+  }
+  std::vector<BandDev> bd;
+  for (const BandInfo& b : p.bands) {
+    BandDev d{};
+    d.start = (int32_t)b.start;
+    d.len = b.len;
+    d.M = b.M;
+    d.logM = b.logM;
+    d.off = (int32_t)b.off;
+    d.goff = (int32_t)b.goff;
+    d.hlo = b.hlo;
+    d.hhi = b.hhi;
+    bd.push_back(d);
+  }
+  if (dtype == 0) {
+    auto cvt = [](const std::vector<double>& v) {
+      std::vector<float> f(v.size());
+      for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+      return f;
+    };
+    std::vector<float> twf = cvt(tw), h0 = cvt(p.h0), hd = cvt(p.hd), g = cvt(p.g), gd = cvt(p.gd);
+    lay.tw = append(blob, twf.data(), twf.size());
+    lay.h0 = append(blob, h0.data(), h0.size());
+    lay.hd = append(blob, hd.data(), hd.size());
+    lay.g = append(blob, g.data(), g.size());
+    lay.gd = append(blob, gd.data(), gd.size());
+  } else {
+    lay.tw = append(blob, tw.data(), tw.size());
+    lay.h0 = append(blob, p.h0.data(), p.h0.size());
+    lay.hd = append(blob, p.hd.data(), p.hd.size());
+    lay.g = append(blob, p.g.data(), p.g.size());
+    lay.gd = append(blob, p.gd.data(), p.gd.size());
+  }
+  lay.bands = append(blob, bd.data(), bd.size());
+  lay.ana = append(blob, p.ana.data(), p.ana.size());
+  lay.syn = append(blob, p.syn.data(), p.syn.size());
+  lay.runs = append(blob, p.runs.data(), p.runs.size());
+  lay.bin_k0 = append(blob, p.bin_k0.data(), p.bin_k0.size());
+  lay.bin_nk = append(blob, p.bin_nk.data(), p.bin_nk.size());
+  blob.resize((blob.size() + 255) & ~size_t(255));
+  lay.total = blob.size();
+}
+
+}  // namespace slicq

@@ -1,0 +1,71 @@
+// FP64 host plan of the constant-Q painless NSG frame and the Tukey slicing
+// windows, and the work schedule of the HIP kernels.
+#pragma once
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace slicq {
+
+struct PlanParams {
+  double fs = 0, fmin = 0, fmax = 0;
+  int32_t bins_per_octave = 0;
+  int64_t slice_len = 0;        // 2N
+  int64_t transition = 0;       // M of the Tukey window
+  double min_win = 16.0;        // minimal filter length in bins
+  int32_t dual_kind = 0;        // 0: canonical dual slice window, 1: indicator of supp h_0
+  int32_t group_cap = 4096;     // coefficients per analysis work item
+  int32_t lds_cap = 9216;       // complex values a synthesis work item may hold
+  int32_t pass_cap = 4096;      // complex values per four-step FFT work item
+};
+
+struct BandInfo {
+  int32_t k = 0;
+  int64_t start = 0;   // signed first bin of J_k
+  int32_t len = 0;     // |J_k|
+  int32_t M = 0;       // M_k = 2N / a_k
+  int32_t logM = 0;
+  int64_t off = 0;     // sum_{k' < k} M_k'
+  int64_t goff = 0;    // offset in the concatenated window tables
+  int32_t hlo = 0, hhi = 0;   // bins of J_k inside [0, N]
+  double xi = 0, omega = 0;   // centre and bandwidth in Hz
+};
+
+struct Plan {
+  PlanParams prm;
+  double Q = 0;
+  int64_t two_n = 0, N = 0, Mt = 0;
+  int32_t K0 = 0, K = 0, nb = 0;
+  std::vector<BandInfo> bands;          // stored bands 0..K+1
+  std::vector<double> g, gd;            // windows over each J_k, concatenated
+  std::vector<double> D;                // frame-operator diagonal, 2N bins
+  std::vector<double> h0, hd;           // slicing window and dual, index j = t + N
+  std::vector<int32_t> bin_k0, bin_nk;  // bands covering each bin of [0, N]
+  int64_t coefs_per_slice = 0;
+  int32_t max_M = 0;
+
+  // kernel schedule
+  std::vector<AnaGroupDev> ana;
+  std::vector<SynGroupDev> syn;
+  std::vector<SynRunDev> runs;
+  int32_t ana_cap = 0, syn_cap = 0;     // largest work item, complex values
+  int32_t N1 = 0, N2 = 0, logN1 = 0, logN2 = 0;
+  int32_t C = 0, P = 0;                 // columns per pass-1 item, row pairs per pass-2 item
+
+  // device tables, per dtype (0: f32, 1: f64); owned by the caller
+  std::mutex mu;
+  void* dev[2] = {nullptr, nullptr};
+  size_t dev_bytes[2] = {0, 0};
+  TableLayout layout[2] = {};
+};
+
+// Builds the plan; returns 0 or a negative status with a message in err.
+int build_plan(const PlanParams& p, Plan& out, std::string& err);
+
+// Packs the device tables for dtype (0 f32, 1 f64) into a host byte vector.
+void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, TableLayout& lay);
+
+}  // namespace slicq

@@ -1,0 +1,77 @@
+"""Builds and drives the CPU emulation runner of the library's kernels.
+
+Test infrastructure only: the runner compiles the library's own kernel,
+pipeline and plan sources with g++ against a thread-per-lane stand-in for the
+HIP runtime (AddressSanitizer and UBSan on), and runs one transform on host
+memory.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_1210_0084_amd", "csrc")
+BUILD = os.path.join(HERE, "_build")
+EXE = os.path.join(BUILD, "emu_runner")
+SOURCES = [os.path.join(HERE, "emu_runner.cpp"), os.path.join(CSRC, "plan.cpp")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "plan.hpp", "common.hpp")]
+
+
+def build() -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    deps = SOURCES + HEADERS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")]
+    if os.path.exists(EXE) and os.path.getmtime(EXE) > max(os.path.getmtime(d) for d in deps):
+        return EXE
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", *SOURCES, "-o", EXE + ".tmp"]
+    subprocess.check_call(cmd)
+    os.replace(EXE + ".tmp", EXE)
+    return EXE
+
+
+def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,
+        group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0) -> np.ndarray:
+    """Runs one emulated transform; returns the raw float64 output."""
+    exe = build()
+    with tempfile.TemporaryDirectory() as td:
+        fin = os.path.join(td, "in.bin")
+        fout = os.path.join(td, "out.bin")
+        np.asarray(payload, dtype=np.float64).tofile(fin)
+        args = [exe, op, str(dtype), repr(float(plan["fs"])), repr(float(plan["fmin"])), repr(float(plan["fmax"])),
+                str(plan["bins_per_octave"]), str(plan["slice_len"]), str(plan["transition"]),
+                repr(float(plan.get("min_win", 16.0))), str(plan.get("dual", 0)), str(group_cap), str(lds_cap),
+                str(pass_cap), str(chunk), fin, fout]
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
+        r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=600)
+        if r.returncode != 0:
+            raise RuntimeError(f"emu_runner failed ({r.returncode}): {r.stderr[-3000:]}")
+        return np.fromfile(fout, dtype=np.float64)
+
+
+def analyze(plan: dict, x: np.ndarray, dtype: int = 1, **kw) -> np.ndarray:
+    out = run("ana", dtype, plan, np.concatenate([[len(x)], x]), **kw)
+    return out[0::2] + 1j * out[1::2]
+
+
+def synthesize(plan: dict, coef: np.ndarray, T: int, dtype: int = 1, adjoint: bool = False, **kw) -> np.ndarray:
+    c = np.asarray(coef, dtype=np.complex128)
+    payload = np.concatenate([[T], np.stack([c.real, c.imag], axis=1).reshape(-1)])
+    return run("adj" if adjoint else "syn", dtype, plan, payload, **kw)
+
+
+def analyze_batched(plan: dict, xs, dtype: int = 1, **kw) -> np.ndarray:
+    lens = [len(x) for x in xs]
+    payload = np.concatenate([[len(xs)], lens] + [np.asarray(x, dtype=np.float64) for x in xs])
+    out = run("bana", dtype, plan, payload, **kw)
+    return out[0::2] + 1j * out[1::2]
+
+
+def synthesize_batched(plan: dict, coef: np.ndarray, lens, dtype: int = 1, adjoint: bool = False, **kw):
+    c = np.asarray(coef, dtype=np.complex128)
+    payload = np.concatenate([[len(lens)], lens, np.stack([c.real, c.imag], axis=1).reshape(-1)])
+    return run("badj" if adjoint else "bsyn", dtype, plan, payload, **kw)

@@ -1,0 +1,32 @@
+// CPU stand-in for the few HIP device features the sliCQ kernels use, so that
+// the unmodified kernel header can be compiled by g++ and run with one OS
+// thread per GPU lane (std::barrier for __syncthreads). Test harness only:
+// never part of the product library.
+#pragma once
+#include <atomic>
+#include <barrier>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__
+
+struct dim3 {
+  unsigned x, y, z;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+
+extern thread_local dim3 threadIdx, blockIdx, blockDim;
+extern thread_local std::barrier<>* emu_barrier;
+
+inline void __syncthreads() { emu_barrier->arrive_and_wait(); }
+
+template <class T>
+inline T unsafeAtomicAdd(T* p, T v) {
+  return std::atomic_ref<T>(*p).fetch_add(v);
+}
