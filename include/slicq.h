@@ -169,6 +169,17 @@ int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dtype, const void* coef, 
                           int32_t nsig, int64_t total_slices, void* work, size_t work_bytes,
                           void* hip_stream);
 
+/* Measurement hook: enqueues one kernel of the pipeline of the preceding
+ * transform call made with the same plan, dtype, buffers and workspace (which
+ * must hold all n_slices slices at once), so that a profiler can time it
+ * alone. Stages: 0 slice FFT pass 1, 1 slice FFT pass 2 and real split,
+ * 2 band analysis, 3 band synthesis, 4 inverse FFT pass A, 5 inverse FFT pass B
+ * with overlap-add. The stage reads what the preceding call left in the
+ * workspace; outputs are overwritten (stage 5 accumulates into the overlap
+ * samples of y, which stage 3 zeroes). */
+int slicq_profile_stage(slicq_plan plan, slicq_dtype dtype, int stage, int64_t n_slices, const void* x,
+                        void* coef, void* y, void* work, size_t work_bytes, void* hip_stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* slicq_last_error(void);
 

@@ -1,0 +1,404 @@
+"""MI355X sliCQ: Python binding of ``libslicq.so`` (include/slicq.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels of the library. PyTorch provides device memory and the HIP stream
+(``torch.cuda.current_stream().cuda_stream``). The binding fails loudly when
+the library is missing; there is no other implementation behind it.
+
+    plan = Plan(44100, 32.7, 22050, 48, 65536, 8192)
+    c = plan.analyze(x)                 # x: (T,) float32/float64 on cuda
+    y = plan.synthesize(c, T)           # perfect reconstruction
+    cb = plan.band(c, k, plan.num_slices(T))   # (S, M_k) view of band k
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = ["Plan", "SliCQFunction", "slicq", "library_path", "SlicqError", "load_library"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libslicq.so")
+_lib = None
+
+F32, F64 = 0, 1
+
+
+class SlicqError(RuntimeError):
+    pass
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("fs", ctypes.c_double), ("fmin", ctypes.c_double), ("fmax", ctypes.c_double),
+                ("bins_per_octave", ctypes.c_int32), ("slice_len", ctypes.c_int64),
+                ("transition_len", ctypes.c_int64), ("min_win", ctypes.c_double),
+                ("dual_slice", ctypes.c_int32), ("group_cap", ctypes.c_int32),
+                ("lds_cap", ctypes.c_int32), ("pass_cap", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("nbands", ctypes.c_int32), ("slice_len", ctypes.c_int64),
+                ("transition_len", ctypes.c_int64), ("coefs_per_slice", ctypes.c_int64),
+                ("Q", ctypes.c_double), ("max_M", ctypes.c_int32), ("n_ana_items", ctypes.c_int32),
+                ("n_syn_items", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Loads libslicq.so (built in-tree by ``python -m paper_1210_0084_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise SlicqError(f"{_LIB_PATH} is missing: build it with `python -m paper_1210_0084_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "nsgt_plan": (ctypes.c_int, [D, D, D, ctypes.c_int, I64, I64, ctypes.POINTER(P)]),
+        "nsgt_plan_ex": (ctypes.c_int, [ctypes.POINTER(_Opts), ctypes.POINTER(P)]),
+        "nsgt_plan_destroy": (None, [P]),
+        "nsgt_plan_info": (ctypes.c_int, [P, ctypes.POINTER(_Info)]),
+        "nsgt_plan_bands": (ctypes.c_int, [P, P, P, P, P, P, P]),
+        "nsgt_plan_windows": (ctypes.c_int, [P, P, P, P, P, P]),
+        "nsgt_plan_table_bytes": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(SZ)]),
+        "nsgt_plan_upload": (ctypes.c_int, [P, ctypes.c_int, P, SZ, P]),
+        "slicq_num_slices": (I64, [P, I64]),
+        "slicq_workspace_size": (ctypes.c_int, [P, ctypes.c_int, I64, ctypes.POINTER(SZ)]),
+        "slicq_analyze": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_synthesize": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_adjoint": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_analyze_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I32, I64, P, I64, P, P, SZ, P]),
+        "slicq_synthesize_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
+        "slicq_adjoint_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
+        "slicq_profile_stage": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, I64, P, P, P, P, SZ, P]),
+        "slicq_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = load_library().slicq_last_error().decode(errors="replace")
+        raise SlicqError(f"slicq error {rc}: {msg}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype in (torch.float32, torch.complex64):
+        return F32
+    if t.dtype in (torch.float64, torch.complex128):
+        return F64
+    raise SlicqError(f"unsupported dtype {t.dtype}: use float32 or float64")
+
+
+def _stream_ptr(dev) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _require_cuda(t, name):
+    if not t.is_cuda:
+        raise SlicqError(f"{name} must be a HIP device tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise SlicqError(f"{name} must be contiguous")
+
+
+class BatchLayout:
+    """Offsets of a ragged batch packed back to back (host and cached device copies)."""
+
+    def __init__(self, plan, lengths):
+        lengths = np.asarray(lengths, dtype=np.int64)
+        self.lengths = lengths
+        self.x_off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+        S = np.array([plan.num_slices(int(t)) for t in lengths], dtype=np.int64)
+        self.slices = S
+        c_sz = S * plan.coefs_per_slice
+        self.coef_off = (np.concatenate([[0], np.cumsum(c_sz)[:-1]]).astype(np.int64) if len(lengths)
+                         else np.zeros(0, dtype=np.int64))
+        self.total_slices = int(S.sum())
+        self.coef_len = int(c_sz.sum())
+        self._dev = {}
+
+    @property
+    def nsig(self) -> int:
+        return len(self.lengths)
+
+    def device(self, dev):
+        key = str(dev)
+        if key not in self._dev:
+            torch = _torch()
+            self._dev[key] = (torch.as_tensor(self.x_off, device=dev), torch.as_tensor(self.coef_off, device=dev))
+        return self._dev[key]
+
+
+class Plan:
+    """A sliCQ plan (Section 3, Table 1; Section 4.3) with its device tables.
+
+    Parameters follow the paper: sampling rate ``fs`` (xi_s), ``fmin``/``fmax``
+    (xi_min, xi_max), ``bins_per_octave`` (B), ``slice_len`` (2N) and
+    ``transition`` (M of the Tukey slicing window).
+    """
+
+    def __init__(self, fs: float, fmin: float, fmax: float, bins_per_octave: int, slice_len: int,
+                 transition: int, min_win: float = 16.0, dual_slice: str = "canonical",
+                 group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0):
+        lib = load_library()
+        o = _Opts(float(fs), float(fmin), float(fmax), int(bins_per_octave), int(slice_len), int(transition),
+                  float(min_win), {"canonical": 0, "indicator": 1}[dual_slice], int(group_cap), int(lds_cap),
+                  int(pass_cap))
+        h = ctypes.c_void_p()
+        _check(lib.nsgt_plan_ex(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        info = _Info()
+        _check(lib.nsgt_plan_info(h, ctypes.byref(info)))
+        self.K = info.K
+        self.nbands = info.nbands
+        self.slice_len = info.slice_len
+        self.N = info.slice_len // 2
+        self.transition = info.transition_len
+        self.coefs_per_slice = info.coefs_per_slice
+        self.Q = info.Q
+        self.max_M = info.max_M
+        self.n_ana_items = info.n_ana_items
+        self.n_syn_items = info.n_syn_items
+        self.fs, self.fmin, self.fmax, self.bins_per_octave = float(fs), float(fmin), float(fmax), int(bins_per_octave)
+        nb = self.nbands
+        self.M = np.zeros(nb, dtype=np.int32)
+        self.offsets = np.zeros(nb, dtype=np.int64)
+        self.starts = np.zeros(nb, dtype=np.int64)
+        self.lengths = np.zeros(nb, dtype=np.int32)
+        self.fc = np.zeros(nb)
+        self.bw = np.zeros(nb)
+        _check(lib.nsgt_plan_bands(h, self.M.ctypes.data, self.offsets.ctypes.data, self.starts.ctypes.data,
+                                   self.lengths.ctypes.data, self.fc.ctypes.data, self.bw.ctypes.data))
+        self._tables = {}
+        self._work = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.nsgt_plan_destroy(h)
+            self._h = None
+
+    # -- host tables -------------------------------------------------------
+    def windows(self):
+        """FP64 host tables: (g, gd, h0, hd, D) as numpy arrays."""
+        tot = int(self.lengths.sum())
+        g, gd = np.zeros(tot), np.zeros(tot)
+        h0, hd, D = np.zeros(self.slice_len), np.zeros(self.slice_len), np.zeros(self.slice_len)
+        _check(self._lib.nsgt_plan_windows(self._h, g.ctypes.data, gd.ctypes.data, h0.ctypes.data,
+                                           hd.ctypes.data, D.ctypes.data))
+        return g, gd, h0, hd, D
+
+    # -- device state --------------------------------------------------------
+    def _ensure_tables(self, dt: int, device):
+        torch = _torch()
+        key = (dt, str(device))
+        if key in self._tables:
+            return
+        nbytes = ctypes.c_size_t()
+        _check(self._lib.nsgt_plan_table_bytes(self._h, dt, ctypes.byref(nbytes)))
+        buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        _check(self._lib.nsgt_plan_upload(self._h, dt, ctypes.c_void_p(buf.data_ptr() + off), nbytes.value,
+                                          ctypes.c_void_p(_stream_ptr(device))))
+        self._tables[key] = buf
+
+    def workspace_bytes(self, dt: int, n_slices: int) -> int:
+        b = ctypes.c_size_t()
+        _check(self._lib.slicq_workspace_size(self._h, dt, int(n_slices), ctypes.byref(b)))
+        return b.value
+
+    def _workspace(self, dt: int, n_slices: int, device, work=None):
+        torch = _torch()
+        need = self.workspace_bytes(dt, n_slices)
+        if work is not None:
+            return work, work.numel() * work.element_size()
+        key = (dt, str(device))
+        w = self._work.get(key)
+        if w is None or w.numel() < need:
+            w = torch.empty(need, dtype=torch.uint8, device=device)
+            self._work[key] = w
+        return w, w.numel()
+
+    # -- shapes -------------------------------------------------------------
+    def num_slices(self, T: int) -> int:
+        return int(self._lib.slicq_num_slices(self._h, int(T)))
+
+    def coef_count(self, T: int) -> int:
+        return self.num_slices(T) * self.coefs_per_slice
+
+    def band(self, coef, k: int, S: int):
+        """Band k of a band-major coefficient vector as an (S, M_k) view."""
+        off = int(self.offsets[k]) * S
+        return coef[off:off + S * int(self.M[k])].view(S, int(self.M[k]))
+
+    # -- transforms ---------------------------------------------------------
+    def analyze(self, x, out=None, work=None):
+        """Coefficients of the real signal x (Algorithm 3), band-major complex vector."""
+        torch = _torch()
+        _require_cuda(x, "x")
+        if x.dim() != 1:
+            raise SlicqError("x must be 1-D; use analyze_batched for several signals")
+        dt = _dtype_code(x)
+        T = x.numel()
+        S = self.num_slices(T)
+        ctype = torch.complex64 if dt == F32 else torch.complex128
+        if out is None:
+            out = torch.empty(S * self.coefs_per_slice, dtype=ctype, device=x.device)
+        _require_cuda(out, "out")
+        self._ensure_tables(dt, x.device)
+        w, wb = self._workspace(dt, S, x.device, work)
+        _check(self._lib.slicq_analyze(self._h, dt, ctypes.c_void_p(x.data_ptr()), T,
+                                       ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(w.data_ptr()),
+                                       wb, ctypes.c_void_p(_stream_ptr(x.device))))
+        return out
+
+    def _synth(self, coef, T, adjoint, out, work):
+        torch = _torch()
+        _require_cuda(coef, "coef")
+        dt = _dtype_code(coef)
+        rtype = torch.float32 if dt == F32 else torch.float64
+        S = self.num_slices(T)
+        if out is None:
+            out = torch.empty(int(T), dtype=rtype, device=coef.device)
+        _require_cuda(out, "out")
+        self._ensure_tables(dt, coef.device)
+        w, wb = self._workspace(dt, S, coef.device, work)
+        fn = self._lib.slicq_adjoint if adjoint else self._lib.slicq_synthesize
+        _check(fn(self._h, dt, ctypes.c_void_p(coef.data_ptr()), coef.numel(), ctypes.c_void_p(out.data_ptr()),
+                  int(T), ctypes.c_void_p(w.data_ptr()), wb, ctypes.c_void_p(_stream_ptr(coef.device))))
+        return out
+
+    def synthesize(self, coef, T: int, out=None, work=None):
+        """Reconstruction from band-major coefficients (Algorithm 4, canonical duals)."""
+        return self._synth(coef, T, False, out, work)
+
+    def adjoint(self, coef, T: int, out=None, work=None):
+        """Re(A^H coef): the transpose of ``analyze`` for the real inner product."""
+        return self._synth(coef, T, True, out, work)
+
+    # -- ragged batches -----------------------------------------------------
+    def batch_layout(self, lengths: Sequence[int]) -> BatchLayout:
+        """Offsets for a ragged batch; pass it back to the batched calls to reuse it."""
+        return BatchLayout(self, lengths)
+
+    def analyze_batched(self, x_packed, lengths=None, out=None, work=None, layout: Optional[BatchLayout] = None):
+        """Analysis of a ragged batch packed back to back in x_packed; one launch per kernel."""
+        torch = _torch()
+        _require_cuda(x_packed, "x_packed")
+        dt = _dtype_code(x_packed)
+        lay = layout if layout is not None else self.batch_layout(lengths)
+        ctype = torch.complex64 if dt == F32 else torch.complex128
+        if out is None:
+            out = torch.empty(max(lay.coef_len, 1), dtype=ctype, device=x_packed.device)
+        _require_cuda(out, "out")
+        d_xoff, d_coff = lay.device(x_packed.device)
+        self._ensure_tables(dt, x_packed.device)
+        w, wb = self._workspace(dt, lay.total_slices, x_packed.device, work)
+        _check(self._lib.slicq_analyze_batched(
+            self._h, dt, ctypes.c_void_p(x_packed.data_ptr()), x_packed.numel(), ctypes.c_void_p(d_xoff.data_ptr()),
+            lay.nsig, lay.total_slices, ctypes.c_void_p(out.data_ptr()), out.numel(),
+            ctypes.c_void_p(d_coff.data_ptr()), ctypes.c_void_p(w.data_ptr()), wb,
+            ctypes.c_void_p(_stream_ptr(x_packed.device))))
+        return out
+
+    def synthesize_batched(self, coef, lengths=None, out=None, work=None, layout: Optional[BatchLayout] = None,
+                           adjoint: bool = False):
+        """Synthesis (or adjoint) of a ragged batch; outputs packed like the inputs."""
+        torch = _torch()
+        _require_cuda(coef, "coef")
+        dt = _dtype_code(coef)
+        lay = layout if layout is not None else self.batch_layout(lengths)
+        rtype = torch.float32 if dt == F32 else torch.float64
+        if out is None:
+            out = torch.empty(max(int(lay.x_off[-1]), 1), dtype=rtype, device=coef.device)
+        _require_cuda(out, "out")
+        d_xoff, d_coff = lay.device(coef.device)
+        self._ensure_tables(dt, coef.device)
+        w, wb = self._workspace(dt, lay.total_slices, coef.device, work)
+        fn = self._lib.slicq_adjoint_batched if adjoint else self._lib.slicq_synthesize_batched
+        _check(fn(self._h, dt, ctypes.c_void_p(coef.data_ptr()), coef.numel(), ctypes.c_void_p(d_coff.data_ptr()),
+                  ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(d_xoff.data_ptr()), lay.nsig,
+                  lay.total_slices, ctypes.c_void_p(w.data_ptr()), wb, ctypes.c_void_p(_stream_ptr(coef.device))))
+        return out
+
+    def profile_stage(self, stage: int, n_slices: int, x, coef, y, work=None):
+        """Enqueues one kernel of the preceding call's pipeline (measurement hook)."""
+        dt = _dtype_code(x)
+        w, wb = self._workspace(dt, n_slices, x.device, work)
+        _check(self._lib.slicq_profile_stage(self._h, dt, int(stage), int(n_slices), ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                             ctypes.c_void_p(w.data_ptr()), wb,
+                                             ctypes.c_void_p(_stream_ptr(x.device))))
+
+
+def _make_function():
+    torch = _torch()
+
+    class SliCQFunction(torch.autograd.Function):
+        """Differentiable analysis: forward = slicq_analyze, backward = slicq_adjoint.
+
+        x is a real (T,) signal or a (B, T) batch of equal-length signals; the
+        output is the band-major coefficient vector (per signal for batches).
+        The backward of a real-input, complex-output linear map is
+        Re(A^H grad).
+        """
+
+        @staticmethod
+        def forward(ctx, x, plan):
+            ctx.plan = plan
+            ctx.shape = x.shape
+            if x.dim() == 1:
+                return plan.analyze(x.contiguous())
+            B, T = x.shape
+            lay = plan.batch_layout([T] * B)
+            ctx.layout = lay
+            c = plan.analyze_batched(x.contiguous().view(-1), layout=lay)
+            return c.view(B, -1)
+
+        @staticmethod
+        def backward(ctx, grad):
+            plan = ctx.plan
+            grad = grad.contiguous()
+            if len(ctx.shape) == 1:
+                return plan.adjoint(grad, ctx.shape[0]), None
+            B, T = ctx.shape
+            gx = plan.synthesize_batched(grad.view(-1), layout=ctx.layout, adjoint=True)
+            return gx.view(B, T), None
+
+    return SliCQFunction
+
+
+_SliCQFunction = None
+
+
+def __getattr__(name):
+    global _SliCQFunction
+    if name == "SliCQFunction":
+        if _SliCQFunction is None:
+            _SliCQFunction = _make_function()
+        return _SliCQFunction
+    raise AttributeError(name)
+
+
+def slicq(x, plan: Plan):
+    """Differentiable sliCQ analysis (see SliCQFunction)."""
+    return __getattr__("SliCQFunction").apply(x, plan)

@@ -44,11 +44,18 @@ struct HipLaunch {
   }
 };
 
+int check_geometry(const slicq::Plan& p, int dt);
+
 int check_plan(slicq_plan plan, slicq_dtype dt) {
   if (!plan) return fail(SLICQ_EINVAL, "null plan");
   if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "dtype must be SLICQ_F32 or SLICQ_F64");
   if (!plan->p.dev[dt]) return fail(SLICQ_ESTATE, "plan tables not uploaded for this dtype (nsgt_plan_upload)");
-  return SLICQ_OK;
+  return check_geometry(plan->p, dt);
+}
+
+int check_geometry(const slicq::Plan& p, int dt) {
+  const bool ok = dt == SLICQ_F32 ? slicq::geometry<float>(p).ok : slicq::geometry<double>(p).ok;
+  return ok ? SLICQ_OK : fail(SLICQ_EINVAL, "plan work items exceed the kernels' block limits");
 }
 
 int64_t slices_of(const slicq::Plan& p, int64_t T) {
@@ -359,6 +366,50 @@ int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dt, const void* coef, int
                           int64_t total, void* work, size_t work_bytes, void* stream) {
   return synth_batched_common(plan, dt, true, coef, coef_len, coef_off, y, y_len, y_off, nsig, total, work,
                               work_bytes, stream);
+}
+
+int slicq_profile_stage(slicq_plan plan, slicq_dtype dt, int stage, int64_t n_slices, const void* x, void* coef,
+                        void* y, void* work, size_t work_bytes, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (stage < 0 || stage > 5) return fail(SLICQ_EINVAL, "stage must be in 0..5");
+  if (n_slices <= 0 || !x || !coef || !y || !work) return fail(SLICQ_EINVAL, "bad argument");
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, n_slices, work_bytes, w))) return rc;
+  if (w.chunk < n_slices) return fail(SLICQ_ESIZE, "profiling needs a workspace for all slices at once");
+  char* wk = static_cast<char*>(work);
+  const auto* tasks = reinterpret_cast<const slicq::SliceTask*>(wk + w.tasks_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HipLaunch L{st};
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    using namespace slicq;
+    KArgs<T> a = make_args<T>(p, dt, false);
+    a.zero_ola = 1;
+    const Geometry<T> g = geometry<T>(p);
+    C2<T>* W1 = reinterpret_cast<C2<T>*>(wk + w.w1_off);
+    C2<T>* W2 = reinterpret_cast<C2<T>*>(wk + w.w2_off);
+    const int64_t n = n_slices;
+    switch (stage) {
+      case 0: L.launch(k_fwd_pass1<T>, n * g.g1, g.b1, g.s1, a, tasks, static_cast<const T*>(x), W1); break;
+      case 1: L.launch(k_fwd_pass2<T>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2); break;
+      case 2:
+        if (g.Ea == 16) L.launch(k_band_ana<T, 16>, n * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, static_cast<C2<T>*>(coef));
+        else L.launch(k_band_ana<T, 32>, n * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, static_cast<C2<T>*>(coef));
+        break;
+      case 3:
+        if (g.Es == 16) L.launch(k_band_syn<T, 16>, n * g.gs, g.bs, g.ss, a, tasks, (const C2<T>*)coef, W2, static_cast<T*>(y));
+        else L.launch(k_band_syn<T, 32>, n * g.gs, g.bs, g.ss, a, tasks, (const C2<T>*)coef, W2, static_cast<T*>(y));
+        break;
+      case 4: L.launch(k_inv_passA<T>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1); break;
+      default: L.launch(k_inv_passB<T>, n * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, static_cast<T*>(y)); break;
+    }
+  };
+  if (dt == SLICQ_F32) go(float{});
+  else go(double{});
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "stage launch");
 }
 
 const char* slicq_last_error(void) { return g_err.c_str(); }

@@ -25,6 +25,11 @@
 
 namespace slicq {
 
+// Largest block each kernel is compiled for (its __launch_bounds__).
+constexpr int kPassThreads = 256;     // k_fwd_pass1/2, k_inv_passA/B
+constexpr int kAnaThreads = 256;      // k_band_ana
+constexpr int kSynThreads = 512;      // k_band_syn
+
 template <class T>
 struct KArgs {
   const C2<T>* tw;        // twiddle pyramid
@@ -187,7 +192,7 @@ __device__ __forceinline__ C2<T> spec_at(const C2<T>* __restrict__ X, int j, int
 // Band analysis: bands k0 .. k0 + cnt - 1 of one slice. Slot r of band k
 // holds X[j] g_k[j] for the bin j of J_k with j = r (mod M_k), or 0; the
 // inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff).
-template <class T>
+template <class T, int E>
 __global__ void __launch_bounds__(256) k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks,
                                                    const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef) {
   extern __shared__ unsigned char smem[];
@@ -208,7 +213,7 @@ __global__ void __launch_bounds__(256) k_band_ana(KArgs<T> a, const SliceTask* _
     buf[pidx(e)] = v;
   }
   __syncthreads();
-  lds_fft<T, 1, CONTIG>(buf, 0, G.logM, G.cnt, 0, a.tw, tid, nthr);
+  lds_fft<T, 1, CONTIG, E>(buf, 0, G.logM, G.cnt, 0, a.tw, tid, nthr);
   const int64_t S = tk.S;
   for (int e = tid; e < total; e += nthr) {
     const int k = G.k0 + (e >> G.logM), n = e & mask;

@@ -26,6 +26,8 @@ inline int ilog2i(int64_t n) {
 
 inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+constexpr size_t kMaxLdsBytes = 160 * 1024;   // LDS of one gfx950 workgroup
+
 // Workspace: [slice tasks][status words][W1: chunk x N][W2: chunk x (N + 64)]
 struct WorkLayout {
   size_t tasks_off = 0, status_off = 0, w1_off = 0, w2_off = 0, total = 0;
@@ -103,8 +105,9 @@ template <class T>
 struct Geometry {
   int g1, b1; size_t s1;      // forward pass 1 / inverse pass B: items per slice, threads, LDS bytes
   int g2, b2; size_t s2;      // forward pass 2 / inverse pass A
-  int ga, ba; size_t sa;      // band analysis
+  int ga, ba, Ea; size_t sa;  // band analysis (Ea values per thread)
   int gs, bs, Es; size_t ss;  // band synthesis (Es values per thread)
+  bool ok;                    // every block fits its kernel's launch bound
 };
 
 template <class T>
@@ -118,12 +121,17 @@ Geometry<T> geometry(const Plan& p) {
   g.b2 = threads_for((int64_t)2 * p.P * p.N1);
   g.s2 = padded(2 * p.P * p.N1) * cb;
   g.ga = (int)p.ana.size();
-  g.ba = threads_for(p.ana_cap);
+  g.Ea = p.ana_cap > 16 * kAnaThreads ? 32 : 16;
+  g.ba = threads_for(p.ana_cap, g.Ea);
   g.sa = padded(p.ana_cap) * cb;
   g.gs = (int)p.syn.size();
   g.Es = p.syn_cap > 16 * 512 ? 32 : 16;
   g.bs = threads_for(p.syn_cap, g.Es);
   g.ss = padded(p.syn_cap) * cb;
+  g.ok = g.b1 <= kPassThreads && g.b2 <= kPassThreads && g.ba <= kAnaThreads && g.bs <= kSynThreads &&
+         (int64_t)p.C * p.N2 <= 16LL * g.b1 && 2LL * p.P * p.N1 <= 16LL * g.b2 &&
+         p.ana_cap <= g.Ea * g.ba && p.syn_cap <= g.Es * g.bs &&
+         std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss)) <= kMaxLdsBytes;
   return g;
 }
 
@@ -133,7 +141,8 @@ void launch_analysis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, con
                      int64_t cnt, const T* x, C2<T>* coef, C2<T>* W1, C2<T>* W2, Launch& L) {
   L.launch(k_fwd_pass1<T>, cnt * g.g1, g.b1, g.s1, a, tasks, x, W1);
   L.launch(k_fwd_pass2<T>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2);
-  L.launch(k_band_ana<T>, cnt * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, coef);
+  if (g.Ea == 16) L.launch(k_band_ana<T, 16>, cnt * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, coef);
+  else L.launch(k_band_ana<T, 32>, cnt * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, coef);
   (void)p;
 }
 

@@ -139,6 +139,10 @@ int run(const std::string& op, slicq::Plan& p, int dt, int64_t chunk_req, const 
   C2<T>* W1 = reinterpret_cast<C2<T>*>(work.data() + w.w1_off);
   C2<T>* W2 = reinterpret_cast<C2<T>*>(work.data() + w.w2_off);
   const Geometry<T> g = geometry<T>(p);
+  if (!g.ok) {
+    std::fprintf(stderr, "work items exceed the kernels' block limits\n");
+    return 9;
+  }
   if (kind == "ana") {
     KArgs<T> a = make_args<T>(p, dt, false);
     for (int64_t t0 = 0; t0 < total; t0 += w.chunk)

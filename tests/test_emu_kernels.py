@@ -1,0 +1,63 @@
+"""CPU parity of the library's kernels, compiled unmodified by g++ against a
+thread-per-lane stand-in for the HIP runtime (tests/emu), against the FP64
+oracle. This checks the kernels' index arithmetic and the launch geometry on
+the host before any GPU run; the GPU tests check the same on the device."""
+import numpy as np
+import pytest
+
+from oracle import OraclePlan, analyze, synthesize, adjoint, pack, unpack, num_slices
+from tests.emu import harness as H
+
+TINY = dict(fs=64.0, fmin=4.0, fmax=16.0, bins_per_octave=3, slice_len=64, transition=8, min_win=0.0)
+TINY2 = dict(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0)
+SIXTEEN = dict(fs=16.0, fmin=2.0, fmax=6.0, bins_per_octave=2, slice_len=16, transition=2, min_win=1.0)
+C4 = dict(fs=44100.0, fmin=65.4, fmax=16000.0, bins_per_octave=36, slice_len=16384, transition=2048)
+C5 = dict(fs=48000.0, fmin=27.5, fmax=20000.0, bins_per_octave=96, slice_len=16384, transition=2048)
+TOL = {0: 1e-5, 1: 1e-12}
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+@pytest.mark.parametrize("kw,T", [(TINY, 1), (TINY, 100), (TINY2, 300), (SIXTEEN, 37)])
+def test_emu_roundtrip_and_adjoint(kw, T, dtype):
+    pl = OraclePlan(**kw)
+    x = np.random.default_rng(T).standard_normal(T)
+    c_ref = analyze(pl, x)
+    ref = pack(pl, c_ref)
+    assert rel(H.analyze(kw, x, dtype), ref) <= TOL[dtype]
+    assert rel(H.synthesize(kw, ref, T, dtype), x) <= TOL[dtype]
+    g = np.random.default_rng(T + 1)
+    cr = g.standard_normal(len(ref)) + 1j * g.standard_normal(len(ref))
+    S = num_slices(T, pl.two_n)
+    assert rel(H.synthesize(kw, cr, T, dtype, adjoint=True), adjoint(pl, unpack(pl, cr, S), T)) <= TOL[dtype]
+    assert rel(H.synthesize(kw, cr, T, dtype), synthesize(pl, unpack(pl, cr, S), T)) <= TOL[dtype]
+
+
+def test_emu_chunked_and_batched():
+    kw = TINY
+    pl = OraclePlan(**kw)
+    x = np.random.default_rng(5).standard_normal(500)
+    ref = pack(pl, analyze(pl, x))
+    assert rel(H.analyze(kw, x, 1, chunk=3), ref) < 1e-12
+    assert rel(H.synthesize(kw, ref, 500, 1, chunk=3), x) < 1e-12
+    xs = [np.random.default_rng(i).standard_normal(n) for i, n in enumerate([100, 0, 64, 257])]
+    cb = H.analyze_batched(kw, xs, 1)
+    refb = np.concatenate([pack(pl, analyze(pl, v)) for v in xs if len(v)])
+    assert rel(cb, refb) < 1e-12
+    yb = H.synthesize_batched(kw, refb, [len(v) for v in xs], 1)
+    assert rel(yb, np.concatenate(xs)) < 1e-12
+
+
+@pytest.mark.parametrize("kw", [C4, C5], ids=["c4", "c5"])
+def test_emu_preset_shapes(kw):
+    # one pair of slices at full slice length: large band groups (M_k = 8192 in c4),
+    # many overlapping narrow bands (c5), both thread-count variants of the band kernels
+    pl = OraclePlan(**kw)
+    T = 9000
+    x = np.random.default_rng(3).standard_normal(T)
+    ref = pack(pl, analyze(pl, x))
+    assert rel(H.analyze(kw, x, 0), ref) <= 1e-5
+    assert rel(H.synthesize(kw, ref, T, 0), x) <= 1e-5

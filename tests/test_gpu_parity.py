@@ -1,0 +1,177 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 over all stored coefficients / all output samples):
+FP32 1e-5 and FP64 1e-12 for coefficients, reconstruction and adjoint.
+"""
+import numpy as np
+import pytest
+
+from oracle import OraclePlan, analyze, synthesize, adjoint, pack, unpack, num_slices
+from workloads import PRESETS, noise_plus_sines, pink_plus_tones
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-12}
+TINY = dict(fs=64.0, fmin=4.0, fmax=16.0, bins_per_octave=3, slice_len=64, transition=8, min_win=0.0)
+TINY2 = dict(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0)
+
+
+def preset(name):
+    p = PRESETS[name]
+    return dict(fs=p.fs, fmin=p.fmin, fmax=p.fmax, bins_per_octave=p.bins_per_octave, slice_len=p.slice_len,
+                transition=p.transition)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def sq():
+    import paper_1210_0084_amd as m
+    return m
+
+
+def torch_dtype(name):
+    import torch
+    return torch.float32 if name == "f32" else torch.float64
+
+
+_plans = {}
+
+
+def gpu_plan(sq, kw):
+    key = tuple(sorted(kw.items()))
+    if key not in _plans:
+        _plans[key] = (sq.Plan(**kw), OraclePlan(**kw))
+    return _plans[key]
+
+
+def check_roundtrip(sq, dev, kw, x, dt, check_adjoint=True, seed=0):
+    import torch
+    plan, opl = gpu_plan(sq, kw)
+    T = len(x)
+    print(f"case 2N={kw['slice_len']} B={kw['bins_per_octave']} T={T} {dt}", flush=True)
+    ref = pack(opl, analyze(opl, x))
+    xd = torch.tensor(x, dtype=torch_dtype(dt), device=dev)
+    c = plan.analyze(xd)
+    y = plan.synthesize(c, T)
+    torch.cuda.synchronize()
+    assert rel(c.cpu().numpy(), ref) <= TOL[dt], rel(c.cpu().numpy(), ref)
+    assert rel(y.cpu().numpy(), x) <= TOL[dt], rel(y.cpu().numpy(), x)
+    if check_adjoint and T > 0:
+        g = np.random.default_rng(seed)
+        S = num_slices(T, opl.two_n)
+        cr = g.standard_normal(len(ref)) + 1j * g.standard_normal(len(ref))
+        ctype = torch.complex64 if dt == "f32" else torch.complex128
+        crd = torch.tensor(cr, dtype=ctype, device=dev)
+        ya = plan.adjoint(crd, T).cpu().numpy()
+        ys = plan.synthesize(crd, T).cpu().numpy()
+        assert rel(ya, adjoint(opl, unpack(opl, cr, S), T)) <= TOL[dt]
+        assert rel(ys, synthesize(opl, unpack(opl, cr, S), T)) <= TOL[dt]
+    return c
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("T", [1, 63, 64, 65, 128, 300, 1000])
+@pytest.mark.parametrize("kw", [TINY, TINY2], ids=["tiny64", "tiny128"])
+def test_tiny_plans(sq, dev, kw, T, dt):
+    x = np.random.default_rng(T).standard_normal(T)
+    check_roundtrip(sq, dev, kw, x, dt, seed=T)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_c1_full(sq, dev, dt):
+    from workloads import make_c1
+    check_roundtrip(sq, dev, preset("c1"), make_c1(), dt)
+
+
+@pytest.mark.parametrize("name,T", [("c3", 100000), ("c4", 264600), ("c5", 60000), ("c2", 150000)])
+def test_preset_shapes_f32(sq, dev, name, T):
+    p = PRESETS[name]
+    x = pink_plus_tones(T, p.fs, 77) if name != "c4" else noise_plus_sines(T, p.fs, 5)
+    check_roundtrip(sq, dev, preset(name), x, "f32", check_adjoint=(name == "c4"))
+
+
+def test_c2_full_stereo_f32(sq, dev):
+    # the benchmarked workload at its full size: 60 s stereo, batched launch
+    import torch
+    from workloads import make_c2
+    kw = preset("c2")
+    plan, opl = gpu_plan(sq, kw)
+    xs = make_c2()
+    T = xs.shape[1]
+    xd = torch.tensor(xs.reshape(-1), dtype=torch.float32, device=dev)
+    c = plan.analyze_batched(xd, [T, T])
+    y = plan.synthesize_batched(c, [T, T])
+    torch.cuda.synchronize()
+    cc = c.cpu().numpy()
+    half = len(cc) // 2
+    for ch in range(2):
+        ref = pack(opl, analyze(opl, xs[ch]))
+        assert rel(cc[ch * half:(ch + 1) * half], ref) <= 1e-5
+    assert rel(y.cpu().numpy(), xs.reshape(-1)) <= 1e-5
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_batch_invariance_bitwise(sq, dev, dt):
+    # each signal's result inside a ragged batch equals its single-signal result bit for bit
+    import torch
+    kw = TINY2
+    plan, _ = gpu_plan(sq, kw)
+    lens = [300, 0, 128, 1, 777, 64]
+    xs = [np.random.default_rng(i + 40).standard_normal(n) for i, n in enumerate(lens)]
+    tdt = torch_dtype(dt)
+    xp = torch.tensor(np.concatenate(xs), dtype=tdt, device=dev)
+    cb = plan.analyze_batched(xp, lens)
+    yb = plan.synthesize_batched(cb, lens)
+    lay = plan.batch_layout(lens)
+    x_off, coef_off = lay.x_off, lay.coef_off
+    for i, n in enumerate(lens):
+        if n == 0:
+            continue
+        ci = plan.analyze(torch.tensor(xs[i], dtype=tdt, device=dev))
+        yi = plan.synthesize(ci, n)
+        assert torch.equal(cb[coef_off[i]:coef_off[i] + ci.numel()], ci)
+        assert torch.equal(yb[x_off[i]:x_off[i + 1]], yi)
+
+
+def test_determinism_bitwise(sq, dev):
+    import torch
+    kw = preset("c4")
+    plan, _ = gpu_plan(sq, kw)
+    x = torch.tensor(noise_plus_sines(100000, 44100.0, 3), dtype=torch.float32, device=dev)
+    c1 = plan.analyze(x).clone()
+    y1 = plan.synthesize(c1, 100000).clone()
+    c2 = plan.analyze(x)
+    y2 = plan.synthesize(c2, 100000)
+    assert torch.equal(c1, c2) and torch.equal(y1, y2)
+
+
+def test_small_workspace_runs_in_chunks(sq, dev):
+    # a workspace for 3 slices processes a 40-slice signal in 14 passes, same result
+    import torch
+    kw = preset("c5")
+    plan, _ = gpu_plan(sq, kw)
+    T = 160000
+    x = torch.tensor(pink_plus_tones(T, 48000.0, 9), dtype=torch.float32, device=dev)
+    S = plan.num_slices(T)
+    small = plan.workspace_bytes(0, S) - (S - 3) * (2 * plan.N + 64) * 8
+    work = torch.empty(small, dtype=torch.uint8, device=dev)
+    c_full = plan.analyze(x).clone()
+    y_full = plan.synthesize(c_full, T).clone()
+    c_chunk = plan.analyze(x, work=work)
+    y_chunk = plan.synthesize(c_chunk, T, work=work)
+    assert torch.equal(c_full, c_chunk) and torch.equal(y_full, y_chunk)
+
+
+def test_size_errors(sq, dev):
+    import torch
+    plan, _ = gpu_plan(sq, TINY2)
+    x = torch.zeros(300, dtype=torch.float32, device=dev)
+    out = torch.empty(10, dtype=torch.complex64, device=dev)
+    with pytest.raises(sq.SlicqError, match="-4"):
+        plan.analyze(x, out=out)
+    with pytest.raises(sq.SlicqError, match="-4"):
+        plan.analyze(x, work=torch.empty(64, dtype=torch.uint8, device=dev))
