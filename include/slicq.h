@@ -30,9 +30,11 @@
  *   threads; concurrent calls must use distinct output and workspace buffers.
  * - Real signals: bands 0..K+1 (DC, K constant-Q bands, Nyquist) are stored.
  *   Bands K+2..2K+1 mirror bands K..1 and carry conjugate coefficients.
- * - Coefficient layout (band-major, complex interleaved re/im of the dtype):
- *   band k, slice m, index n < M_k lives at element S * off_k + m * M_k + n,
- *   off_k = sum_{k' < k} M_k', S = number of slices of the signal.
+ * - Coefficient layout (complex interleaved re/im of the dtype), chosen per
+ *   plan: band-major puts band k, slice m, index n < M_k at element
+ *   S * off_k + m * M_k + n (each band a contiguous S x M_k array); slice-major
+ *   puts it at m * C + off_k + n (each slice's c^m contiguous, Section 4.1),
+ *   with off_k = sum_{k' < k} M_k', C = sum_k M_k, S = slices of the signal.
  */
 #ifndef SLICQ_H
 #define SLICQ_H
@@ -68,10 +70,13 @@ typedef struct {
   int64_t transition_len;   /* Tukey transition M, 0 < M < N, N - M even */
   double min_win;           /* minimal band support in bins (Section 5.3), default 16 */
   int32_t dual_slice;       /* 0: canonical dual h_0 / sum_m T_mN h_0^2, 1: indicator of supp h_0 */
-  int32_t group_cap;        /* tuning: coefficients per analysis work item (power of two), default 4096 */
+  int32_t group_cap;        /* tuning: coefficients of the own bands of a band work item (power of two), default 2048 */
   int32_t lds_cap;          /* tuning: complex values per synthesis work item, default 9216 */
   int32_t pass_cap;         /* tuning: complex values per slice-FFT work item (power of two), default 4096 */
+  int32_t coef_layout;      /* SLICQ_BAND_MAJOR (0) or SLICQ_SLICE_MAJOR (1), see below */
 } slicq_plan_opts;
+
+enum { SLICQ_BAND_MAJOR = 0, SLICQ_SLICE_MAJOR = 1 };
 
 typedef struct {
   int32_t K;                /* constant-Q bands 1..K */
@@ -83,7 +88,7 @@ typedef struct {
   int32_t max_M;            /* largest M_k */
   int32_t n_ana_items;      /* analysis work items per slice */
   int32_t n_syn_items;      /* synthesis work items per slice */
-  int32_t pad_;
+  int32_t coef_layout;      /* SLICQ_BAND_MAJOR or SLICQ_SLICE_MAJOR */
 } slicq_plan_info;
 
 /* Design a plan from the paper's parameters (Section 3, Table 1; Section
@@ -94,7 +99,8 @@ typedef struct {
 int nsgt_plan(double fs, double fmin, double fmax, int bins_per_octave, int64_t slice_len_2N,
               int64_t transition_len, slicq_plan* out);
 
-/* As nsgt_plan with every option explicit; zero tuning fields take defaults. */
+/* As nsgt_plan with every option explicit; zero tuning fields take defaults.
+ * nsgt_plan uses the band-major layout. */
 int nsgt_plan_ex(const slicq_plan_opts* opts, slicq_plan* out);
 
 /* Frees the plan's host memory. The caller still owns the device tables. */

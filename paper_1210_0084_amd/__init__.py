@@ -36,14 +36,14 @@ class _Opts(ctypes.Structure):
                 ("bins_per_octave", ctypes.c_int32), ("slice_len", ctypes.c_int64),
                 ("transition_len", ctypes.c_int64), ("min_win", ctypes.c_double),
                 ("dual_slice", ctypes.c_int32), ("group_cap", ctypes.c_int32),
-                ("lds_cap", ctypes.c_int32), ("pass_cap", ctypes.c_int32)]
+                ("lds_cap", ctypes.c_int32), ("pass_cap", ctypes.c_int32), ("coef_layout", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("nbands", ctypes.c_int32), ("slice_len", ctypes.c_int64),
                 ("transition_len", ctypes.c_int64), ("coefs_per_slice", ctypes.c_int64),
                 ("Q", ctypes.c_double), ("max_M", ctypes.c_int32), ("n_ana_items", ctypes.c_int32),
-                ("n_syn_items", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("n_syn_items", ctypes.c_int32), ("coef_layout", ctypes.c_int32)]
 
 
 def library_path() -> str:
@@ -157,11 +157,11 @@ class Plan:
 
     def __init__(self, fs: float, fmin: float, fmax: float, bins_per_octave: int, slice_len: int,
                  transition: int, min_win: float = 16.0, dual_slice: str = "canonical",
-                 group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0):
+                 group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: str = "band"):
         lib = load_library()
         o = _Opts(float(fs), float(fmin), float(fmax), int(bins_per_octave), int(slice_len), int(transition),
                   float(min_win), {"canonical": 0, "indicator": 1}[dual_slice], int(group_cap), int(lds_cap),
-                  int(pass_cap))
+                  int(pass_cap), {"band": 0, "slice": 1}[layout])
         h = ctypes.c_void_p()
         _check(lib.nsgt_plan_ex(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -178,6 +178,7 @@ class Plan:
         self.max_M = info.max_M
         self.n_ana_items = info.n_ana_items
         self.n_syn_items = info.n_syn_items
+        self.layout = "slice" if info.coef_layout == 1 else "band"
         self.fs, self.fmin, self.fmax, self.bins_per_octave = float(fs), float(fmin), float(fmax), int(bins_per_octave)
         nb = self.nbands
         self.M = np.zeros(nb, dtype=np.int32)
@@ -246,9 +247,18 @@ class Plan:
         return self.num_slices(T) * self.coefs_per_slice
 
     def band(self, coef, k: int, S: int):
-        """Band k of a band-major coefficient vector as an (S, M_k) view."""
-        off = int(self.offsets[k]) * S
-        return coef[off:off + S * int(self.M[k])].view(S, int(self.M[k]))
+        """Band k of one signal's coefficient vector as an (S, M_k) view."""
+        Mk, off = int(self.M[k]), int(self.offsets[k])
+        if self.layout == "slice":
+            return coef[:S * self.coefs_per_slice].view(S, self.coefs_per_slice)[:, off:off + Mk]
+        return coef[off * S:off * S + S * Mk].view(S, Mk)
+
+    def to_band_major(self, coef, S: int):
+        """Band-major copy of one signal's coefficients (identity for band-major plans)."""
+        if self.layout == "band":
+            return coef
+        import torch
+        return torch.cat([self.band(coef, k, S).reshape(-1) for k in range(self.nbands)])
 
     # -- transforms ---------------------------------------------------------
     def analyze(self, x, out=None, work=None):

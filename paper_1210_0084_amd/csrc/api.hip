@@ -63,6 +63,15 @@ int64_t slices_of(const slicq::Plan& p, int64_t T) {
   return 2 * ((T + p.two_n - 1) / p.two_n);
 }
 
+// One signal must keep its padded length and coefficient count below 2^31.
+int check_signal_size(const slicq::Plan& p, int64_t T) {
+  const int64_t S = slices_of(p, T);
+  if (S * p.N > slicq::kMaxSignalElems || S * p.coefs_per_slice > slicq::kMaxSignalElems)
+    return fail(SLICQ_EINVAL, "signal too long for one call: split it (padded length and coefficient count "
+                              "must stay below 2^31)");
+  return SLICQ_OK;
+}
+
 int layout_or_fail(const slicq::Plan& p, int dt, int64_t ntasks, size_t bytes, slicq::WorkLayout& w) {
   if (!slicq::work_layout(p, dt, ntasks, bytes, w)) {
     char b[200];
@@ -130,6 +139,7 @@ int synth_common(slicq_plan plan, slicq_dtype dt, bool adjoint, const void* coef
   if (T < 0) return fail(SLICQ_EINVAL, "T must be >= 0");
   const int64_t S = slices_of(p, T);
   if (S == 0) return SLICQ_OK;
+  if ((rc = check_signal_size(p, T))) return rc;
   if (!coef || !y || !work) return fail(SLICQ_EINVAL, "null buffer");
   if (coef_count < S * p.coefs_per_slice) return fail(SLICQ_ESIZE, "coef_count < S * coefs_per_slice");
   slicq::WorkLayout w;
@@ -190,6 +200,7 @@ int nsgt_plan_ex(const slicq_plan_opts* o, slicq_plan* out) {
   if (o->group_cap) pp.group_cap = o->group_cap;
   if (o->lds_cap) pp.lds_cap = o->lds_cap;
   if (o->pass_cap) pp.pass_cap = o->pass_cap;
+  pp.coef_layout = o->coef_layout;
   slicq_plan h = new (std::nothrow) slicq_plan_s;
   if (!h) return fail(SLICQ_ENOMEM, "out of host memory");
   std::string err;
@@ -237,6 +248,7 @@ int nsgt_plan_info(slicq_plan plan, slicq_plan_info* info) {
   info->max_M = p.max_M;
   info->n_ana_items = (int32_t)p.ana.size();
   info->n_syn_items = (int32_t)p.syn.size();
+  info->coef_layout = p.prm.coef_layout;
   return SLICQ_OK;
 }
 
@@ -312,6 +324,7 @@ int slicq_analyze(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, voi
   if (T < 0) return fail(SLICQ_EINVAL, "T must be >= 0");
   const int64_t S = slices_of(p, T);
   if (S == 0) return SLICQ_OK;
+  if ((rc = check_signal_size(p, T))) return rc;
   if (!x || !coef || !work) return fail(SLICQ_EINVAL, "null buffer");
   if (coef_count < S * p.coefs_per_slice) return fail(SLICQ_ESIZE, "coef_count < S * coefs_per_slice");
   slicq::WorkLayout w;

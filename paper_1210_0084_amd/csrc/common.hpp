@@ -46,9 +46,14 @@ struct alignas(16) SynRunDev {
   int32_t lds_off, pad0_, pad1_, pad2_;
 };
 
-// Byte offsets of the device tables inside one uploaded blob.
+// Byte offsets of the device tables inside one uploaded blob. The frequency
+// overlap-add of synthesis is a per-bin program: bin j (0..N) sums entries
+// ent_off[j] .. ent_off[j+1]-1, entry e reading the transformed coefficient at
+// LDS position ent_pos[e].x (and, for the self-mirrored DC and Nyquist bands,
+// the conjugate of the one at ent_pos[e].y, else y = -1) times ent_wsyn[e]
+// (synthesis, dual windows) or ent_wadj[e] (adjoint, analysis windows).
 struct TableLayout {
-  uint64_t tw, h0, hd, g, gd, bands, ana, syn, runs, bin_k0, bin_nk, total;
+  uint64_t tw, h0, hd, g, gd, bands, ana, syn, runs, ent_off, ent_pos, ent_wsyn, ent_wadj, total;
 };
 
 }  // namespace slicq

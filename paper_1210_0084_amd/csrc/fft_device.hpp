@@ -101,9 +101,31 @@ __device__ __forceinline__ void dft_reg(C2<T>* v) {
 // Twiddle e^{DIR 2 pi i k / n} from the pyramid (entry n + k holds e^{-2 pi i k / n}).
 template <class T, int DIR>
 __device__ __forceinline__ C2<T> twiddle(const C2<T>* __restrict__ tw, int n, int k) {
-  C2<T> w = tw[n + k];
+  C2<T> w = tw[(unsigned)(n + k)];
   if constexpr (DIR > 0) w.y = -w.y;
   return w;
+}
+
+// Powers w^r, r = 1..R-1, of w = e^{DIR 2 pi i k / n}: w^1, w^2, w^4, w^8 come
+// from the table, every other power is a product of at most three of them.
+template <class T, int DIR, int R>
+__device__ __forceinline__ void twiddle_powers(const C2<T>* __restrict__ tw, int n, int k, C2<T>* w) {
+  w[1] = twiddle<T, DIR>(tw, n, k);
+  if constexpr (R > 2) {
+    w[2] = twiddle<T, DIR>(tw, n, 2 * k);
+    w[3] = cmul(w[1], w[2]);
+  }
+  if constexpr (R > 4) {
+    w[4] = twiddle<T, DIR>(tw, n, 4 * k);
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+  }
+  if constexpr (R > 8) {
+    w[8] = twiddle<T, DIR>(tw, n, 8 * k);
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+  }
 }
 
 // Batch layouts of `nseq` sequences of length n in LDS (padded indices):
@@ -136,9 +158,10 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int base, int logn, in
         v[i][r] = buf[pidx(base + pos)];
       }
       if (Ns > 1) {
-        const int k = j & (Ns - 1);
+        C2<T> w[R];
+        twiddle_powers<T, DIR, R>(tw, Ns * R, j & (Ns - 1), w);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twiddle<T, DIR>(tw, Ns * R, r * k));
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
       }
       dft_reg<T, R, DIR>(v[i]);
     }
@@ -169,7 +192,7 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int base, int logn, in
 // inverse (e^+). The caller synchronises the data in; the routine ends with a
 // barrier.
 template <class T, int DIR, int LAY, int E = 16>
-__device__ void lds_fft(C2<T>* buf, int base, int logn, int nseq, int lognseq,
+__device__ __forceinline__ void lds_fft(C2<T>* buf, int base, int logn, int nseq, int lognseq,
                         const C2<T>* __restrict__ tw, int tid, int nthr) {
   int Ns = 1, logNs = 0, rem = logn;
   while (rem > 0) {

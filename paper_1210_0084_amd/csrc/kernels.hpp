@@ -15,6 +15,10 @@
 //                         same four-step factorisation, multiply by h~_0 and
 //                         overlap-add into the output.
 // The adjoint of analysis uses the synthesis kernels with g_k and h_0.
+//
+// Every thread owns at most E values of a work item. Global loads are issued
+// for all of a thread's values before any is used (loops unrolled to E), so a
+// work item waits for memory once per phase rather than once per value.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -29,6 +33,10 @@ namespace slicq {
 constexpr int kPassThreads = 256;     // k_fwd_pass1/2, k_inv_passA/B
 constexpr int kAnaThreads = 256;      // k_band_ana
 constexpr int kSynThreads = 512;      // k_band_syn
+constexpr int kPassE = 16;            // values per thread in the slice-FFT passes
+// Largest padded length and coefficient count of one signal: offsets inside a
+// signal are 32-bit.
+constexpr int64_t kMaxSignalElems = 0x7fffffffLL;
 
 template <class T>
 struct KArgs {
@@ -36,27 +44,66 @@ struct KArgs {
   const T* h0;            // analysis slice window (2N)
   const T* hsyn;          // synthesis slice window: h~_0 (synthesis) or h_0 (adjoint)
   const T* g;             // analysis band windows
-  const T* gsyn;          // synthesis band windows: g~_k (synthesis) or g_k (adjoint)
   const BandDev* bands;
   const AnaGroupDev* ana;
   const SynGroupDev* syn;
   const SynRunDev* runs;
-  const int32_t* bin_k0;
-  const int32_t* bin_nk;
+  const int32_t* ent_off; // frequency overlap-add program
+  const int2* ent_pos;
+  const T* ent_w;         // its weights: dual windows (synthesis) or analysis windows (adjoint)
   int32_t N, Mt, K, n_ana;
   int32_t n_syn, N1, N2, logN1;
   int32_t logN2, C, logC, P;
   int32_t logP, zero_ola;   // zero_ola: band_syn zeroes the output overlaps
+  int32_t slice_major, cps; // coefficient layout (see coef_index), coefficients per slice
   int64_t ws1, ws2;       // complex values per slice in the two workspace regions
   T scale;                // (2N)^{-1/2}
-  T inner_w;              // weight of bands 1..K in the frequency overlap-add
 };
 
+// Element index of coefficient n of band k (packing offset off_k, M_k values)
+// of the task's slice: band-major S off_k + m M_k + n, or slice-major
+// m sum_k M_k + off_k + n; both relative to the signal's coef_base.
 template <class T>
-__device__ __forceinline__ T load_sample(const T* __restrict__ x, const SliceTask& tk, int64_t j) {
-  int64_t idx = tk.x_start + j;
-  if (idx >= tk.x_period) idx -= tk.x_period;
-  return idx < tk.x_valid ? x[tk.x_base + idx] : T(0);
+__device__ __forceinline__ int coef_index(const KArgs<T>& a, const SliceTask& tk, int off, int M, int n) {
+  return a.slice_major ? tk.m * a.cps + off + n : tk.S * off + tk.m * M + n;
+}
+
+// Byte offset, 16-byte aligned, just past `values` padded complex values in LDS.
+template <class T>
+__host__ __device__ constexpr size_t lds_tail_offset(int values) {
+  return ((size_t)padded(values) * 2 * sizeof(T) + 15) & ~(size_t)15;
+}
+
+// A slice's view of its signal (or ring): xs = x + x_base, sample j of the
+// slice at (start + j) mod period, zero at and beyond `valid`. Offsets within
+// one signal are 32-bit (the C ABI rejects longer signals).
+struct SliceIn {
+  int start, period, valid, even;
+};
+
+__device__ __forceinline__ SliceIn slice_in(const SliceTask& tk) {
+  return {(int)tk.x_start, (int)tk.x_period, (int)tk.x_valid,
+          ((tk.x_base | tk.x_start | tk.x_period) & 1) == 0};
+}
+
+template <class T>
+__device__ __forceinline__ T load_sample(const T* __restrict__ xs, const SliceIn& si, int j) {
+  int idx = si.start + j;
+  if (idx >= si.period) idx -= si.period;
+  return idx < si.valid ? xs[idx] : T(0);
+}
+
+// Samples j and j + 1 (j even) of the slice as one complex value. With an even
+// base, start and period the pair is contiguous and aligned: one vector load.
+template <class T>
+__device__ __forceinline__ C2<T> load_sample_pair(const T* __restrict__ xs, const SliceIn& si, int j) {
+  if (si.even) {
+    int idx = si.start + j;
+    if (idx >= si.period) idx -= si.period;
+    if (idx + 1 < si.valid) return *reinterpret_cast<const C2<T>*>(xs + idx);
+    return {idx < si.valid ? xs[idx] : T(0), T(0)};
+  }
+  return {load_sample(xs, si, j), load_sample(xs, si, j + 1)};
 }
 
 // ---------------------------------------------------------------------------
@@ -65,8 +112,8 @@ __device__ __forceinline__ T load_sample(const T* __restrict__ x, const SliceTas
 // C columns n1 in [cb C, cb C + C), transforms each over n2 (length N2),
 // applies e^{-2 pi i n1 k2 / N} and stores W1[k2 N1 + n1].
 template <class T>
-__global__ void __launch_bounds__(256) k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks,
-                                                    const T* __restrict__ x, C2<T>* __restrict__ W1) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict__ x, C2<T>* __restrict__ W1) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int nCB = a.N1 >> a.logC;
@@ -77,25 +124,49 @@ __global__ void __launch_bounds__(256) k_fwd_pass1(KArgs<T> a, const SliceTask* 
   const int total = a.C * a.N2;
   const int jlo = (a.N - a.Mt) / 2 + 1;              // first non-zero sample of h_0
   const int jhi = a.N + (a.N + a.Mt) / 2 - 1;        // last non-zero sample of h_0
-  for (int e = tid; e < total; e += nthr) {
-    const int c = e & (a.C - 1), n2 = e >> a.logC;
-    const int n = cb * a.C + c + a.N1 * n2;
-    const int j = 2 * n;
-    T re = 0, im = 0;
-    if (j + 1 >= jlo && j <= jhi) {
-      re = load_sample(x, tk, j) * a.h0[j];
-      im = load_sample(x, tk, j + 1) * a.h0[j + 1];
+  const T* __restrict__ xs = x + tk.x_base;
+  const SliceIn si = slice_in(tk);
+  C2<T> v[kPassE];
+  // two batches of loads keep the register budget of three waves per SIMD
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    C2<T> s2[kPassE / 2], h2[kPassE / 2];
+#pragma unroll
+    for (int q = 0; q < kPassE / 2; ++q) {
+      const int e = tid + (h * kPassE / 2 + q) * nthr;
+      s2[q] = h2[q] = {T(0), T(0)};
+      if (e < total) {
+        const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
+        if (j + 1 >= jlo && j <= jhi) {
+          s2[q] = load_sample_pair(xs, si, j);
+          h2[q] = *reinterpret_cast<const C2<T>*>(a.h0 + j);
+        }
+      }
     }
-    buf[pidx(e)] = {re, im};
+#pragma unroll
+    for (int q = 0; q < kPassE / 2; ++q) {
+      const int e = tid + (h * kPassE / 2 + q) * nthr;
+      if (e < total) buf[pidx(e)] = {s2[q].x * h2[q].x, s2[q].y * h2[q].y};
+    }
   }
   __syncthreads();
   lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, a.tw, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
-  for (int e = tid; e < total; e += nthr) {
-    const int c = e & (a.C - 1), k2 = e >> a.logC;
-    const int n1 = cb * a.C + c;
-    C2<T> v = cmul(buf[pidx(e)], twiddle<T, -1>(a.tw, a.N, (n1 * k2) & (a.N - 1)));
-    out[(int64_t)k2 * a.N1 + n1] = v;
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) {
+      const int n1 = cb * a.C + (e & (a.C - 1)), k2 = e >> a.logC;
+      v[i] = twiddle<T, -1>(a.tw, a.N, (n1 * k2) & (a.N - 1));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) {
+      const int n1 = cb * a.C + (e & (a.C - 1)), k2 = e >> a.logC;
+      out[k2 * a.N1 + n1] = cmul(buf[pidx(e)], v[i]);
+    }
   }
 }
 
@@ -107,6 +178,37 @@ __device__ __forceinline__ int pass2_row(int rb, int s, int P, int N2) {
   const int i = s - P;
   if (rb == 0 && i == 0) return N2 / 2;
   return N2 - (rb * P + i);
+}
+
+// The pair (k, N - k) of packed-spectrum bins a pass-2 unit t handles, and
+// where the two values sit in LDS (sequence-interleaved rows). Row 0 pairs k1
+// with N1 - k1 (k1 < N1/2; unit k1 = 0 also yields bin N/2 at la2); row N2/2
+// pairs k1 with N1 - 1 - k1.
+struct PairIdx {
+  int k, la, lb, la2;
+};
+
+__device__ __forceinline__ PairIdx pass2_pair(int t, int rb, int P, int logP, int N1, int N2, int logTwoP) {
+  const int i = t & (P - 1), k1 = t >> logP;
+  const int row = rb * P + i;
+  PairIdx q;
+  q.la2 = -1;
+  if (row != 0) {
+    q.k = N2 * k1 + row;
+    q.la = (k1 << logTwoP) + i;
+    q.lb = ((N1 - 1 - k1) << logTwoP) + P + i;
+  } else if (k1 < N1 / 2) {
+    q.k = N2 * k1;
+    q.la = k1 << logTwoP;
+    q.lb = ((N1 - k1) & (N1 - 1)) << logTwoP;
+    if (k1 == 0) q.la2 = (N1 / 2) << logTwoP;
+  } else {
+    const int kk = k1 - N1 / 2;
+    q.k = N2 * kk + N2 / 2;
+    q.la = (kk << logTwoP) + P;
+    q.lb = ((N1 - 1 - kk) << logTwoP) + P;
+  }
+  return q;
 }
 
 // The unitary real spectrum from the packed FFT: with a = Zc[k], b = Zc[N-k],
@@ -126,57 +228,56 @@ __device__ __forceinline__ void real_split(C2<T> za, C2<T> zb, C2<T> w, T s, C2<
 // (length N1), giving Zc[N2 k1 + k2], and splits pairs (k, N - k) into the
 // real spectrum X[0..N] of the slice (W2).
 template <class T>
-__global__ void __launch_bounds__(256) k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1,
-                                                    C2<T>* __restrict__ W2) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int nRB = (a.N2 / 2) >> a.logP;
   const int task = blockIdx.x / nRB, rb = blockIdx.x - task * nRB;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int P = a.P, twoP = 2 * a.P, logTwoP = a.logP + 1;
+  const int total = twoP * a.N1;
   const C2<T>* in = W1 + (int64_t)task * a.ws1;
-  for (int e = tid; e < twoP * a.N1; e += nthr) {
-    const int s = e >> a.logN1, n1 = e & (a.N1 - 1);
-    const int row = pass2_row(rb, s, P, a.N2);
-    buf[pidx((n1 << logTwoP) + s)] = in[(int64_t)row * a.N1 + n1];
+  C2<T> v[kPassE];
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) v[i] = in[pass2_row(rb, e >> a.logN1, P, a.N2) * a.N1 + (e & (a.N1 - 1))];
+  }
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[pidx(((e & (a.N1 - 1)) << logTwoP) + (e >> a.logN1))] = v[i];
   }
   __syncthreads();
   lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, a.tw, tid, nthr);
   C2<T>* X = W2 + (int64_t)task * a.ws2;
-  const int N = a.N, N1 = a.N1, N2 = a.N2;
-  for (int t = tid; t < P * N1; t += nthr) {
-    const int i = t & (P - 1), k1 = t >> a.logP;
-    const int row = rb * P + i;
-    C2<T> xk, xnk;
-    if (row != 0) {
-      const int k = N2 * k1 + row;
-      const C2<T> za = buf[pidx((k1 << logTwoP) + i)];
-      const C2<T> zb = buf[pidx(((N1 - 1 - k1) << logTwoP) + P + i)];
-      real_split(za, zb, twiddle<T, -1>(a.tw, 2 * N, k), a.scale, xk, xnk);
-      X[k] = xk;
-      X[N - k] = xnk;
-    } else if (k1 < N1 / 2) {
-      // row 0: pairs (k1, N1 - k1); k1 = 0 gives X[0], X[N] and also X[N/2]
-      const int k = N2 * k1;
-      const C2<T> za = buf[pidx((k1 << logTwoP))];
-      const C2<T> zb = buf[pidx((((N1 - k1) & (N1 - 1)) << logTwoP))];
-      real_split(za, zb, twiddle<T, -1>(a.tw, 2 * N, k), a.scale, xk, xnk);
-      X[k] = xk;
-      X[N - k] = xnk;
-      if (k1 == 0) {
-        const C2<T> zh = buf[pidx(((N1 / 2) << logTwoP))];
-        real_split(zh, zh, twiddle<T, -1>(a.tw, 2 * N, N / 2), a.scale, xk, xnk);
+  const int N = a.N, units = P * a.N1;
+  constexpr int U = kPassE / 2;
+  C2<T> w[U], w2 = {T(0), T(0)};
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int t = tid + i * nthr;
+    if (t < units) {
+      const PairIdx q = pass2_pair(t, rb, P, a.logP, a.N1, a.N2, logTwoP);
+      w[i] = twiddle<T, -1>(a.tw, 2 * N, q.k);
+      if (q.la2 >= 0) w2 = twiddle<T, -1>(a.tw, 2 * N, N / 2);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int t = tid + i * nthr;
+    if (t < units) {
+      const PairIdx q = pass2_pair(t, rb, P, a.logP, a.N1, a.N2, logTwoP);
+      C2<T> xk, xnk;
+      real_split(buf[pidx(q.la)], buf[pidx(q.lb)], w[i], a.scale, xk, xnk);
+      X[q.k] = xk;
+      X[N - q.k] = xnk;
+      if (q.la2 >= 0) {
+        const C2<T> zh = buf[pidx(q.la2)];
+        real_split(zh, zh, w2, a.scale, xk, xnk);
         X[N / 2] = xk;
       }
-    } else {
-      // row N2/2 (sequence P): pairs (kk, N1 - 1 - kk)
-      const int kk = k1 - N1 / 2;
-      const int k = N2 * kk + N2 / 2;
-      const C2<T> za = buf[pidx((kk << logTwoP) + P)];
-      const C2<T> zb = buf[pidx(((N1 - 1 - kk) << logTwoP) + P)];
-      real_split(za, zb, twiddle<T, -1>(a.tw, 2 * N, k), a.scale, xk, xnk);
-      X[k] = xk;
-      X[N - k] = xnk;
     }
   }
 }
@@ -193,8 +294,8 @@ __device__ __forceinline__ C2<T> spec_at(const C2<T>* __restrict__ X, int j, int
 // holds X[j] g_k[j] for the bin j of J_k with j = r (mod M_k), or 0; the
 // inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff).
 template <class T, int E>
-__global__ void __launch_bounds__(256) k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks,
-                                                   const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int task = blockIdx.x / a.n_ana, gi = blockIdx.x - task * a.n_ana;
@@ -202,35 +303,49 @@ __global__ void __launch_bounds__(256) k_band_ana(KArgs<T> a, const SliceTask* _
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const C2<T>* X = W2 + (int64_t)task * a.ws2;
   const int total = G.cnt << G.logM, mask = G.M - 1;
-  for (int e = tid; e < total; e += nthr) {
-    const int k = G.k0 + (e >> G.logM), r = e & mask;
-    const BandDev B = a.bands[k];
-    const int t = (r - B.start) & mask;
-    C2<T> v = {0, 0};
-    if (t < B.len) v = cscale(spec_at(X, B.start + t, a.N), a.g[B.goff + t]);
-    buf[pidx(e)] = v;
+  BandDev* bd = reinterpret_cast<BandDev*>(smem + lds_tail_offset<T>(total));
+  for (int b = tid; b < G.cnt; b += nthr) bd[b] = a.bands[G.k0 + b];
+  __syncthreads();
+  const C2<T>* X = W2 + (int64_t)task * a.ws2;
+  C2<T> v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = tid + i * nthr;
+    v[i] = {T(0), T(0)};
+    if (e < total) {
+      const BandDev B = bd[e >> G.logM];
+      const int t = ((e & mask) - B.start) & mask;
+      if (t < B.len) v[i] = cscale(spec_at(X, B.start + t, a.N), a.g[B.goff + t]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[pidx(e)] = v[i];
   }
   __syncthreads();
   lds_fft<T, 1, CONTIG, E>(buf, 0, G.logM, G.cnt, 0, a.tw, tid, nthr);
-  const int64_t S = tk.S;
-  for (int e = tid; e < total; e += nthr) {
-    const int k = G.k0 + (e >> G.logM), n = e & mask;
-    const int64_t dst = tk.coef_base + S * a.bands[k].off + (int64_t)tk.m * G.M + n;
-    coef[dst] = buf[pidx(e)];
+  C2<T>* __restrict__ cs = coef + tk.coef_base;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) {
+      cs[coef_index(a, tk, bd[e >> G.logM].off, G.M, e & mask)] = buf[pidx(e)];
+    }
   }
 }
 
 // Band synthesis: owned bins [lo, hi) of the half spectrum of one slice.
-// Every band ke..kb is transformed (DFT_{M_k}), then each owned bin j sums
-// w_k[j] C_k[j mod M_k] over the bands covering it, in increasing k: weight
-// inner_w for bands 1..K and, for the self-mirrored DC and Nyquist bands,
-// (w[j]/2)(C[j mod M] + conj C[-j mod M]) (real part of the full synthesis).
+// Every band ke..kb is transformed (DFT_{M_k}, runs of equal M_k), then each
+// owned bin runs its overlap-add program: the sum over the bands covering it,
+// in increasing k, of weight * C_k[j mod M_k] (for the self-mirrored DC and
+// Nyquist bands weight * (C[j mod M] + conj C[-j mod M]), the real part of the
+// full synthesis).
 template <class T, int E>
-__global__ void __launch_bounds__(512) k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks,
-                                                   const C2<T>* __restrict__ coef, C2<T>* __restrict__ W2,
-                                                   T* __restrict__ y) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ coef, C2<T>* __restrict__ W2,
+           T* __restrict__ y) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int task = blockIdx.x / a.n_syn, gi = blockIdx.x - task * a.n_syn;
@@ -238,17 +353,10 @@ __global__ void __launch_bounds__(512) k_band_syn(KArgs<T> a, const SliceTask* _
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int64_t S = tk.S;
-  const int base_off = a.bands[G.ke].off;
-  for (int ri = 0; ri < G.nrun; ++ri) {
-    const SynRunDev R = a.runs[G.run0 + ri];
-    const int tot = R.cnt << R.logM;
-    for (int e = tid; e < tot; e += nthr) {
-      const int k = R.k0 + (e >> R.logM), n = e & (R.M - 1);
-      const int64_t src = tk.coef_base + S * a.bands[k].off + (int64_t)tk.m * R.M + n;
-      buf[pidx(R.lds_off + e)] = coef[src];
-    }
-  }
+  const int nb = G.kb - G.ke + 1;
+  const C2<T>* __restrict__ cs = coef + tk.coef_base;
+  int* boff = reinterpret_cast<int*>(smem + lds_tail_offset<T>(G.total));   // off_k of bands ke..kb
+  for (int b = tid; b < nb; b += nthr) boff[b] = a.bands[G.ke + b].off;
   if (gi == 0 && a.zero_ola && (tk.flags & 1)) {
     // zero the right-hand overlap of this slice in the output, which the
     // inverse pass then accumulates into from this slice and the next
@@ -262,26 +370,65 @@ __global__ void __launch_bounds__(512) k_band_syn(KArgs<T> a, const SliceTask* _
   __syncthreads();
   for (int ri = 0; ri < G.nrun; ++ri) {
     const SynRunDev R = a.runs[G.run0 + ri];
+    const int tot = R.cnt << R.logM;
+    C2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * nthr;
+      if (e < tot) {
+        const int b = R.k0 - G.ke + (e >> R.logM);
+        v[i] = cs[coef_index(a, tk, boff[b], R.M, e & (R.M - 1))];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * nthr;
+      if (e < tot) buf[pidx(R.lds_off + e)] = v[i];
+    }
+  }
+  __syncthreads();
+  for (int ri = 0; ri < G.nrun; ++ri) {
+    const SynRunDev R = a.runs[G.run0 + ri];
     lds_fft<T, -1, CONTIG, E>(buf, R.lds_off, R.logM, R.cnt, 0, a.tw, tid, nthr);
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;
-  const int K1 = a.K + 1;
-  for (int j = G.lo + tid; j < G.hi; j += nthr) {
-    const int k0 = a.bin_k0[j], nk = a.bin_nk[j];
-    C2<T> acc = {0, 0};
-    for (int k = k0; k < k0 + nk; ++k) {
-      const BandDev B = a.bands[k];
-      const int lpos = B.off - base_off;
-      const T w = a.gsyn[B.goff + (j - B.start)];
-      const C2<T> c1 = buf[pidx(lpos + (j & (B.M - 1)))];
-      if (k == 0 || k == K1) {
-        const C2<T> c2 = buf[pidx(lpos + ((-j) & (B.M - 1)))];
-        acc = cadd(acc, cscale(cadd(c1, cconj(c2)), T(0.5) * w));
-      } else {
-        acc = cadd(acc, cscale(c1, a.inner_w * w));
+  for (int j0 = G.lo; j0 < G.hi; j0 += 4 * nthr) {
+    int e0[4], e1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + tid + q * nthr;
+      e0[q] = e1[q] = 0;
+      if (j < G.hi) {
+        e0[q] = a.ent_off[j];
+        e1[q] = a.ent_off[j + 1];
       }
     }
-    Z[j] = acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + tid + q * nthr;
+      if (j >= G.hi) continue;
+      C2<T> acc = {T(0), T(0)};
+      for (int e = e0[q]; e < e1[q]; e += 4) {
+        int2 ps[4];
+        T ws[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (e + u < e1[q]) {
+            ps[u] = a.ent_pos[e + u];
+            ws[u] = a.ent_w[e + u];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (e + u < e1[q]) {
+            C2<T> c = buf[pidx(ps[u].x)];
+            if (ps[u].y >= 0) c = cadd(c, cconj(buf[pidx(ps[u].y)]));
+            acc = cadd(acc, cscale(c, ws[u]));
+          }
+        }
+      }
+      Z[j] = acc;
+    }
   }
 }
 
@@ -299,8 +446,8 @@ __device__ __forceinline__ void herm_pack(C2<T> a, C2<T> b, C2<T> u, C2<T>& zk, 
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2,
-                                                    C2<T>* __restrict__ W1) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int nRB = (a.N2 / 2) >> a.logP;
@@ -309,40 +456,59 @@ __global__ void __launch_bounds__(256) k_inv_passA(KArgs<T> a, const C2<T>* __re
   const int P = a.P, twoP = 2 * a.P, logTwoP = a.logP + 1;
   const int N = a.N, N1 = a.N1, N2 = a.N2;
   const C2<T>* Z = W2 + (int64_t)task * a.ws2;
-  for (int t = tid; t < P * N1; t += nthr) {
-    const int i = t & (P - 1), k1 = t >> a.logP;
-    const int row = rb * P + i;
-    C2<T> zk, znk;
-    if (row != 0) {
-      const int k = N2 * k1 + row;
-      herm_pack(Z[k], Z[N - k], twiddle<T, 1>(a.tw, 2 * N, k), zk, znk);
-      buf[pidx((k1 << logTwoP) + i)] = zk;
-      buf[pidx(((N1 - 1 - k1) << logTwoP) + P + i)] = znk;
-    } else if (k1 < N1 / 2) {
-      const int k = N2 * k1;
-      herm_pack(Z[k], Z[N - k], twiddle<T, 1>(a.tw, 2 * N, k), zk, znk);
-      buf[pidx(k1 << logTwoP)] = zk;
-      if (k1 != 0) buf[pidx(((N1 - k1) & (N1 - 1)) << logTwoP)] = znk;
-      if (k1 == 0) {
-        herm_pack(Z[N / 2], Z[N / 2], twiddle<T, 1>(a.tw, 2 * N, N / 2), zk, znk);
-        buf[pidx((N1 / 2) << logTwoP)] = zk;
+  const int units = P * N1;
+  constexpr int U = kPassE / 2;
+  C2<T> za[U], zb[U], w[U], zh = {T(0), T(0)}, wh = {T(0), T(0)};
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int t = tid + i * nthr;
+    if (t < units) {
+      const PairIdx q = pass2_pair(t, rb, P, a.logP, N1, N2, logTwoP);
+      za[i] = Z[q.k];
+      zb[i] = Z[N - q.k];
+      w[i] = twiddle<T, 1>(a.tw, 2 * N, q.k);
+      if (q.la2 >= 0) {
+        zh = Z[N / 2];
+        wh = twiddle<T, 1>(a.tw, 2 * N, N / 2);
       }
-    } else {
-      const int kk = k1 - N1 / 2;
-      const int k = N2 * kk + N2 / 2;
-      herm_pack(Z[k], Z[N - k], twiddle<T, 1>(a.tw, 2 * N, k), zk, znk);
-      buf[pidx((kk << logTwoP) + P)] = zk;
-      buf[pidx(((N1 - 1 - kk) << logTwoP) + P)] = znk;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int t = tid + i * nthr;
+    if (t < units) {
+      const PairIdx q = pass2_pair(t, rb, P, a.logP, N1, N2, logTwoP);
+      C2<T> zk, znk;
+      herm_pack(za[i], zb[i], w[i], zk, znk);
+      buf[pidx(q.la)] = zk;
+      if (q.k != 0) buf[pidx(q.lb)] = znk;     // bin 0 has no partner in [0, N)
+      if (q.la2 >= 0) {
+        herm_pack(zh, zh, wh, zk, znk);
+        buf[pidx(q.la2)] = zk;
+      }
     }
   }
   __syncthreads();
   lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, a.tw, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
-  for (int e = tid; e < twoP * N1; e += nthr) {
-    const int s = e >> a.logN1, n1 = e & (N1 - 1);
-    const int row = pass2_row(rb, s, P, N2);
-    const C2<T> v = cmul(buf[pidx((n1 << logTwoP) + s)], twiddle<T, 1>(a.tw, N, (n1 * row) & (N - 1)));
-    out[(int64_t)row * N1 + n1] = v;
+  const int total = twoP * N1;
+  C2<T> tw[kPassE];
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) {
+      const int row = pass2_row(rb, e >> a.logN1, P, N2);
+      tw[i] = twiddle<T, 1>(a.tw, N, ((e & (N1 - 1)) * row) & (N - 1));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) {
+      const int s = e >> a.logN1, n1 = e & (N1 - 1);
+      const int row = pass2_row(rb, s, P, N2);
+      out[row * N1 + n1] = cmul(buf[pidx((n1 << logTwoP) + s)], tw[i]);
+    }
   }
 }
 
@@ -350,24 +516,24 @@ __global__ void __launch_bounds__(256) k_inv_passA(KArgs<T> a, const C2<T>* __re
 // only this slice contributes, atomic adds on the M-1 samples shared with a
 // neighbour (exactly two contributions into a zeroed sample: order-free).
 template <class T>
-__device__ __forceinline__ void ola_store(T* __restrict__ y, const SliceTask& tk, int j, T v, int N, int Mt) {
+__device__ __forceinline__ void ola_store(T* __restrict__ ys, int ystart, int yperiod, int yvalid, int j, T v,
+                                          int N, int Mt) {
   int dj = j - N;
   if (dj < 0) dj = -dj;
   if (2 * dj >= N + Mt) return;
-  int64_t idx = tk.y_start + j;
-  if (idx >= tk.y_period) idx -= tk.y_period;
-  if (idx >= tk.y_valid) return;
-  T* p = y + tk.y_base + idx;
-  if (2 * dj <= N - Mt) *p = v;
-  else unsafeAtomicAdd(p, v);
+  int idx = ystart + j;
+  if (idx >= yperiod) idx -= yperiod;
+  if (idx >= yvalid) return;
+  if (2 * dj <= N - Mt) ys[idx] = v;
+  else unsafeAtomicAdd(ys + idx, v);
 }
 
 // Inverse pass B: columns n1 in [cb C, cb C + C): transform over k2 (length
 // N2, e^+), giving z[n1 + N1 n2] = y[2n] + i y[2n+1]; scale, multiply by the
 // synthesis slice window and overlap-add (Algorithm 4).
 template <class T>
-__global__ void __launch_bounds__(256) k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks,
-                                                    const C2<T>* __restrict__ W1, T* __restrict__ y) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W1, T* __restrict__ y) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int nCB = a.N1 >> a.logC;
@@ -377,19 +543,39 @@ __global__ void __launch_bounds__(256) k_inv_passB(KArgs<T> a, const SliceTask* 
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = a.C * a.N2;
   const C2<T>* in = W1 + (int64_t)task * a.ws1;
-  for (int e = tid; e < total; e += nthr) {
-    const int c = e & (a.C - 1), k2 = e >> a.logC;
-    buf[pidx(e)] = in[(int64_t)k2 * a.N1 + cb * a.C + c];
+  C2<T> v[kPassE];
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) v[i] = in[(e >> a.logC) * a.N1 + cb * a.C + (e & (a.C - 1))];
+  }
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[pidx(e)] = v[i];
   }
   __syncthreads();
   lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, a.tw, tid, nthr);
-  for (int e = tid; e < total; e += nthr) {
-    const int c = e & (a.C - 1), n2 = e >> a.logC;
-    const int n = cb * a.C + c + a.N1 * n2;
-    const C2<T> v = buf[pidx(e)];
-    const int j = 2 * n;
-    ola_store(y, tk, j, v.x * a.scale * a.hsyn[j], a.N, a.Mt);
-    ola_store(y, tk, j + 1, v.y * a.scale * a.hsyn[j + 1], a.N, a.Mt);
+  T* __restrict__ ys = y + tk.y_base;
+  const int ys0 = (int)tk.y_start, yper = (int)tk.y_period, yval = (int)tk.y_valid;
+  C2<T> h[kPassE];
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) {
+      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
+      h[i] = *reinterpret_cast<const C2<T>*>(a.hsyn + j);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) {
+      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
+      const C2<T> z = buf[pidx(e)];
+      ola_store(ys, ys0, yper, yval, j, z.x * a.scale * h[i].x, a.N, a.Mt);
+      ola_store(ys, ys0, yper, yval, j + 1, z.y * a.scale * h[i].y, a.N, a.Mt);
+    }
   }
 }
 
@@ -418,9 +604,9 @@ __global__ void __launch_bounds__(256) k_tasks_plain(SliceTask* __restrict__ tas
   if (i >= count) return;
   const int64_t m = m0 + i;
   const int64_t L = S * N;
-  SliceTask t;
+  SliceTask t{};
   t.x_base = 0;
-  t.x_start = ((m - 1) * N + L) % L;
+  t.x_start = m == 0 ? L - N : (m - 1) * N;
   t.x_period = L;
   t.x_valid = T;
   t.y_base = 0;
@@ -431,17 +617,16 @@ __global__ void __launch_bounds__(256) k_tasks_plain(SliceTask* __restrict__ tas
   t.m = (int32_t)m;
   t.S = (int32_t)S;
   t.flags = 1;
-  t.pad_ = 0;
-  t.pad2_ = 0;
   tasks[i] = t;
 }
 
 // Slices of a ragged batch: signal b holds samples x_off[b] .. x_off[b+1]-1
-// and its coefficients start at coef_off[b]. One block of 1024 threads first
-// marks every task slot unused, then scans the slice counts
-// S_b = 2 ceil(T_b / 2N) and writes the tasks of every signal in order.
-// Signals whose samples or coefficients fall outside the buffers are skipped
-// and flagged in status[0]; status[1] receives the number of slices.
+// and its coefficients start at coef_off[b]. One block of 1024 threads scans
+// the slice counts S_b = 2 ceil(T_b / 2N) of 1024 signals at a time and then
+// fills that chunk's tasks in parallel (each thread finds its signal by binary
+// search in the scan). Signals whose samples or coefficients fall outside the
+// buffers get unused task slots and set status[0]; slots past the last task
+// are marked unused; status[1] receives the number of slices.
 __global__ void __launch_bounds__(1024) k_tasks_batched(SliceTask* __restrict__ tasks,
                                                         const int64_t* __restrict__ x_off,
                                                         const int64_t* __restrict__ coef_off,
@@ -454,10 +639,6 @@ __global__ void __launch_bounds__(1024) k_tasks_batched(SliceTask* __restrict__ 
   int64_t& carry = scan[1024];
   int32_t& bad = *reinterpret_cast<int32_t*>(&scan[1025]);
   const int tid = threadIdx.x;
-  for (int64_t i = tid; i < max_tasks; i += 1024) {
-    SliceTask t{};
-    tasks[i] = t;
-  }
   if (tid == 0) {
     carry = 0;
     bad = 0;
@@ -465,9 +646,9 @@ __global__ void __launch_bounds__(1024) k_tasks_batched(SliceTask* __restrict__ 
   __syncthreads();
   for (int32_t b0 = 0; b0 < nsig; b0 += 1024) {
     const int32_t b = b0 + tid;
-    int64_t Tb = 0, Sb = 0;
+    int64_t Sb = 0;
     if (b < nsig) {
-      Tb = x_off[b + 1] - x_off[b];
+      int64_t Tb = x_off[b + 1] - x_off[b];
       if (Tb < 0) Tb = 0;
       Sb = 2 * ((Tb + 2 * N - 1) / (2 * N));
     }
@@ -479,35 +660,53 @@ __global__ void __launch_bounds__(1024) k_tasks_batched(SliceTask* __restrict__ 
       scan[tid] += v;
       __syncthreads();
     }
-    const int64_t first = carry + scan[tid] - Sb;
-    if (b < nsig && Sb > 0) {
-      const bool ok = x_off[b] >= 0 && x_off[b] + Tb <= x_len && coef_off[b] >= 0 &&
-                      coef_off[b] + Sb * coefs_per_slice <= coef_len && first + Sb <= max_tasks;
-      if (!ok) {
+    const int64_t chunk = scan[1023], base = carry;
+    for (int64_t i = tid; i < chunk; i += 1024) {
+      const int64_t g = base + i;
+      if (g >= max_tasks) {
         bad = 1;
-      } else {
-        const int64_t L = Sb * N;
-        for (int64_t m = 0; m < Sb; ++m) {
-          SliceTask t{};
-          t.x_base = x_off[b];
-          t.x_start = ((m - 1) * N + L) % L;
-          t.x_period = L;
-          t.x_valid = Tb;
-          t.y_base = x_off[b];
-          t.y_start = t.x_start;
-          t.y_period = L;
-          t.y_valid = Tb;
-          t.coef_base = coef_off[b];
-          t.m = (int32_t)m;
-          t.S = (int32_t)Sb;
-          t.flags = 1;
-          tasks[first + m] = t;
-        }
+        break;
       }
+      int lo = 0, hi = 1023;                     // first s with scan[s] > i
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (scan[mid] > i) hi = mid;
+        else lo = mid + 1;
+      }
+      const int32_t sb = b0 + lo;
+      const int64_t m = i - (lo ? scan[lo - 1] : 0);
+      const int64_t Tb = x_off[sb + 1] - x_off[sb];
+      const int64_t S = 2 * ((Tb + 2 * N - 1) / (2 * N));
+      const int64_t L = S * N;
+      const bool ok = x_off[sb] >= 0 && x_off[sb + 1] <= x_len && coef_off[sb] >= 0 &&
+                      coef_off[sb] + S * coefs_per_slice <= coef_len && L <= kMaxSignalElems &&
+                      S * coefs_per_slice <= kMaxSignalElems;
+      SliceTask t{};
+      if (ok) {
+        t.x_base = x_off[sb];
+        t.x_start = m == 0 ? L - N : (m - 1) * N;
+        t.x_period = L;
+        t.x_valid = Tb;
+        t.y_base = x_off[sb];
+        t.y_start = t.x_start;
+        t.y_period = L;
+        t.y_valid = Tb;
+        t.coef_base = coef_off[sb];
+        t.m = (int32_t)m;
+        t.S = (int32_t)S;
+        t.flags = 1;
+      } else {
+        bad = 1;
+      }
+      tasks[g] = t;
     }
     __syncthreads();
-    if (tid == 1023) carry += scan[1023];
+    if (tid == 0) carry = base + chunk;
     __syncthreads();
+  }
+  for (int64_t i = carry + tid; i < max_tasks; i += 1024) {
+    SliceTask t{};
+    tasks[i] = t;
   }
   if (tid == 0) {
     status[0] = bad;

@@ -74,13 +74,13 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
   a.h0 = reinterpret_cast<const T*>(base + L.h0);
   a.hsyn = reinterpret_cast<const T*>(base + (adjoint ? L.h0 : L.hd));
   a.g = reinterpret_cast<const T*>(base + L.g);
-  a.gsyn = reinterpret_cast<const T*>(base + (adjoint ? L.g : L.gd));
   a.bands = reinterpret_cast<const BandDev*>(base + L.bands);
   a.ana = reinterpret_cast<const AnaGroupDev*>(base + L.ana);
   a.syn = reinterpret_cast<const SynGroupDev*>(base + L.syn);
   a.runs = reinterpret_cast<const SynRunDev*>(base + L.runs);
-  a.bin_k0 = reinterpret_cast<const int32_t*>(base + L.bin_k0);
-  a.bin_nk = reinterpret_cast<const int32_t*>(base + L.bin_nk);
+  a.ent_off = reinterpret_cast<const int32_t*>(base + L.ent_off);
+  a.ent_pos = reinterpret_cast<const int2*>(base + L.ent_pos);
+  a.ent_w = reinterpret_cast<const T*>(base + (adjoint ? L.ent_wadj : L.ent_wsyn));
   a.N = (int32_t)p.N;
   a.Mt = (int32_t)p.Mt;
   a.K = p.K;
@@ -97,7 +97,8 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
   a.ws1 = ws1_len(p);
   a.ws2 = ws2_len(p);
   a.scale = (T)(1.0 / std::sqrt((double)p.two_n));
-  a.inner_w = adjoint ? T(0.5) : T(1.0);
+  a.slice_major = p.prm.coef_layout;
+  a.cps = (int32_t)p.coefs_per_slice;
   return a;
 }
 
@@ -123,11 +124,11 @@ Geometry<T> geometry(const Plan& p) {
   g.ga = (int)p.ana.size();
   g.Ea = p.ana_cap > 16 * kAnaThreads ? 32 : 16;
   g.ba = threads_for(p.ana_cap, g.Ea);
-  g.sa = padded(p.ana_cap) * cb;
+  g.sa = lds_tail_offset<T>(p.ana_cap) + 256 * sizeof(BandDev);
   g.gs = (int)p.syn.size();
   g.Es = p.syn_cap > 16 * 512 ? 32 : 16;
   g.bs = threads_for(p.syn_cap, g.Es);
-  g.ss = padded(p.syn_cap) * cb;
+  g.ss = lds_tail_offset<T>(p.syn_cap) + (size_t)p.syn_bands * sizeof(int);
   g.ok = g.b1 <= kPassThreads && g.b2 <= kPassThreads && g.ba <= kAnaThreads && g.bs <= kSynThreads &&
          (int64_t)p.C * p.N2 <= 16LL * g.b1 && 2LL * p.P * p.N1 <= 16LL * g.b2 &&
          p.ana_cap <= g.Ea * g.ba && p.syn_cap <= g.Es * g.bs &&

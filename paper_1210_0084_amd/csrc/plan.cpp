@@ -21,6 +21,8 @@ namespace slicq {
 
 namespace {
 
+constexpr int kMaxGroupBands = 256;   // band descriptors one work item stages in LDS
+
 int64_t next_pow2(int64_t n) {
   int64_t p = 1;
   while (p < n) p <<= 1;
@@ -128,8 +130,8 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     err = "transition length M needs 0 < M < N and N - M even";
     return -1;
   }
-  if (!(p.min_win >= 0) || p.dual_kind < 0 || p.dual_kind > 1) {
-    err = "min_win must be >= 0 and dual_kind 0 or 1";
+  if (!(p.min_win >= 0) || p.dual_kind < 0 || p.dual_kind > 1 || p.coef_layout < 0 || p.coef_layout > 1) {
+    err = "min_win must be >= 0, dual_kind and coef_layout 0 or 1";
     return -1;
   }
   if (p.group_cap < 16 || p.group_cap > 4096 || p.lds_cap < p.group_cap || p.lds_cap > 16384 ||
@@ -325,7 +327,9 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     gdv.M = out.bands[k].M;
     gdv.logM = out.bands[k].logM;
     int cnt = 1;
-    while (k + cnt < K + 2 && out.bands[k + cnt].M == gdv.M && (cnt + 1) * gdv.M <= p.group_cap) ++cnt;
+    while (k + cnt < K + 2 && out.bands[k + cnt].M == gdv.M && (cnt + 1) * gdv.M <= p.group_cap &&
+           cnt < kMaxGroupBands)
+      ++cnt;
     gdv.cnt = cnt;
     out.ana.push_back(gdv);
     out.ana_cap = std::max(out.ana_cap, cnt * gdv.M);
@@ -347,9 +351,9 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
       int cnt = 1;
       const int M = out.bands[k].M;
       while (k + cnt < K + 2 && out.bands[k + cnt].M == M && (cnt + 1) * M <= p.group_cap &&
-             extra + (int64_t)(cnt + 1) * M <= p.lds_cap)
+             extra + (int64_t)(cnt + 1) * M <= p.lds_cap && k + cnt - ke < kMaxGroupBands)
         ++cnt;
-      if (extra + (int64_t)cnt * M > p.lds_cap) {
+      if (extra + (int64_t)cnt * M > p.lds_cap || k + cnt - ke > kMaxGroupBands) {
         std::snprintf(msg, sizeof msg, "bins near band %d need more than %d coefficients in one "
                       "synthesis work item; raise lds_cap", k, p.lds_cap);
         err = msg;
@@ -383,9 +387,38 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
       s.nrun = (int32_t)out.runs.size() - s.run0;
       s.total = (int32_t)(out.bands[kb].off + out.bands[kb].M - out.bands[ke].off);
       out.syn_cap = std::max(out.syn_cap, s.total);
+      out.syn_bands = std::max(out.syn_bands, kb - ke + 1);
       out.syn.push_back(s);
     }
   }
+
+  // frequency overlap-add program: for every bin j of [0, N], in increasing k,
+  // the bands covering it with their LDS position inside the owning work item
+  out.ent_off.assign(N + 2, 0);
+  out.ent_pos.clear();
+  out.ent_wsyn.clear();
+  out.ent_wadj.clear();
+  for (const SynGroupDev& G : out.syn) {
+    const int64_t base = out.bands[G.ke].off;
+    for (int64_t j = G.lo; j < G.hi; ++j) {
+      out.ent_off[j] = (int32_t)out.ent_wsyn.size();
+      for (int k = out.bin_k0[j]; k < out.bin_k0[j] + out.bin_nk[j]; ++k) {
+        const BandInfo& b = out.bands[k];
+        if (k < G.ke || k > G.kb) {
+          err = "synthesis work item misses a band covering one of its bins";
+          return -1;
+        }
+        const int64_t lds = b.off - base;
+        const int64_t t = j - b.start;
+        const bool selfmirror = (k == 0 || k == K + 1);
+        out.ent_pos.push_back((int32_t)(lds + (j & (b.M - 1))));
+        out.ent_pos.push_back(selfmirror ? (int32_t)(lds + ((-j) & (b.M - 1))) : -1);
+        out.ent_wsyn.push_back((selfmirror ? 0.5 : 1.0) * out.gd[b.goff + t]);
+        out.ent_wadj.push_back(0.5 * out.g[b.goff + t]);
+      }
+    }
+  }
+  out.ent_off[N + 1] = (int32_t)out.ent_wsyn.size();
   return 0;
 }
 
@@ -443,8 +476,16 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
   lay.ana = append(blob, p.ana.data(), p.ana.size());
   lay.syn = append(blob, p.syn.data(), p.syn.size());
   lay.runs = append(blob, p.runs.data(), p.runs.size());
-  lay.bin_k0 = append(blob, p.bin_k0.data(), p.bin_k0.size());
-  lay.bin_nk = append(blob, p.bin_nk.data(), p.bin_nk.size());
+  lay.ent_off = append(blob, p.ent_off.data(), p.ent_off.size());
+  lay.ent_pos = append(blob, p.ent_pos.data(), p.ent_pos.size());
+  if (dtype == 0) {
+    std::vector<float> ws(p.ent_wsyn.begin(), p.ent_wsyn.end()), wa(p.ent_wadj.begin(), p.ent_wadj.end());
+    lay.ent_wsyn = append(blob, ws.data(), ws.size());
+    lay.ent_wadj = append(blob, wa.data(), wa.size());
+  } else {
+    lay.ent_wsyn = append(blob, p.ent_wsyn.data(), p.ent_wsyn.size());
+    lay.ent_wadj = append(blob, p.ent_wadj.data(), p.ent_wadj.size());
+  }
   blob.resize((blob.size() + 255) & ~size_t(255));
   lay.total = blob.size();
 }

@@ -17,9 +17,10 @@ struct PlanParams {
   int64_t transition = 0;       // M of the Tukey window
   double min_win = 16.0;        // minimal filter length in bins
   int32_t dual_kind = 0;        // 0: canonical dual slice window, 1: indicator of supp h_0
-  int32_t group_cap = 4096;     // coefficients per analysis work item
+  int32_t group_cap = 2048;     // coefficients per band work item (own bands)
   int32_t lds_cap = 9216;       // complex values a synthesis work item may hold
   int32_t pass_cap = 4096;      // complex values per four-step FFT work item
+  int32_t coef_layout = 0;      // 0: band-major, 1: slice-major
 };
 
 struct BandInfo {
@@ -44,6 +45,9 @@ struct Plan {
   std::vector<double> D;                // frame-operator diagonal, 2N bins
   std::vector<double> h0, hd;           // slicing window and dual, index j = t + N
   std::vector<int32_t> bin_k0, bin_nk;  // bands covering each bin of [0, N]
+  std::vector<int32_t> ent_off;         // frequency overlap-add program (see TableLayout)
+  std::vector<int32_t> ent_pos;         // pairs (x, y)
+  std::vector<double> ent_wsyn, ent_wadj;
   int64_t coefs_per_slice = 0;
   int32_t max_M = 0;
 
@@ -52,6 +56,7 @@ struct Plan {
   std::vector<SynGroupDev> syn;
   std::vector<SynRunDev> runs;
   int32_t ana_cap = 0, syn_cap = 0;     // largest work item, complex values
+  int32_t syn_bands = 0;                // most bands in one synthesis work item
   int32_t N1 = 0, N2 = 0, logN1 = 0, logN2 = 0;
   int32_t C = 0, P = 0;                 // columns per pass-1 item, row pairs per pass-2 item
 

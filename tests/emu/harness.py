@@ -35,7 +35,7 @@ def build() -> str:
 
 
 def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,
-        group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0) -> np.ndarray:
+        group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: int = 0) -> np.ndarray:
     """Runs one emulated transform; returns the raw float64 output."""
     exe = build()
     with tempfile.TemporaryDirectory() as td:
@@ -45,7 +45,7 @@ def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,
         args = [exe, op, str(dtype), repr(float(plan["fs"])), repr(float(plan["fmin"])), repr(float(plan["fmax"])),
                 str(plan["bins_per_octave"]), str(plan["slice_len"]), str(plan["transition"]),
                 repr(float(plan.get("min_win", 16.0))), str(plan.get("dual", 0)), str(group_cap), str(lds_cap),
-                str(pass_cap), str(chunk), fin, fout]
+                str(pass_cap), str(chunk), str(layout), fin, fout]
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
         r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=600)
         if r.returncode != 0:

@@ -16,6 +16,10 @@
 #define __launch_bounds__(...)
 #define __shared__
 
+struct int2 {
+  int x, y;
+};
+
 struct dim3 {
   unsigned x, y, z;
   dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}

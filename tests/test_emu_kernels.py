@@ -61,3 +61,20 @@ def test_emu_preset_shapes(kw):
     ref = pack(pl, analyze(pl, x))
     assert rel(H.analyze(kw, x, 0), ref) <= 1e-5
     assert rel(H.synthesize(kw, ref, T, 0), x) <= 1e-5
+
+
+def test_emu_slice_major_layout():
+    # slice-major packing: slice m's coefficients c^m contiguous, band k at m*C + off_k
+    kw = TINY2
+    pl = OraclePlan(**kw)
+    T = 300
+    x = np.random.default_rng(21).standard_normal(T)
+    c = analyze(pl, x)
+    S = num_slices(T, pl.two_n)
+    slice_major = np.concatenate([np.concatenate([ck[m] for ck in c]) for m in range(S)])
+    assert rel(H.analyze(kw, x, 1, layout=1), slice_major) < 1e-12
+    assert rel(H.synthesize(kw, slice_major, T, 1, layout=1), x) < 1e-12
+    xs = [np.random.default_rng(i).standard_normal(n) for i, n in enumerate([100, 0, 257])]
+    ref = np.concatenate([np.concatenate([np.concatenate([ck[m] for ck in analyze(pl, v)])
+                                          for m in range(num_slices(len(v), pl.two_n))]) for v in xs if len(v)])
+    assert rel(H.analyze_batched(kw, xs, 1, layout=1), ref) < 1e-12

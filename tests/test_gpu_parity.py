@@ -175,3 +175,21 @@ def test_size_errors(sq, dev):
         plan.analyze(x, out=out)
     with pytest.raises(sq.SlicqError, match="-4"):
         plan.analyze(x, work=torch.empty(64, dtype=torch.uint8, device=dev))
+
+
+@pytest.mark.parametrize("name,T", [("c2", 150000), ("c4", 100000), ("c5", 60000)])
+def test_slice_major_layout(sq, dev, name, T):
+    import torch
+    kw = preset(name)
+    plan = sq.Plan(**kw, layout="slice")
+    opl = OraclePlan(**kw)
+    p = PRESETS[name]
+    x = pink_plus_tones(T, p.fs, 31)
+    ref = pack(opl, analyze(opl, x))
+    c = plan.analyze(torch.tensor(x, dtype=torch.float32, device=dev))
+    y = plan.synthesize(c, T)
+    S = plan.num_slices(T)
+    assert rel(plan.to_band_major(c, S).cpu().numpy(), ref) <= 1e-5
+    assert rel(y.cpu().numpy(), x) <= 1e-5
+    k = plan.nbands // 2
+    assert torch.equal(plan.band(c, k, S), c.view(S, plan.coefs_per_slice)[:, plan.offsets[k]:plan.offsets[k] + plan.M[k]])
