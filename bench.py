@@ -46,6 +46,29 @@ def stage_bytes(plan, n_slices: int, b: int) -> dict:
     return {k: v * n_slices for k, v in per.items()}
 
 
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1210_0084_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str = "c2"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
+    None when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.loads(fh.readline())
+    if rec.get("kernels_sha256") != kernel_sources_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    return int(rec["kernels"][kernel]["traffic_bytes"])
+
+
 def time_stages(plan, n_slices, x, coef, y, reps=20):
     import torch
     out = {}
@@ -164,7 +187,8 @@ def main():
                                "2N=65536, M=8192; analysis+synthesis",
                    "signals": 2, "samples_per_signal": T, "slices": S, "coefs_per_slice": plan.coefs_per_slice},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom), "algorithmic_bytes": sbytes[dom]},
         "path": {"algorithmic_bytes_per_step": path_bytes,
                  "GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1),
                  "frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
