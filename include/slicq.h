@@ -175,6 +175,61 @@ int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dtype, const void* coef, 
                           int32_t nsig, int64_t total_slices, void* work, size_t work_bytes,
                           void* hip_stream);
 
+/* ---- Streaming service (real-time streams, continuously batched) ----------
+ * Each stream is the linear sliCQ of an unbounded signal that is zero before
+ * sample 0: slice m is centred on sample mN (Algorithm 3) and becomes ready
+ * once mN + (N+M)/2 samples have been pushed; its output samples are final
+ * once slice m is done for t <= mN + (N-M)/2 (Algorithm 4 overlap-add), and
+ * equal the input samples (Proposition 3). Each tick processes every ready
+ * slice of every open stream in one launch sequence on the server's own HIP
+ * stream and synchronises with it; pushes, polls, opens and closes from other
+ * threads proceed meanwhile and join the next tick. Per-stream state (input
+ * and output rings of 4N samples) lives in device memory allocated once at
+ * creation; admission is limited by max_streams and hbm_budget_bytes
+ * (0 = no budget). Samples passed to push/poll are host memory of the
+ * server's dtype. A device error fences the server (SLICQ_EHIP on every later
+ * call). */
+typedef struct slicq_stream_server_s* slicq_stream_server;
+
+typedef struct {
+  int64_t ticks, slices, samples_in, samples_out;
+  int64_t admitted, rejected, closed, gap_samples;
+  double latency_p50_s, latency_p99_s, latency_max_s;  /* ready-hop arrival to tick completion */
+  int64_t latency_count;
+  double busy_s;             /* host time spent inside ticks */
+  int32_t slots;             /* streams the budget admits */
+  int32_t pad_;
+  int64_t ring_len;          /* samples per ring (4N) */
+  int64_t bytes_per_stream;  /* device bytes per admitted stream */
+} slicq_stream_stats;
+
+int slicq_stream_server_create(slicq_plan plan, slicq_dtype dtype, int32_t max_streams, int32_t max_batch,
+                               size_t hbm_budget_bytes, slicq_stream_server* out);
+void slicq_stream_server_destroy(slicq_stream_server server);
+/* Admits a stream: *id >= 0, or SLICQ_EBUSY when no slot fits the budget. */
+int slicq_stream_open(slicq_stream_server server, int32_t* id);
+/* Appends n samples; push_gap appends n zeros for a hop that never arrived. */
+int slicq_stream_push(slicq_stream_server server, int32_t id, const void* samples, int64_t n);
+int slicq_stream_push_gap(slicq_stream_server server, int32_t id, int64_t n);
+/* One batch over all streams; *n_slices receives the slices processed. */
+int slicq_stream_tick(slicq_stream_server server, int64_t* n_slices);
+/* Moves up to max final output samples of stream id into out; *n receives the count. */
+int slicq_stream_poll(slicq_stream_server server, int32_t id, void* out, int64_t max, int64_t* n);
+/* Ends a stream (also mid-slice); its slot is cleared before reuse. */
+int slicq_stream_close(slicq_stream_server server, int32_t id);
+/* Coefficients of stream id's most recent slice (slice-major c^m: band k at
+ * off_k, coefs_per_slice complex values of the dtype, host memory of at least
+ * cap values), when the last tick processed it; *m receives the slice index,
+ * or -1 if the last tick did not process this stream. */
+int slicq_stream_coefs(slicq_stream_server server, int32_t id, void* out, int64_t cap, int64_t* m);
+int slicq_stream_stats_get(slicq_stream_server server, slicq_stream_stats* stats);
+int slicq_stream_stats_reset(slicq_stream_server server);
+/* Per-stream checkpoint: counters, queued samples and both rings. With
+ * buf == NULL only *bytes is set. restore() loads a snapshot of the same plan
+ * and dtype into an open stream; outputs then continue bit for bit. */
+int slicq_stream_snapshot(slicq_stream_server server, int32_t id, void* buf, size_t cap, size_t* bytes);
+int slicq_stream_restore(slicq_stream_server server, int32_t id, const void* buf, size_t bytes);
+
 /* Measurement hook: enqueues one kernel of the pipeline of the preceding
  * transform call made with the same plan, dtype, buffers and workspace (which
  * must hold all n_slices slices at once), so that a profiler can time it

@@ -18,7 +18,8 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Plan", "SliCQFunction", "slicq", "library_path", "SlicqError", "load_library"]
+__all__ = ["Plan", "SliCQFunction", "slicq", "library_path", "SlicqError", "SlicqBusy", "StreamServer",
+           "load_library"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libslicq.so")
@@ -29,6 +30,19 @@ F32, F64 = 0, 1
 
 class SlicqError(RuntimeError):
     pass
+
+
+class SlicqBusy(SlicqError):
+    """Admission refused: no stream slot within the server's memory budget."""
+
+
+class _StreamStats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("slices", ctypes.c_int64), ("samples_in", ctypes.c_int64),
+                ("samples_out", ctypes.c_int64), ("admitted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("closed", ctypes.c_int64), ("gap_samples", ctypes.c_int64), ("latency_p50_s", ctypes.c_double),
+                ("latency_p99_s", ctypes.c_double), ("latency_max_s", ctypes.c_double),
+                ("latency_count", ctypes.c_int64), ("busy_s", ctypes.c_double), ("slots", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("ring_len", ctypes.c_int64), ("bytes_per_stream", ctypes.c_int64)]
 
 
 class _Opts(ctypes.Structure):
@@ -77,6 +91,19 @@ def load_library():
         "slicq_synthesize_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_adjoint_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_profile_stage": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, I64, P, P, P, P, SZ, P]),
+        "slicq_stream_server_create": (ctypes.c_int, [P, ctypes.c_int, I32, I32, SZ, ctypes.POINTER(P)]),
+        "slicq_stream_server_destroy": (None, [P]),
+        "slicq_stream_open": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
+        "slicq_stream_push": (ctypes.c_int, [P, I32, P, I64]),
+        "slicq_stream_push_gap": (ctypes.c_int, [P, I32, I64]),
+        "slicq_stream_tick": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+        "slicq_stream_poll": (ctypes.c_int, [P, I32, P, I64, ctypes.POINTER(I64)]),
+        "slicq_stream_close": (ctypes.c_int, [P, I32]),
+        "slicq_stream_coefs": (ctypes.c_int, [P, I32, P, I64, ctypes.POINTER(I64)]),
+        "slicq_stream_stats_get": (ctypes.c_int, [P, ctypes.POINTER(_StreamStats)]),
+        "slicq_stream_stats_reset": (ctypes.c_int, [P]),
+        "slicq_stream_snapshot": (ctypes.c_int, [P, I32, P, SZ, ctypes.POINTER(SZ)]),
+        "slicq_stream_restore": (ctypes.c_int, [P, I32, P, SZ]),
         "slicq_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -90,7 +117,7 @@ def load_library():
 def _check(rc: int):
     if rc != 0:
         msg = load_library().slicq_last_error().decode(errors="replace")
-        raise SlicqError(f"slicq error {rc}: {msg}")
+        raise (SlicqBusy if rc == -5 else SlicqError)(f"slicq error {rc}: {msg}")
 
 
 def _torch():
@@ -358,6 +385,89 @@ class Plan:
                                              ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                              ctypes.c_void_p(w.data_ptr()), wb,
                                              ctypes.c_void_p(_stream_ptr(x.device))))
+
+
+class StreamServer:
+    """Real-time streaming sliCQ (continuous batching; see slicq.h).
+
+    Streams are admitted with ``open()`` (SlicqBusy when the memory budget is
+    full), fed with ``push(id, samples)`` from any thread, processed by
+    ``tick()`` (every ready slice of every stream in one launch sequence) and
+    drained with ``poll(id)``. Samples are host numpy arrays of the dtype.
+    """
+
+    def __init__(self, plan: Plan, dtype: str = "f32", max_streams: int = 512, max_batch: int = 1024,
+                 hbm_budget_bytes: int = 0, device=None):
+        torch = _torch()
+        self.plan = plan
+        self.dt = F32 if dtype == "f32" else F64
+        self.np_dtype = np.float32 if self.dt == F32 else np.float64
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        plan._ensure_tables(self.dt, dev)
+        torch.cuda.synchronize(dev)
+        self._lib = plan._lib
+        h = ctypes.c_void_p()
+        _check(self._lib.slicq_stream_server_create(plan._h, self.dt, int(max_streams), int(max_batch),
+                                                    int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.slicq_stream_server_destroy(h)
+            self._h = None
+
+    def open(self) -> int:
+        i = ctypes.c_int32()
+        _check(self._lib.slicq_stream_open(self._h, ctypes.byref(i)))
+        return i.value
+
+    def push(self, sid: int, samples) -> None:
+        a = np.ascontiguousarray(samples, dtype=self.np_dtype)
+        _check(self._lib.slicq_stream_push(self._h, int(sid), a.ctypes.data, a.size))
+
+    def push_gap(self, sid: int, n: int) -> None:
+        _check(self._lib.slicq_stream_push_gap(self._h, int(sid), int(n)))
+
+    def tick(self) -> int:
+        n = ctypes.c_int64()
+        _check(self._lib.slicq_stream_tick(self._h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, sid: int, max_samples: int = 1 << 22):
+        out = np.empty(int(max_samples), dtype=self.np_dtype)
+        n = ctypes.c_int64()
+        _check(self._lib.slicq_stream_poll(self._h, int(sid), out.ctypes.data, out.size, ctypes.byref(n)))
+        return out[:n.value].copy()
+
+    def close(self, sid: int) -> None:
+        _check(self._lib.slicq_stream_close(self._h, int(sid)))
+
+    def last_coefs(self, sid: int):
+        """(m, c^m) of the stream's most recent slice, or (-1, None)."""
+        ct = np.complex64 if self.dt == F32 else np.complex128
+        out = np.empty(self.plan.coefs_per_slice, dtype=ct)
+        m = ctypes.c_int64()
+        _check(self._lib.slicq_stream_coefs(self._h, int(sid), out.ctypes.data, out.size, ctypes.byref(m)))
+        return (m.value, out) if m.value >= 0 else (-1, None)
+
+    def stats(self) -> dict:
+        st = _StreamStats()
+        _check(self._lib.slicq_stream_stats_get(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in _StreamStats._fields_ if name != "pad_"}
+
+    def reset_stats(self) -> None:
+        _check(self._lib.slicq_stream_stats_reset(self._h))
+
+    def snapshot(self, sid: int) -> bytes:
+        n = ctypes.c_size_t()
+        _check(self._lib.slicq_stream_snapshot(self._h, int(sid), None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self._lib.slicq_stream_snapshot(self._h, int(sid), buf, n.value, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def restore(self, sid: int, blob: bytes) -> None:
+        _check(self._lib.slicq_stream_restore(self._h, int(sid), blob, len(blob)))
 
 
 def _make_function():

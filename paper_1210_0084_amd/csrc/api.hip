@@ -10,6 +10,7 @@
 
 #include "../../include/slicq.h"
 #include "pipeline.hpp"
+#include "stream_server.hpp"
 
 struct slicq_plan_s {
   slicq::Plan p;
@@ -181,9 +182,216 @@ int synth_batched_common(slicq_plan plan, slicq_dtype dt, bool adjoint, const vo
                          : run_synthesis<double>(p, dt, adjoint, tasks, total, coef, y, w, wk, st);
 }
 
+// Device backend of the streaming server: its own non-blocking stream (default
+// priority), hipMalloc'd device buffers, hipHostMalloc'd staging.
+struct HipBackend {
+  hipStream_t st = nullptr;
+  void* dmalloc(size_t n) {
+    void* p = nullptr;
+    return hipMalloc(&p, n) == hipSuccess ? p : nullptr;
+  }
+  void dfree(void* p) {
+    if (p) (void)hipFree(p);
+  }
+  void* hmalloc(size_t n) {
+    void* p = nullptr;
+    return hipHostMalloc(&p, n, hipHostMallocDefault) == hipSuccess ? p : nullptr;
+  }
+  void hfree(void* p) {
+    if (p) (void)hipHostFree(p);
+  }
+  void h2d(void* d, const void* h, size_t n) { (void)hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, st); }
+  void d2h(void* h, const void* d, size_t n) { (void)hipMemcpyAsync(h, d, n, hipMemcpyDeviceToHost, st); }
+  template <class K, class... A>
+  void launch(K kernel, int64_t grid, int block, size_t shmem, A... args) {
+    HipLaunch L{st};
+    L.launch(kernel, grid, block, shmem, args...);
+  }
+  bool sync() { return hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess; }
+};
+
+}  // namespace
+
+struct slicq_stream_server_s {
+  HipBackend be;
+  slicq::StreamServer<float, HipBackend>* f = nullptr;
+  slicq::StreamServer<double, HipBackend>* d = nullptr;
+  int dt = 0;
+  ~slicq_stream_server_s() {
+    delete f;
+    delete d;
+    if (be.st) (void)hipStreamDestroy(be.st);
+  }
+};
+
+namespace {
+
+template <class F>
+int with_server(slicq_stream_server s, F&& fn) {
+  if (!s) return fail(SLICQ_EINVAL, "null server");
+  if ((s->f && s->f->fenced()) || (s->d && s->d->fenced()))
+    return fail(SLICQ_EHIP, "the server hit a device error and is fenced; destroy it");
+  return s->dt == SLICQ_F32 ? fn(*s->f) : fn(*s->d);
+}
+
 }  // namespace
 
 extern "C" {
+
+int slicq_stream_server_create(slicq_plan plan, slicq_dtype dt, int32_t max_streams, int32_t max_batch,
+                               size_t hbm_budget_bytes, slicq_stream_server* out) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  if (!out || max_streams <= 0 || max_batch <= 0) return fail(SLICQ_EINVAL, "bad server arguments");
+  *out = nullptr;
+  auto* s = new (std::nothrow) slicq_stream_server_s;
+  if (!s) return fail(SLICQ_ENOMEM, "out of host memory");
+  s->dt = dt;
+  hipError_t e = hipStreamCreateWithFlags(&s->be.st, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "stream creation");
+  }
+  std::string err;
+  bool ok;
+  if (dt == SLICQ_F32) {
+    s->f = new slicq::StreamServer<float, HipBackend>(plan->p, dt, s->be, max_streams, max_batch, hbm_budget_bytes);
+    ok = s->f->init(err);
+  } else {
+    s->d = new slicq::StreamServer<double, HipBackend>(plan->p, dt, s->be, max_streams, max_batch, hbm_budget_bytes);
+    ok = s->d->init(err);
+  }
+  if (!ok) {
+    delete s;
+    return fail(err.find("budget") != std::string::npos ? SLICQ_EBUSY : SLICQ_ENOMEM, err);
+  }
+  *out = s;
+  return SLICQ_OK;
+}
+
+void slicq_stream_server_destroy(slicq_stream_server s) { delete s; }
+
+int slicq_stream_open(slicq_stream_server s, int32_t* id) {
+  if (!id) return fail(SLICQ_EINVAL, "null id");
+  return with_server(s, [&](auto& srv) -> int {
+    const int r = srv.open();
+    *id = r;
+    return r >= 0 ? SLICQ_OK : fail(SLICQ_EBUSY, "no free stream slot within the memory budget");
+  });
+}
+
+int slicq_stream_push(slicq_stream_server s, int32_t id, const void* samples, int64_t n) {
+  return with_server(s, [&](auto& srv) -> int {
+    using T = std::remove_pointer_t<decltype(srv.ring_type())>;
+    if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
+    if (n < 0 || (n > 0 && !samples)) return fail(SLICQ_EINVAL, "bad samples");
+    srv.push(id, static_cast<const T*>(samples), n);
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_push_gap(slicq_stream_server s, int32_t id, int64_t n) {
+  return with_server(s, [&](auto& srv) -> int {
+    if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
+    if (n < 0) return fail(SLICQ_EINVAL, "bad count");
+    srv.push_gap(id, n);
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_tick(slicq_stream_server s, int64_t* n_slices) {
+  return with_server(s, [&](auto& srv) -> int {
+    const int64_t r = srv.tick();
+    if (n_slices) *n_slices = r < 0 ? 0 : r;
+    return r >= 0 ? SLICQ_OK : fail(SLICQ_EHIP, "device error in a streaming tick");
+  });
+}
+
+int slicq_stream_poll(slicq_stream_server s, int32_t id, void* out, int64_t max, int64_t* n) {
+  return with_server(s, [&](auto& srv) -> int {
+    using T = std::remove_pointer_t<decltype(srv.ring_type())>;
+    if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
+    if (!n || max < 0 || (max > 0 && !out)) return fail(SLICQ_EINVAL, "bad output buffer");
+    *n = srv.poll(id, static_cast<T*>(out), max);
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_close(slicq_stream_server s, int32_t id) {
+  return with_server(s, [&](auto& srv) -> int {
+    if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
+    srv.close(id);
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_stats_get(slicq_stream_server s, slicq_stream_stats* out) {
+  if (!out) return fail(SLICQ_EINVAL, "null stats");
+  return with_server(s, [&](auto& srv) -> int {
+    const slicq::StreamStats t = srv.stats();
+    std::memset(out, 0, sizeof *out);
+    out->ticks = t.ticks;
+    out->slices = t.slices;
+    out->samples_in = t.samples_in;
+    out->samples_out = t.samples_out;
+    out->admitted = t.admitted;
+    out->rejected = t.rejected;
+    out->closed = t.closed;
+    out->gap_samples = t.gaps;
+    out->latency_p50_s = t.latency_p50;
+    out->latency_p99_s = t.latency_p99;
+    out->latency_max_s = t.latency_max;
+    out->latency_count = t.latency_count;
+    out->busy_s = t.busy_seconds;
+    out->slots = srv.slots();
+    out->ring_len = srv.ring();
+    out->bytes_per_stream = (int64_t)srv.per_stream_bytes();
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_coefs(slicq_stream_server s, int32_t id, void* out, int64_t cap, int64_t* m) {
+  if (!m) return fail(SLICQ_EINVAL, "null m");
+  return with_server(s, [&](auto& srv) -> int {
+    using T = std::remove_pointer_t<decltype(srv.ring_type())>;
+    if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
+    if (!out || cap < srv.coefs_per_slice()) return fail(SLICQ_ESIZE, "buffer below coefs_per_slice");
+    *m = srv.last_coefs(id, static_cast<slicq::C2<T>*>(out));
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_stats_reset(slicq_stream_server s) {
+  return with_server(s, [&](auto& srv) -> int {
+    srv.reset_stats();
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_snapshot(slicq_stream_server s, int32_t id, void* buf, size_t cap, size_t* bytes) {
+  if (!bytes) return fail(SLICQ_EINVAL, "null size");
+  return with_server(s, [&](auto& srv) -> int {
+    if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
+    std::vector<unsigned char> blob;
+    if (!srv.snapshot(id, blob)) return fail(SLICQ_EHIP, "device error while reading the stream state");
+    *bytes = blob.size();
+    if (!buf) return SLICQ_OK;
+    if (cap < blob.size()) return fail(SLICQ_ESIZE, "snapshot buffer too small");
+    std::memcpy(buf, blob.data(), blob.size());
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_restore(slicq_stream_server s, int32_t id, const void* buf, size_t bytes) {
+  return with_server(s, [&](auto& srv) -> int {
+    if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
+    if (!buf) return fail(SLICQ_EINVAL, "null snapshot");
+    if (!srv.restore(id, static_cast<const unsigned char*>(buf), bytes))
+      return fail(SLICQ_EINVAL, "snapshot does not match this server (plan, dtype or size)");
+    return SLICQ_OK;
+  });
+}
+
 
 int nsgt_plan_ex(const slicq_plan_opts* o, slicq_plan* out) {
   if (!o || !out) return fail(SLICQ_EINVAL, "null argument");

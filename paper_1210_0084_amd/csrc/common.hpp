@@ -46,6 +46,13 @@ struct alignas(16) SynRunDev {
   int32_t lds_off, pad0_, pad1_, pad2_;
 };
 
+// Streaming: `count` samples move between position `pos` (mod R) of the ring
+// of stream slot `slot` and offset `off` of a packed staging buffer.
+struct alignas(16) RingCopy {
+  int32_t slot, count;
+  int64_t pos, off;
+};
+
 // Byte offsets of the device tables inside one uploaded blob. The frequency
 // overlap-add of synthesis is a per-bin program: bin j (0..N) sums entries
 // ent_off[j] .. ent_off[j+1]-1, entry e reading the transformed coefficient at

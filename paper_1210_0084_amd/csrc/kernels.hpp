@@ -597,6 +597,28 @@ __global__ void __launch_bounds__(256) k_zero_overlaps(const SliceTask* __restri
   if (idx < tk.y_valid) y[tk.y_base + idx] = T(0);
 }
 
+// Streaming ring traffic: block b moves descriptor b's samples from the packed
+// staging buffer into the ring (to_ring) or from the ring into staging.
+// R is a power of two.
+template <class T>
+__global__ void __launch_bounds__(256) k_ring_copy(const RingCopy* __restrict__ d, T* __restrict__ staging,
+                                                   T* __restrict__ rings, int64_t R, int32_t to_ring) {
+  const RingCopy c = d[blockIdx.x];
+  T* ring = rings + (int64_t)c.slot * R;
+  for (int i = threadIdx.x; i < c.count; i += blockDim.x) {
+    const int64_t r = (c.pos + i) & (R - 1);
+    if (to_ring) ring[r] = staging[c.off + i];
+    else staging[c.off + i] = ring[r];
+  }
+}
+
+// Zeroes `n` values starting at p.
+template <class T>
+__global__ void __launch_bounds__(256) k_fill_zero(T* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
+}
+
 // Slices of one signal of T samples (L = 2N ceil(T/2N), S = L/N), m0.. m0+count-1.
 __global__ void __launch_bounds__(256) k_tasks_plain(SliceTask* __restrict__ tasks, int64_t m0,
                                                      int64_t count, int64_t T, int64_t N, int64_t S) {

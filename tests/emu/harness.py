@@ -19,19 +19,52 @@ CSRC = os.path.join(ROOT, "paper_1210_0084_amd", "csrc")
 BUILD = os.path.join(HERE, "_build")
 EXE = os.path.join(BUILD, "emu_runner")
 SOURCES = [os.path.join(HERE, "emu_runner.cpp"), os.path.join(CSRC, "plan.cpp")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "plan.hpp", "common.hpp")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "plan.hpp", "common.hpp",
+                                            "stream_server.hpp")]
+STREAM_EXE = os.path.join(BUILD, "stream_runner")
+
+
+def _build(exe: str, main_src: str) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [main_src, os.path.join(CSRC, "plan.cpp")]
+    deps = srcs + HEADERS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")]
+    if os.path.exists(exe) and os.path.getmtime(exe) > max(os.path.getmtime(d) for d in deps):
+        return exe
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", *srcs, "-o", exe + ".tmp"]
+    subprocess.check_call(cmd)
+    os.replace(exe + ".tmp", exe)
+    return exe
 
 
 def build() -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    deps = SOURCES + HEADERS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")]
-    if os.path.exists(EXE) and os.path.getmtime(EXE) > max(os.path.getmtime(d) for d in deps):
-        return EXE
-    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-           "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", *SOURCES, "-o", EXE + ".tmp"]
-    subprocess.check_call(cmd)
-    os.replace(EXE + ".tmp", EXE)
-    return EXE
+    return _build(EXE, os.path.join(HERE, "emu_runner.cpp"))
+
+
+def stream(plan: dict, signals, hop: int, dtype: int = 1, mode: int = 0, max_streams: int = 8,
+           max_batch: int = 16, budget: int = 0):
+    """Runs the streaming scenario of stream_runner.cpp; returns (outputs, stats)."""
+    exe = _build(STREAM_EXE, os.path.join(HERE, "stream_runner.cpp"))
+    lens = [len(s) for s in signals]
+    payload = np.concatenate([[len(signals)], lens] + [np.asarray(s, dtype=np.float64) for s in signals])
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
+        payload.tofile(fin)
+        args = [exe, str(dtype), repr(float(plan["fs"])), repr(float(plan["fmin"])), repr(float(plan["fmax"])),
+                str(plan["bins_per_octave"]), str(plan["slice_len"]), str(plan["transition"]),
+                repr(float(plan.get("min_win", 16.0))), str(max_streams), str(max_batch), str(budget), str(hop),
+                str(mode), fin, fout]
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
+        r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"stream_runner failed ({r.returncode}): {r.stderr[-3000:]}")
+        out = np.fromfile(fout, dtype=np.float64)
+    sel = range(len(signals)) if mode == 0 else [mode - 1]
+    ys, pos = [], 0
+    for i in sel:
+        ys.append(out[pos:pos + lens[i]])
+        pos += lens[i]
+    return ys, out[pos:pos + 4]
 
 
 def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,

@@ -78,3 +78,17 @@ def test_emu_slice_major_layout():
     ref = np.concatenate([np.concatenate([np.concatenate([ck[m] for ck in analyze(pl, v)])
                                           for m in range(num_slices(len(v), pl.two_n))]) for v in xs if len(v)])
     assert rel(H.analyze_batched(kw, xs, 1, layout=1), ref) < 1e-12
+
+
+def test_emu_streaming_server():
+    # the streaming scheduler with the library's kernels on the CPU: every
+    # stream's output reconstructs its input (Proposition 3, linear slicing),
+    # is bit-identical alone and in the mix, and a snapshot replays bit for bit
+    kw = TINY2
+    sig = [np.random.default_rng(70 + i).standard_normal(n) for i, n in enumerate([700, 333, 520])]
+    ys, stats = H.stream(kw, sig, hop=32, dtype=1, mode=0, max_streams=4, max_batch=6)
+    for y, x in zip(ys, sig):
+        assert np.abs(y - x).max() < 1e-12
+    alone, _ = H.stream(kw, sig, hop=32, dtype=1, mode=2, max_streams=4, max_batch=6)
+    assert np.array_equal(alone[0], ys[1])
+    assert stats[0] == 4 and stats[1] == 0 and stats[2] > 0      # 3 streams + the snapshot replay

@@ -1,0 +1,161 @@
+"""Streaming service on the GPU: per-slice coefficients against the oracle's
+linear (streaming) analysis, reconstruction, identical results alone and in
+the mix, admission by memory budget, snapshot/restore, gaps and closing."""
+import numpy as np
+import pytest
+
+from oracle import OraclePlan, analyze_stream
+from workloads import PRESETS, pink_plus_tones
+
+pytestmark = pytest.mark.gpu
+
+
+def c5_kw():
+    p = PRESETS["c5"]
+    return dict(fs=p.fs, fmin=p.fmin, fmax=p.fmax, bins_per_octave=p.bins_per_octave, slice_len=p.slice_len,
+                transition=p.transition)
+
+
+@pytest.fixture(scope="module")
+def sq():
+    import paper_1210_0084_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def plan(sq, dev):
+    return sq.Plan(**c5_kw(), layout="slice")
+
+
+HOP = 4096
+
+
+def feed(server, ids, signals, hop=HOP, coefs_of=None):
+    """Round-robin hops, one tick per round, then a zero flush; returns outputs
+    (first T samples of each stream) and, for stream coefs_of, {m: c^m}."""
+    plan = server.plan
+    flush = plan.N + plan.transition
+    outs = {i: [] for i in ids}
+    caps = {}
+    fed = {i: 0 for i in ids}
+    total = {i: len(s) + flush for i, s in zip(ids, signals)}
+    sig = dict(zip(ids, signals))
+    while any(fed[i] < total[i] for i in ids):
+        for i in ids:
+            if fed[i] >= total[i]:
+                continue
+            n = min(hop, total[i] - fed[i])
+            h = np.zeros(n)
+            lo, hi = fed[i], min(fed[i] + n, len(sig[i]))
+            if hi > lo:
+                h[:hi - lo] = sig[i][lo:hi]
+            server.push(i, h)
+            fed[i] += n
+        server.tick()
+        if coefs_of is not None:
+            m, c = server.last_coefs(coefs_of)
+            if m >= 0:
+                caps[m] = c
+        for i in ids:
+            outs[i].append(server.poll(i))
+    return {i: np.concatenate(outs[i])[:len(sig[i])] for i in ids}, caps
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_stream_coefficients_and_reconstruction(sq, plan):
+    srv = sq.StreamServer(plan, "f32", max_streams=8, max_batch=64)
+    sigs = [pink_plus_tones(96000, 48000.0, 5_000_000 + i) for i in range(4)]
+    ids = [srv.open() for _ in sigs]
+    outs, caps = feed(srv, ids, sigs, coefs_of=ids[0])
+    for i, s in zip(ids, sigs):
+        assert rel(outs[i], s) <= 1e-5
+    opl = OraclePlan(**c5_kw())
+    ref = analyze_stream(opl, sigs[0], max(caps) + 1)
+    for m, c in caps.items():
+        r = np.concatenate([ck[m] for ck in ref])
+        assert rel(c, r) <= 1e-5, m
+    st = srv.stats()
+    assert st["slices"] > 0 and st["latency_count"] > 0 and st["latency_p99_s"] >= st["latency_p50_s"] > 0
+
+
+def test_alone_equals_in_the_mix_bitwise(sq, plan):
+    sigs = [pink_plus_tones(70000 + 3000 * i, 48000.0, 5_000_100 + i) for i in range(6)]
+    mix = sq.StreamServer(plan, "f32", max_streams=8, max_batch=64)
+    ids = [mix.open() for _ in sigs]
+    outs, caps_mix = feed(mix, ids, sigs, coefs_of=ids[3])
+    alone = sq.StreamServer(plan, "f32", max_streams=8, max_batch=64)
+    a = alone.open()
+    out_a, caps_a = feed(alone, [a], [sigs[3]], coefs_of=a)
+    assert np.array_equal(out_a[a], outs[ids[3]])
+    assert caps_a.keys() == caps_mix.keys()
+    for m in caps_a:
+        assert np.array_equal(caps_a[m], caps_mix[m])
+
+
+def test_admission_by_memory_budget(sq, plan):
+    per = 2 * 4 * plan.N * 4            # two rings of 4N float32 samples
+    srv = sq.StreamServer(plan, "f32", max_streams=16, max_batch=8, hbm_budget_bytes=3 * per)
+    assert srv.stats()["slots"] == 3
+    ids = [srv.open() for _ in range(3)]
+    with pytest.raises(sq.SlicqBusy):
+        srv.open()
+    srv.close(ids[1])
+    srv.tick()
+    assert srv.open() == ids[1]
+    st = srv.stats()
+    assert st["admitted"] == 4 and st["rejected"] == 1 and st["closed"] == 1
+
+
+def test_snapshot_restore_bitwise(sq, plan):
+    srv = sq.StreamServer(plan, "f32", max_streams=4, max_batch=16)
+    x = pink_plus_tones(120000, 48000.0, 5_000_200)
+    a = srv.open()
+    head = 40960
+    for lo in range(0, head, HOP):
+        srv.push(a, x[lo:lo + HOP])
+        srv.tick()
+    first = srv.poll(a)
+    blob = srv.snapshot(a)
+    rest = x[head:]
+    for lo in range(0, len(rest), HOP):
+        srv.push(a, rest[lo:lo + HOP])
+        srv.tick()
+    cont = srv.poll(a)
+    b = srv.open()
+    srv.restore(b, blob)
+    for lo in range(0, len(rest), HOP):
+        srv.push(b, rest[lo:lo + HOP])
+        srv.tick()
+    replay = srv.poll(b)
+    assert len(first) > 0 and np.array_equal(cont, replay)
+
+
+def test_gap_and_close_midstream(sq, plan):
+    srv = sq.StreamServer(plan, "f32", max_streams=2, max_batch=16)
+    x = pink_plus_tones(90000, 48000.0, 5_000_300)
+    a = srv.open()
+    expect = x.copy()
+    fed = 0
+    out = []
+    for k in range(0, len(x) // HOP):
+        if k == 5:
+            srv.push_gap(a, HOP)               # the hop never arrived
+            expect[fed:fed + HOP] = 0.0
+        else:
+            srv.push(a, x[fed:fed + HOP])
+        fed += HOP
+        srv.tick()
+        out.append(srv.poll(a))
+    y = np.concatenate(out)
+    assert len(y) > 6 * HOP
+    assert rel(y, expect[:len(y)]) <= 1e-5
+    assert srv.stats()["gap_samples"] == HOP
+    srv.close(a)                               # mid-slice: queued input is dropped
+    srv.tick()
+    b = srv.open()
+    z = pink_plus_tones(50000, 48000.0, 5_000_301)
+    outs, _ = feed(srv, [b], [z])
+    assert rel(outs[b], z) <= 1e-5
