@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "sliCQ analysis+synthesis Msamples/s at 1 GPU, % HBM roofline; p99 slice latency"
 STAGES = ["fwd_pass1", "fwd_pass2", "band_ana", "band_syn", "inv_passA", "inv_passB"]
 
 
@@ -109,6 +110,224 @@ def cpu_baseline(prm, xs, seconds_target=15.0):
                       f"best of {reps}; reconstruction max error {err:.1e}"}
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _preset(name):
+    from workloads import PRESETS
+    p = PRESETS[name]
+    return dict(fs=p.fs, fmin=p.fmin, fmax=p.fmax, bins_per_octave=p.bins_per_octave, slice_len=p.slice_len,
+                transition=p.transition)
+
+
+def bench_batched(args):
+    """Ragged batch of 256 signals (5-30 s): one graph launch of the batched
+    calls, the same calls eagerly, and a loop of single-signal calls."""
+    import torch
+    import paper_1210_0084_amd as sq
+    from paper_1210_0084_amd.tuning import BatchGraph
+    from workloads import batch_lengths, pink_plus_tones
+    dev = torch.device("cuda:0")
+    prm = _preset("c3")
+    # lengths as the ragged-batch generator draws them; content cut from one
+    # 60 s pink-plus-tones recording at random offsets (the time of the
+    # transform does not depend on the samples, generating 256 distinct
+    # recordings would take minutes of host time)
+    lens = [int(t) for t in batch_lengths(args.c3_signals, 44100.0, 4)]
+    base = pink_plus_tones(int(60 * 44100), 44100.0, 4_000_012).astype(np.float32)
+    g = np.random.default_rng(4)
+    offs0 = [int(g.integers(0, len(base) - t + 1)) for t in lens]
+    plan = sq.Plan(**prm)
+    lay = plan.batch_layout(lens)
+    x = torch.tensor(np.concatenate([base[o:o + t] for o, t in zip(offs0, lens)]), device=dev)
+    coef = torch.empty(lay.coef_len, dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    graph = BatchGraph(plan, x, coef, y, lay)
+    ms_graph = _time(graph.replay, args.steps, args.warmup)
+    err = float((y - x).abs().max())
+    ms_eager = _time(lambda: (plan.analyze_batched(x, out=coef, layout=lay),
+                              plan.synthesize_batched(coef, out=y, layout=lay)), args.steps, args.warmup)
+    offs = lay.x_off
+    cofs = lay.coef_off
+    views = [(x[offs[i]:offs[i + 1]], coef[cofs[i]:cofs[i] + lay.slices[i] * plan.coefs_per_slice],
+              y[offs[i]:offs[i + 1]]) for i in range(len(lens))]
+
+    def loop():
+        for xi, ci, yi in views:
+            plan.analyze(xi, out=ci)
+            plan.synthesize(ci, xi.numel(), out=yi)
+    ms_loop = _time(loop, max(1, args.steps // 5), 1)
+    samples = int(sum(lens))
+    path_bytes = 2 * 4 * samples + 2 * 8 * lay.total_slices * plan.coefs_per_slice
+    rate = lambda ms: round(samples / (ms * 1e-3) / 1e6, 1)
+    return {"metric": METRIC, "value": rate(ms_graph), "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_graph, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"ragged batch of {len(lens)} signals of 5-30 s (44.1 kHz), B=24, "
+                                   "41.2-22050 Hz, 2N=32768, M=4096; analysis+synthesis in one HIP graph",
+                       "samples": samples, "slices": lay.total_slices},
+            "path": {"GBs": round(path_bytes / (ms_graph * 1e-3) / 1e9, 1),
+                     "frac": round(path_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "reconstruction_max_abs_err": err},
+            "compare": {"graph_ms": round(ms_graph, 3), "eager_batched_ms": round(ms_eager, 3),
+                        "per_signal_loop_ms": round(ms_loop, 3), "graph_Msps": rate(ms_graph),
+                        "eager_Msps": rate(ms_eager), "loop_Msps": rate(ms_loop)}}
+
+
+def bench_differentiable(args):
+    """Batch of 32 x 6 s: loss of the log-magnitude coefficients against a
+    second batch, forward through SliCQFunction and backward through the
+    adjoint kernel, beside the plain analysis + synthesis of the same batch."""
+    import torch
+    import paper_1210_0084_amd as sq
+    from workloads import make_c4
+    dev = torch.device("cuda:0")
+    plan = sq.Plan(**_preset("c4"))
+    xb = make_c4(args.c4_batch)
+    yb = make_c4(args.c4_batch, target=True)
+    B, T = xb.shape
+    x = torch.tensor(xb, dtype=torch.float32, device=dev, requires_grad=True)
+    with torch.no_grad():
+        cy = sq.slicq(torch.tensor(yb, dtype=torch.float32, device=dev), plan)
+        ly = torch.log1p(cy.real ** 2 + cy.imag ** 2)
+
+    def fwd_bwd():
+        x.grad = None
+        c = sq.slicq(x, plan)
+        loss = ((torch.log1p(c.real ** 2 + c.imag ** 2) - ly) ** 2).sum()
+        loss.backward()
+    ms_fb = _time(fwd_bwd, args.steps, args.warmup)
+    lay = plan.batch_layout([T] * B)
+    xf = x.detach().reshape(-1).contiguous()
+    coef = torch.empty(lay.coef_len, dtype=torch.complex64, device=dev)
+    yy = torch.empty_like(xf)
+    ms_plain = _time(lambda: (plan.analyze_batched(xf, out=coef, layout=lay),
+                              plan.synthesize_batched(coef, out=yy, layout=lay)), args.steps, args.warmup)
+    ms_adj = _time(lambda: plan.synthesize_batched(coef, out=yy, layout=lay, adjoint=True), args.steps, args.warmup)
+    samples = B * T
+    rate = lambda ms: round(samples / (ms * 1e-3) / 1e6, 1)
+    return {"metric": METRIC, "value": rate(ms_fb), "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_fb, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{B} x 6 s (264600 samples) at 44.1 kHz, B=36, 65.4-16000 Hz, 2N=16384, "
+                                   "M=2048; log-magnitude loss forward + adjoint backward", "slices": lay.total_slices},
+            "compare": {"forward_backward_ms": round(ms_fb, 3), "plain_analysis_synthesis_ms": round(ms_plain, 3),
+                        "adjoint_only_ms": round(ms_adj, 3), "forward_backward_Msps": rate(ms_fb),
+                        "plain_Msps": rate(ms_plain)}}
+
+
+def bench_stream(args):
+    """Streaming service: 512 streams of 48 kHz audio delivering 4096-sample
+    hops. Paced: hops arrive at real-time rate with Poisson stream arrivals
+    and exponential lifetimes (mean 60 s), one tick thread batches whatever
+    is ready; reports p50/p99 slice latency. Unpaced: every stream pushes as
+    fast as the server drains, for the sustainable throughput."""
+    import threading
+    import torch
+    import paper_1210_0084_amd as sq
+    from workloads import make_c5_stream
+    torch.cuda.init()
+    plan = sq.Plan(**_preset("c5"), layout="slice")
+    fs, hop, n_streams = 48000.0, 4096, args.c5_streams
+    pool = [make_c5_stream(i, int(fs * 10)).astype(np.float32) for i in range(16)]
+    srv = sq.StreamServer(plan, "f32", max_streams=n_streams + 64, max_batch=2 * n_streams)
+    rng = np.random.default_rng(5)
+    stop = threading.Event()
+    lock = threading.Lock()
+
+    def ticker():
+        while not stop.is_set():
+            if srv.tick() == 0:
+                time.sleep(2e-4)
+
+    active = {}
+    def open_stream(k):
+        sid = srv.open()
+        active[sid] = {"src": k % len(pool), "pos": 0, "end": time.perf_counter() + rng.exponential(60.0)}
+    for k in range(n_streams):
+        open_stream(k)
+    th = threading.Thread(target=ticker, daemon=True)
+    th.start()
+    hop_s = hop / fs
+    t0 = time.perf_counter()
+    next_arrival = t0 + rng.exponential(60.0 / n_streams)
+    nxt = t0
+    k_new = n_streams
+    while time.perf_counter() - t0 < args.c5_seconds:
+        now = time.perf_counter()
+        if now < nxt:
+            time.sleep(min(nxt - now, 0.005))
+            continue
+        for sid in list(active):
+            st = active[sid]
+            if now > st["end"]:
+                srv.close(sid)
+                del active[sid]
+                continue
+            src = pool[st["src"]]
+            a = st["pos"] % (len(src) - hop)
+            srv.push(sid, src[a:a + hop])
+            st["pos"] += hop
+            srv.poll(sid)
+        while next_arrival <= now:
+            try:
+                open_stream(k_new)
+            except sq.SlicqBusy:
+                pass
+            k_new += 1
+            next_arrival += rng.exponential(60.0 / n_streams)
+        nxt += hop_s
+    stop.set()
+    th.join()
+    paced = srv.stats()
+    wall = time.perf_counter() - t0
+    # unpaced: push one hop per stream per round as fast as ticks drain
+    srv.reset_stats()
+    ids = list(active)
+    hops = [pool[active[i]["src"]][:hop] for i in ids]
+    t1 = time.perf_counter()
+    rounds = 0
+    while time.perf_counter() - t1 < args.c5_seconds / 2:
+        for i, h in zip(ids, hops):
+            srv.push(i, h)
+        srv.tick()
+        for i in ids:
+            srv.poll(i)
+        rounds += 1
+    un = srv.stats()
+    t_un = time.perf_counter() - t1
+    return {"metric": METRIC, "value": round(paced["samples_in"] / wall / 1e6, 2), "unit": "Msamples/s",
+            "n_gpus": 1, "steps": paced["ticks"], "warmup": 0, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{n_streams} real-time streams at 48 kHz, 4096-sample hops, Poisson "
+                                   "arrivals, mean lifetime 60 s; B=96, 27.5-20000 Hz, 2N=16384, M=2048",
+                       "seconds": round(wall, 1)},
+            "latency_ms": {"p50": round(paced["latency_p50_s"] * 1e3, 3), "p99": round(paced["latency_p99_s"] * 1e3, 3),
+                           "max": round(paced["latency_max_s"] * 1e3, 3), "slices": paced["latency_count"]},
+            "paced": {k: paced[k] for k in ("ticks", "slices", "samples_in", "samples_out", "admitted", "rejected",
+                                            "closed")},
+            "unpaced": {"Msamples_per_s": round(un["samples_in"] / t_un / 1e6, 2), "slices_per_s":
+                        round(un["slices"] / t_un, 1), "streams": len(ids), "rounds": rounds,
+                        "latency_p50_ms": round(un["latency_p50_s"] * 1e3, 3),
+                        "latency_p99_ms": round(un["latency_p99_s"] * 1e3, 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,11 +337,23 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (scale for HBM byte counters)")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
+                    help="c2 (default): 60 s stereo; c3: ragged batch in a HIP graph; c4: differentiable; "
+                         "c5: streaming service")
+    ap.add_argument("--c3-signals", type=int, default=256)
+    ap.add_argument("--c4-batch", type=int, default=32)
+    ap.add_argument("--c5-streams", type=int, default=512)
+    ap.add_argument("--c5-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (slices would shard with a "
               "one-time overlap halo exchange; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload != "c2":
+        fn = {"c3": bench_batched, "c4": bench_differentiable, "c5": bench_stream}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
 
     import torch
     import paper_1210_0084_amd as sq
@@ -171,7 +402,7 @@ def main():
     achieved = sbytes[dom] / (stage_ms[dom] * 1e-3) / 1e9
     path_bytes = 2 * 4 * samples + 2 * 8 * S * plan.coefs_per_slice
     rec = {
-        "metric": "sliCQ analysis+synthesis Msamples/s at 1 GPU, % HBM roofline; p99 slice latency",
+        "metric": METRIC,
         "value": round(value, 1),
         "unit": "Msamples/s",
         "n_gpus": 1,

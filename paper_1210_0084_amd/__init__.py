@@ -337,6 +337,16 @@ class Plan:
         """Offsets for a ragged batch; pass it back to the batched calls to reuse it."""
         return BatchLayout(self, lengths)
 
+    def _uniform_layout(self, B: int, T: int) -> BatchLayout:
+        """Cached layout of B signals of T samples (the autograd path reuses it every step)."""
+        cache = self.__dict__.setdefault("_layouts", {})
+        lay = cache.get((B, T))
+        if lay is None:
+            if len(cache) >= 16:
+                cache.clear()
+            lay = cache[(B, T)] = BatchLayout(self, [T] * B)
+        return lay
+
     def analyze_batched(self, x_packed, lengths=None, out=None, work=None, layout: Optional[BatchLayout] = None):
         """Analysis of a ragged batch packed back to back in x_packed; one launch per kernel."""
         torch = _torch()
@@ -434,11 +444,20 @@ class StreamServer:
         _check(self._lib.slicq_stream_tick(self._h, ctypes.byref(n)))
         return n.value
 
-    def poll(self, sid: int, max_samples: int = 1 << 22):
-        out = np.empty(int(max_samples), dtype=self.np_dtype)
+    def poll(self, sid: int, max_samples: Optional[int] = None):
+        """Final output samples of stream sid (all that are ready, or at most max_samples)."""
+        parts = []
+        left = int(max_samples) if max_samples is not None else -1
         n = ctypes.c_int64()
-        _check(self._lib.slicq_stream_poll(self._h, int(sid), out.ctypes.data, out.size, ctypes.byref(n)))
-        return out[:n.value].copy()
+        while left != 0:
+            out = np.empty(1 << 16 if left < 0 else min(left, 1 << 16), dtype=self.np_dtype)
+            _check(self._lib.slicq_stream_poll(self._h, int(sid), out.ctypes.data, out.size, ctypes.byref(n)))
+            parts.append(out[:n.value])
+            if left > 0:
+                left -= n.value
+            if n.value < out.size:
+                break
+        return parts[0] if len(parts) == 1 else np.concatenate(parts)
 
     def close(self, sid: int) -> None:
         _check(self._lib.slicq_stream_close(self._h, int(sid)))
@@ -489,7 +508,7 @@ def _make_function():
             if x.dim() == 1:
                 return plan.analyze(x.contiguous())
             B, T = x.shape
-            lay = plan.batch_layout([T] * B)
+            lay = plan._uniform_layout(B, T)
             ctx.layout = lay
             c = plan.analyze_batched(x.contiguous().view(-1), layout=lay)
             return c.view(B, -1)

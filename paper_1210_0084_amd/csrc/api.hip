@@ -5,7 +5,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/slicq.h"
@@ -20,6 +22,7 @@ struct slicq_plan_s {
 namespace {
 
 thread_local std::string g_err;
+constexpr size_t kMaxLdsBytesAbi = slicq::kMaxLdsBytes;
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -32,15 +35,25 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(SLICQ_EHIP, b);
 }
 
+// Raises a kernel's dynamic-LDS limit once (not per launch, so that launches
+// recorded into a graph contain nothing but the kernels).
+void allow_lds(const void* kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lk(mu);
+  size_t& cur = done[kernel];
+  if (bytes > cur) {
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytesAbi);
+    cur = kMaxLdsBytesAbi;
+  }
+}
+
 struct HipLaunch {
   hipStream_t st;
   template <class K, class... A>
   void launch(K kernel, int64_t grid, int block, size_t shmem, A... args) {
     if (grid <= 0) return;
-    if (shmem > 65536) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    }
+    if (shmem > 65536) allow_lds(reinterpret_cast<const void*>(kernel), shmem);
     hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3((unsigned)block), shmem, st, args...);
   }
 };
