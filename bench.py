@@ -86,6 +86,12 @@ def time_stages(plan, n_slices, x, coef, y, reps=20):
     return out
 
 
+def _stage_report(plan, n_slices, x, coef, y, reps):
+    ms = time_stages(plan, n_slices, x, coef, y, reps)
+    sb = stage_bytes(plan, n_slices, 4)
+    return {k: {"ms": round(ms[k], 4), "GBs": round(sb[k] / (ms[k] * 1e-3) / 1e9, 1)} for k in STAGES}
+
+
 def cpu_baseline(prm, xs, seconds_target=15.0):
     """The FP64 oracle (unchanged) on the first slices of the left channel."""
     from oracle import OraclePlan, analyze, synthesize
@@ -163,6 +169,7 @@ def bench_batched(args):
     err = float((y - x).abs().max())
     ms_eager = _time(lambda: (plan.analyze_batched(x, out=coef, layout=lay),
                               plan.synthesize_batched(coef, out=y, layout=lay)), args.steps, args.warmup)
+    stages = _stage_report(plan, lay.total_slices, x, coef, y, args.stage_reps)
     offs = lay.x_off
     cofs = lay.coef_off
     views = [(x[offs[i]:offs[i + 1]], coef[cofs[i]:cofs[i] + lay.slices[i] * plan.coefs_per_slice],
@@ -185,6 +192,7 @@ def bench_batched(args):
             "path": {"GBs": round(path_bytes / (ms_graph * 1e-3) / 1e9, 1),
                      "frac": round(path_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "reconstruction_max_abs_err": err},
+            "stages": stages,
             "compare": {"graph_ms": round(ms_graph, 3), "eager_batched_ms": round(ms_eager, 3),
                         "per_signal_loop_ms": round(ms_loop, 3), "graph_Msps": rate(ms_graph),
                         "eager_Msps": rate(ms_eager), "loop_Msps": rate(ms_loop)}}
@@ -220,6 +228,9 @@ def bench_differentiable(args):
     ms_plain = _time(lambda: (plan.analyze_batched(xf, out=coef, layout=lay),
                               plan.synthesize_batched(coef, out=yy, layout=lay)), args.steps, args.warmup)
     ms_adj = _time(lambda: plan.synthesize_batched(coef, out=yy, layout=lay, adjoint=True), args.steps, args.warmup)
+    plan.analyze_batched(xf, out=coef, layout=lay)
+    plan.synthesize_batched(coef, out=yy, layout=lay)
+    stages = _stage_report(plan, lay.total_slices, xf, coef, yy, args.stage_reps)
     samples = B * T
     rate = lambda ms: round(samples / (ms * 1e-3) / 1e6, 1)
     return {"metric": METRIC, "value": rate(ms_fb), "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
@@ -227,6 +238,7 @@ def bench_differentiable(args):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"{B} x 6 s (264600 samples) at 44.1 kHz, B=36, 65.4-16000 Hz, 2N=16384, "
                                    "M=2048; log-magnitude loss forward + adjoint backward", "slices": lay.total_slices},
+            "stages": stages,
             "compare": {"forward_backward_ms": round(ms_fb, 3), "plain_analysis_synthesis_ms": round(ms_plain, 3),
                         "adjoint_only_ms": round(ms_adj, 3), "forward_backward_Msps": rate(ms_fb),
                         "plain_Msps": rate(ms_plain)}}

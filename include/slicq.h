@@ -70,8 +70,10 @@ typedef struct {
   int64_t transition_len;   /* Tukey transition M, 0 < M < N, N - M even */
   double min_win;           /* minimal band support in bins (Section 5.3), default 16 */
   int32_t dual_slice;       /* 0: canonical dual h_0 / sum_m T_mN h_0^2, 1: indicator of supp h_0 */
-  int32_t group_cap;        /* tuning: coefficients of the own bands of a band work item (power of two), default 2048 */
-  int32_t lds_cap;          /* tuning: complex values per synthesis work item, default 9216 */
+  int32_t group_cap;        /* tuning: coefficients per analysis work item (power of two, 16..4096), default 2048 */
+  int32_t lds_cap;          /* tuning: target complex values per synthesis work item, own and overlapping
+                               bands (64..16384), default 4096; a single band with the bands reaching
+                               into its bins may exceed it, up to 16384 */
   int32_t pass_cap;         /* tuning: complex values per slice-FFT work item (power of two), default 4096 */
   int32_t coef_layout;      /* SLICQ_BAND_MAJOR (0) or SLICQ_SLICE_MAJOR (1), see below */
 } slicq_plan_opts;

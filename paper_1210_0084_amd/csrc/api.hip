@@ -629,12 +629,10 @@ int slicq_profile_stage(slicq_plan plan, slicq_dtype dt, int stage, int64_t n_sl
       case 0: L.launch(k_fwd_pass1<T>, n * g.g1, g.b1, g.s1, a, tasks, static_cast<const T*>(x), W1); break;
       case 1: L.launch(k_fwd_pass2<T>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2); break;
       case 2:
-        if (g.Ea == 16) L.launch(k_band_ana<T, 16>, n * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, static_cast<C2<T>*>(coef));
-        else L.launch(k_band_ana<T, 32>, n * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, static_cast<C2<T>*>(coef));
+        launch_band_ana(a, g, tasks, n, (const C2<T>*)W2, static_cast<C2<T>*>(coef), L);
         break;
       case 3:
-        if (g.Es == 16) L.launch(k_band_syn<T, 16>, n * g.gs, g.bs, g.ss, a, tasks, (const C2<T>*)coef, W2, static_cast<T*>(y));
-        else L.launch(k_band_syn<T, 32>, n * g.gs, g.bs, g.ss, a, tasks, (const C2<T>*)coef, W2, static_cast<T*>(y));
+        launch_band_syn(a, g, tasks, n, (const C2<T>*)coef, W2, static_cast<T*>(y), L);
         break;
       case 4: L.launch(k_inv_passA<T>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1); break;
       default: L.launch(k_inv_passB<T>, n * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, static_cast<T*>(y)); break;

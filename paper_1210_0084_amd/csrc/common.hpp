@@ -29,22 +29,42 @@ struct alignas(16) BandDev {
   int32_t off, goff, hlo, hhi;
 };
 
+// Four 32-bit integers (one 16-byte load).
+struct alignas(16) I4 {
+  int32_t x, y, z, w;
+};
+
+// Largest work item (complex values) of the kernels for small items; larger
+// items (a wide DC or Nyquist plateau band) go to kernels with more threads
+// or more values per thread.
+constexpr int kAnaSmallValues = 4096;
+constexpr int kSynSmallValues = 8192;
+constexpr int kSynMaxValues = 16384;    // largest synthesis work item
+// Most bands one work item may span (an analysis item stages their
+// descriptors in LDS).
+constexpr int kMaxGroupBands = 256;
+
 // Analysis work item: bands k0 .. k0 + cnt - 1, all with M_k = M.
 struct alignas(16) AnaGroupDev {
   int32_t k0, cnt, M, logM;
 };
 
 // Synthesis work item: bins [lo, hi) of the half spectrum, built from bands
-// ke .. kb whose coefficients are transformed in runs of equal M_k.
+// ke .. kb whose coefficients are transformed in runs of equal M_k (at most
+// kMaxRuns runs); maxM is the largest M_k among them.
 struct alignas(16) SynGroupDev {
   int32_t ke, kb, lo, hi;
-  int32_t run0, nrun, total, pad_;
+  int32_t run0, nrun, total, maxM;
 };
 
+// A run: bands k0 .. k0 + cnt - 1 with M_k = M, packed from offset off of the
+// slice's coefficients, held at LDS position lds_off of the work item.
 struct alignas(16) SynRunDev {
   int32_t k0, cnt, M, logM;
-  int32_t lds_off, pad0_, pad1_, pad2_;
+  int32_t lds_off, off, pad0_, pad1_;
 };
+
+constexpr int kMaxRuns = 8;
 
 // Streaming: `count` samples move between position `pos` (mod R) of the ring
 // of stream slot `slot` and offset `off` of a packed staging buffer.
@@ -54,13 +74,18 @@ struct alignas(16) RingCopy {
 };
 
 // Byte offsets of the device tables inside one uploaded blob. The frequency
-// overlap-add of synthesis is a per-bin program: bin j (0..N) sums entries
-// ent_off[j] .. ent_off[j+1]-1, entry e reading the transformed coefficient at
-// LDS position ent_pos[e].x (and, for the self-mirrored DC and Nyquist bands,
-// the conjugate of the one at ent_pos[e].y, else y = -1) times ent_wsyn[e]
-// (synthesis, dual windows) or ent_wadj[e] (adjoint, analysis windows).
+// overlap-add of synthesis is a per-bin program over the bands covering bin
+// j (0..N) in increasing k; an entry reads the transformed coefficient at LDS
+// position x of the owning work item (and, for the self-mirrored DC and
+// Nyquist bands, adds the conjugate of the one at position y, else y = -1)
+// times a weight: the dual window (synthesis) or the analysis window
+// (adjoint). The first two entries of bin j sit at fixed places, ent2_pos[j]
+// = (x0, y0, x1, y1) and ent2_w*[2j], ent2_w*[2j + 1] (weight 0 and x = 0
+// for a missing entry); any further entries are ent_off[j] .. ent_off[j+1]-1
+// of ent_pos (pairs x, y) and ent_w*.
 struct TableLayout {
-  uint64_t tw, h0, hd, g, gd, bands, ana, syn, runs, ent_off, ent_pos, ent_wsyn, ent_wadj, total;
+  uint64_t tw, h0, hd, g, gd, bands, ana, syn, runs;
+  uint64_t ent2_pos, ent2_wsyn, ent2_wadj, ent_off, ent_pos, ent_wsyn, ent_wadj, total;
 };
 
 }  // namespace slicq

@@ -32,6 +32,9 @@ __device__ __forceinline__ C2<T> mul_mi(C2<T> a) {
   else return {-a.y, a.x};
 }
 
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+
 // LDS index with one pad slot every 16 complex values (bank spreading for the
 // strided Stockham stores).
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
@@ -106,23 +109,53 @@ __device__ __forceinline__ C2<T> twiddle(const C2<T>* __restrict__ tw, int n, in
   return w;
 }
 
-// Powers w^r, r = 1..R-1, of w = e^{DIR 2 pi i k / n}: w^1, w^2, w^4, w^8 come
-// from the table, every other power is a product of at most three of them.
-template <class T, int DIR, int R>
-__device__ __forceinline__ void twiddle_powers(const C2<T>* __restrict__ tw, int n, int k, C2<T>* w) {
-  w[1] = twiddle<T, DIR>(tw, n, k);
+// Twiddle sources for the LDS FFT; get(n, k) returns e^{-2 pi i k / n} for
+// 0 <= k < n/2. TwGlobal reads the pyramid in global memory; TwLds reads the
+// lower halves of its levels 2, 4, ..., n_max staged in LDS, level n at
+// entries n/2 - 1 .. n - 2 (n_max - 1 entries in all, contiguous per level).
+template <class T>
+struct TwGlobal {
+  const C2<T>* __restrict__ tw;
+  __device__ __forceinline__ C2<T> get(int n, int k) const { return tw[(unsigned)(n + k)]; }
+};
+
+template <class T>
+struct TwLds {
+  const C2<T>* tw;
+  __device__ __forceinline__ C2<T> get(int n, int k) const { return tw[(n >> 1) - 1 + k]; }
+};
+
+// Entry i of the TwLds table for levels up to n_max: level n = 2^(floor(log2(i + 1)) + 1),
+// k = i + 1 - n/2, read from the pyramid.
+template <class T>
+__device__ __forceinline__ C2<T> tw_stage_value(const C2<T>* __restrict__ tw, int i) {
+  const int n = 2 << (31 - __builtin_clz((unsigned)(i + 1)));
+  return tw[(unsigned)(n + i + 1 - (n >> 1))];
+}
+
+// Powers w^r, r = 1..R-1, of w = e^{DIR 2 pi i k / n}, k < n / R: w^1, w^2,
+// w^4, w^8 are read (w^r = e^{-2 pi i k / (n/r)}, contiguous in k within a
+// level), every other power is a product of at most three of them.
+template <class T, int DIR, int R, class TW>
+__device__ __forceinline__ void twiddle_powers(const TW& src, int n, int k, C2<T>* w) {
+  auto rd = [&](int m) {
+    C2<T> v = src.get(m, k);
+    if constexpr (DIR > 0) v.y = -v.y;
+    return v;
+  };
+  w[1] = rd(n);
   if constexpr (R > 2) {
-    w[2] = twiddle<T, DIR>(tw, n, 2 * k);
+    w[2] = rd(n >> 1);
     w[3] = cmul(w[1], w[2]);
   }
   if constexpr (R > 4) {
-    w[4] = twiddle<T, DIR>(tw, n, 4 * k);
+    w[4] = rd(n >> 2);
     w[5] = cmul(w[4], w[1]);
     w[6] = cmul(w[4], w[2]);
     w[7] = cmul(w[4], w[3]);
   }
   if constexpr (R > 8) {
-    w[8] = twiddle<T, DIR>(tw, n, 8 * k);
+    w[8] = rd(n >> 3);
 #pragma unroll
     for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
   }
@@ -135,36 +168,41 @@ enum Layout { CONTIG = 0, INTERLEAVED = 1 };
 // One in-place Stockham pass of radix R. Ns is the product of the radices of
 // earlier passes. Every thread reads all of its units into registers, the
 // block synchronises, then every thread writes back.
-template <class T, int DIR, int R, int LAY, int E>
+template <class T, int DIR, int R, int LAY, int E, class TW>
 __device__ __forceinline__ void stockham_pass(C2<T>* buf, int base, int logn, int Ns, int logNs,
-                                              int nseq, int lognseq, const C2<T>* __restrict__ tw,
+                                              int nseq, int lognseq, const TW& tws,
                                               int tid, int nthr) {
   constexpr int U = E / R;
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
   C2<T> v[U][R];
   const int lunits = logn - LR;            // log2 of units per sequence
   const int total = (LAY == CONTIG) ? (nseq << lunits) : (1 << (lognseq + lunits));
+  // Threads past the last unit repeat it (no branch around the reads, so the
+  // reads of all units are in flight together); only real units write back.
 #pragma unroll
   for (int i = 0; i < U; ++i) {
-    const int u = tid + i * nthr;
-    if (u < total) {
-      int s, j;
-      if constexpr (LAY == CONTIG) { s = u >> lunits; j = u & ((1 << lunits) - 1); }
-      else { s = u & ((1 << lognseq) - 1); j = u >> lognseq; }
+    const int u = imin(tid + i * nthr, total - 1);
+    int s, j;
+    if constexpr (LAY == CONTIG) { s = u >> lunits; j = u & ((1 << lunits) - 1); }
+    else { s = u & ((1 << lognseq) - 1); j = u >> lognseq; }
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int e = j + (r << lunits);
-        const int pos = (LAY == CONTIG) ? (s << logn) + e : (e << lognseq) + s;
-        v[i][r] = buf[pidx(base + pos)];
-      }
-      if (Ns > 1) {
-        C2<T> w[R];
-        twiddle_powers<T, DIR, R>(tw, Ns * R, j & (Ns - 1), w);
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
-      }
-      dft_reg<T, R, DIR>(v[i]);
+    for (int r = 0; r < R; ++r) {
+      const int e = j + (r << lunits);
+      const int pos = (LAY == CONTIG) ? (s << logn) + e : (e << lognseq) + s;
+      v[i][r] = buf[pidx(base + pos)];
     }
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    if (Ns > 1) {
+      const int u = imin(tid + i * nthr, total - 1);
+      const int j = (LAY == CONTIG) ? (u & ((1 << lunits) - 1)) : (u >> lognseq);
+      C2<T> w[R];
+      twiddle_powers<T, DIR, R>(tws, Ns * R, j & (Ns - 1), w);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
+    }
+    dft_reg<T, R, DIR>(v[i]);
   }
   __syncthreads();
 #pragma unroll
@@ -188,25 +226,36 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int base, int logn, in
 
 // Batched FFT of `nseq` sequences of length 2^logn held in LDS at padded
 // positions pidx(base + pos); INTERLEAVED needs nseq = 2^lognseq. Needs
-// nseq * n <= E * nthr. Unnormalised, DIR < 0 forward (e^-), DIR > 0
+// nseq * n <= E * nthr. Passes have radix at most RMAX (each thread holds E
+// values, E / R butterflies of radix R). Unnormalised, DIR < 0 forward (e^-), DIR > 0
 // inverse (e^+). The caller synchronises the data in; the routine ends with a
 // barrier.
-template <class T, int DIR, int LAY, int E = 16>
+template <class T, int DIR, int LAY, int E = 16, int RMAX = (E < 16 ? E : 16), class TW>
 __device__ __forceinline__ void lds_fft(C2<T>* buf, int base, int logn, int nseq, int lognseq,
-                        const C2<T>* __restrict__ tw, int tid, int nthr) {
+                        const TW& tw, int tid, int nthr) {
+  static_assert(E >= 2 && (E & (E - 1)) == 0, "E must be a power of two");
+  static_assert(RMAX >= 2 && RMAX <= E && RMAX <= 16, "largest radix must fit E");
   int Ns = 1, logNs = 0, rem = logn;
   while (rem > 0) {
-    if (rem >= 4) {
-      stockham_pass<T, DIR, 16, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
-      Ns <<= 4; logNs += 4; rem -= 4;
-    } else if (rem == 3) {
-      stockham_pass<T, DIR, 8, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
-      Ns <<= 3; logNs += 3; rem -= 3;
-    } else if (rem == 2) {
-      stockham_pass<T, DIR, 4, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+    if constexpr (RMAX >= 16) {
+      if (rem >= 4) {
+        stockham_pass<T, DIR, 16, LAY, E, TW>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+        Ns <<= 4; logNs += 4; rem -= 4;
+        continue;
+      }
+    }
+    if constexpr (RMAX >= 8) {
+      if (rem >= 3) {
+        stockham_pass<T, DIR, 8, LAY, E, TW>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+        Ns <<= 3; logNs += 3; rem -= 3;
+        continue;
+      }
+    }
+    if (RMAX >= 4 && rem >= 2) {
+      stockham_pass<T, DIR, (RMAX >= 4 ? 4 : 2), LAY, E, TW>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
       Ns <<= 2; logNs += 2; rem -= 2;
     } else {
-      stockham_pass<T, DIR, 2, LAY, E>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
+      stockham_pass<T, DIR, 2, LAY, E, TW>(buf, base, logn, Ns, logNs, nseq, lognseq, tw, tid, nthr);
       Ns <<= 1; logNs += 1; rem -= 1;
     }
   }

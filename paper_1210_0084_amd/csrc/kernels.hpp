@@ -31,8 +31,20 @@ namespace slicq {
 
 // Largest block each kernel is compiled for (its __launch_bounds__).
 constexpr int kPassThreads = 256;     // k_fwd_pass1/2, k_inv_passA/B
-constexpr int kAnaThreads = 256;      // k_band_ana
-constexpr int kSynThreads = 512;      // k_band_syn
+// Band kernels: items of at most kAnaSmallValues / kSynSmallValues values run
+// with kSmallE values per thread; larger ones with kBigAnaE / kBigSynE values
+// per thread in blocks of up to 1024 threads, all at kSmallWaves waves per
+// SIMD (FFT radix at most 8).
+constexpr int kSmallE = 8;
+constexpr int kBigAnaE = 8;
+constexpr int kBigSynE = 16;
+constexpr int kSmallWaves = 4;
+constexpr int kAnaThreads = kAnaSmallValues / kSmallE;   // k_band_ana, small items
+constexpr int kAnaBigThreads = 1024;                     // k_band_ana, large items
+constexpr int kSynThreads = kSynSmallValues / kSmallE;   // k_band_syn, small items
+constexpr int kSynBigThreads = 1024;                     // k_band_syn, large items
+static_assert(kAnaBigThreads * kBigAnaE >= 8192 && kSynBigThreads * kBigSynE >= kSynMaxValues,
+              "large work items must fit one block");
 constexpr int kPassE = 16;            // values per thread in the slice-FFT passes
 // Largest padded length and coefficient count of one signal: offsets inside a
 // signal are 32-bit.
@@ -48,25 +60,22 @@ struct KArgs {
   const AnaGroupDev* ana;
   const SynGroupDev* syn;
   const SynRunDev* runs;
-  const int32_t* ent_off; // frequency overlap-add program
+  const I4* ent2_pos;     // frequency overlap-add program: two fixed entries per bin
+  const T* ent2_w;        // their weights: dual windows (synthesis) or analysis windows (adjoint)
+  const int32_t* ent_off; // further entries of each bin
   const int2* ent_pos;
-  const T* ent_w;         // its weights: dual windows (synthesis) or analysis windows (adjoint)
-  int32_t N, Mt, K, n_ana;
-  int32_t n_syn, N1, N2, logN1;
+  const T* ent_w;
+  int32_t N, Mt, K, N1;
+  int32_t N2, logN1, pad0_, pad1_;
   int32_t logN2, C, logC, P;
   int32_t logP, zero_ola;   // zero_ola: band_syn zeroes the output overlaps
-  int32_t slice_major, cps; // coefficient layout (see coef_index), coefficients per slice
+  // coefficient layout: coefficient n of band k (packing offset off_k) of
+  // slice m sits at S off_k + m M_k + n (band-major) or m cps + off_k + n
+  // (slice-major), relative to the signal's coef_base
+  int32_t slice_major, cps;
   int64_t ws1, ws2;       // complex values per slice in the two workspace regions
   T scale;                // (2N)^{-1/2}
 };
-
-// Element index of coefficient n of band k (packing offset off_k, M_k values)
-// of the task's slice: band-major S off_k + m M_k + n, or slice-major
-// m sum_k M_k + off_k + n; both relative to the signal's coef_base.
-template <class T>
-__device__ __forceinline__ int coef_index(const KArgs<T>& a, const SliceTask& tk, int off, int M, int n) {
-  return a.slice_major ? tk.m * a.cps + off + n : tk.S * off + tk.m * M + n;
-}
 
 // Byte offset, 16-byte aligned, just past `values` padded complex values in LDS.
 template <class T>
@@ -150,7 +159,7 @@ k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict
     }
   }
   __syncthreads();
-  lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, a.tw, tid, nthr);
+  lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
@@ -250,7 +259,7 @@ k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
     if (e < total) buf[pidx(((e & (a.N1 - 1)) << logTwoP) + (e >> a.logN1))] = v[i];
   }
   __syncthreads();
-  lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, a.tw, tid, nthr);
+  lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* X = W2 + (int64_t)task * a.ws2;
   const int N = a.N, units = P * a.N1;
   constexpr int U = kPassE / 2;
@@ -282,58 +291,101 @@ k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
   }
 }
 
-// Value of the full slice spectrum at signed bin j from the half spectrum.
+// Stages the TwLds table for FFT lengths up to n (n - 1 entries) at twl:
+// each thread issues up to 8 loads before writing any of them.
 template <class T>
-__device__ __forceinline__ C2<T> spec_at(const C2<T>* __restrict__ X, int j, int N) {
-  if (j < 0) return cconj(X[-j]);
-  if (j > N) return cconj(X[2 * N - j]);
-  return X[j];
+__device__ __forceinline__ void stage_twiddles(C2<T>* twl, const C2<T>* __restrict__ tw, int n, int tid, int nthr) {
+  for (int b = tid; b < n - 1; b += 8 * nthr) {
+    C2<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = tw_stage_value(tw, imin(b + q * nthr, n - 2));
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (b + q * nthr < n - 1) twl[b + q * nthr] = v[q];
+  }
 }
 
 // Band analysis: bands k0 .. k0 + cnt - 1 of one slice. Slot r of band k
 // holds X[j] g_k[j] for the bin j of J_k with j = r (mod M_k), or 0; the
-// inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff).
-template <class T, int E>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef) {
+// inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff). Bins
+// outside [0, N] read the half spectrum by conjugate symmetry.
+// Block b takes work item g0 + b mod ng of task b / ng. TWL stages the
+// twiddles of lengths up to M in LDS.
+// LDS: values (padded) | per band (start, len, goff) | twiddles.
+template <class T, int E, int NT, int WPE, bool TWL>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef,
+           int g0, int ng) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  const int task = blockIdx.x / a.n_ana, gi = blockIdx.x - task * a.n_ana;
+  const int task = blockIdx.x / ng, gi = g0 + (int)blockIdx.x - task * ng;
   const AnaGroupDev G = a.ana[gi];
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = G.cnt << G.logM, mask = G.M - 1;
-  BandDev* bd = reinterpret_cast<BandDev*>(smem + lds_tail_offset<T>(total));
-  for (int b = tid; b < G.cnt; b += nthr) bd[b] = a.bands[G.k0 + b];
-  __syncthreads();
-  const C2<T>* X = W2 + (int64_t)task * a.ws2;
-  C2<T> v[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = tid + i * nthr;
-    v[i] = {T(0), T(0)};
-    if (e < total) {
-      const BandDev B = bd[e >> G.logM];
-      const int t = ((e & mask) - B.start) & mask;
-      if (t < B.len) v[i] = cscale(spec_at(X, B.start + t, a.N), a.g[B.goff + t]);
+  I4* bd = reinterpret_cast<I4*>(smem + lds_tail_offset<T>(total));
+  C2<T>* twl = reinterpret_cast<C2<T>*>(bd + G.cnt);
+  {
+    const BandDev B = a.bands[G.k0 + imin(tid, G.cnt - 1)];
+    if constexpr (TWL) stage_twiddles(twl, a.tw, G.M, tid, nthr);
+    if (tid < G.cnt) bd[tid] = {B.start, B.len, B.goff, 0};
+    for (int b = tid + nthr; b < G.cnt; b += nthr) {
+      const BandDev B2 = a.bands[G.k0 + b];
+      bd[b] = {B2.start, B2.len, B2.goff, 0};
     }
   }
+  __syncthreads();
+  // gather: all addresses first (no branches), then every load, then the products
+  const C2<T>* __restrict__ X = W2 + (int64_t)task * a.ws2;
+  int xi[E], wi[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = imin(tid + i * nthr, total - 1);
+    const I4 B = bd[e >> G.logM];
+    const int t = ((e & mask) - B.x) & mask;
+    const int j = B.x + t;                               // signed bin, -N < j < 2N
+    const bool in = tid + i * nthr < total && t < B.y;
+    const int jj = j < 0 ? -j : (j > a.N ? 2 * a.N - j : j);
+    const bool cj = j < 0 || j > a.N;
+    xi[i] = in ? (cj ? ~jj : jj) : 0;                    // ~jj (< 0) marks a conjugate
+    wi[i] = in ? B.z + t : -1;
+  }
+  C2<T> xv[E];
+  T gv[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    xv[i] = X[xi[i] < 0 ? ~xi[i] : xi[i]];
+    gv[i] = a.g[imax(wi[i], 0)];
+  }
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int e = tid + i * nthr;
-    if (e < total) buf[pidx(e)] = v[i];
+    if (e < total) {
+      const T w = wi[i] < 0 ? T(0) : gv[i];
+      buf[pidx(e)] = {xv[i].x * w, (xi[i] < 0 ? -xv[i].y : xv[i].y) * w};
+    }
   }
   __syncthreads();
-  lds_fft<T, 1, CONTIG, E>(buf, 0, G.logM, G.cnt, 0, a.tw, tid, nthr);
+  if constexpr (TWL) lds_fft<T, 1, CONTIG, E, 8>(buf, 0, G.logM, G.cnt, 0, TwLds<T>{twl}, tid, nthr);
+  else lds_fft<T, 1, CONTIG, E, 8>(buf, 0, G.logM, G.cnt, 0, TwGlobal<T>{a.tw}, tid, nthr);
+  // bands k0.. are consecutive with equal M: off_k = off_k0 + (k - k0) M
   C2<T>* __restrict__ cs = coef + tk.coef_base;
+  const int off0 = a.bands[G.k0].off;
+  const int base = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * G.M;
+  const int bstride = a.slice_major ? G.M : tk.S * G.M;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int e = tid + i * nthr;
-    if (e < total) {
-      cs[coef_index(a, tk, bd[e >> G.logM].off, G.M, e & mask)] = buf[pidx(e)];
-    }
+    if (e < total) cs[base + (e >> G.logM) * bstride + (e & mask)] = buf[pidx(e)];
   }
+}
+
+// Element index of LDS position p of a synthesis item inside run R: band
+// k0 + q / M, coefficient q mod M, q = p - lds_off (band-major layout).
+__device__ __forceinline__ int run_coef_index(const SliceTask& tk, const SynRunDev& R, int p) {
+  const int q = p - R.lds_off;
+  return tk.S * (R.off + (q >> R.logM) * R.M) + tk.m * R.M + (q & (R.M - 1));
 }
 
 // Band synthesis: owned bins [lo, hi) of the half spectrum of one slice.
@@ -341,22 +393,22 @@ k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
 // owned bin runs its overlap-add program: the sum over the bands covering it,
 // in increasing k, of weight * C_k[j mod M_k] (for the self-mirrored DC and
 // Nyquist bands weight * (C[j mod M] + conj C[-j mod M]), the real part of the
-// full synthesis).
-template <class T, int E>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+// full synthesis). Block b takes work item g0 + b mod ng of task b / ng; item
+// 0 also clears the slice's output overlap. TWL stages the twiddles in LDS.
+// LDS: values (padded) | twiddles.
+template <class T, int E, int NT, int WPE, bool TWL>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ coef, C2<T>* __restrict__ W2,
-           T* __restrict__ y) {
+           T* __restrict__ y, int g0, int ng) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  const int task = blockIdx.x / a.n_syn, gi = blockIdx.x - task * a.n_syn;
+  const int task = blockIdx.x / ng, gi = g0 + (int)blockIdx.x - task * ng;
   const SynGroupDev G = a.syn[gi];
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int nb = G.kb - G.ke + 1;
+  C2<T>* twl = reinterpret_cast<C2<T>*>(smem + lds_tail_offset<T>(G.total));
   const C2<T>* __restrict__ cs = coef + tk.coef_base;
-  int* boff = reinterpret_cast<int*>(smem + lds_tail_offset<T>(G.total));   // off_k of bands ke..kb
-  for (int b = tid; b < nb; b += nthr) boff[b] = a.bands[G.ke + b].off;
   if (gi == 0 && a.zero_ola && (tk.flags & 1)) {
     // zero the right-hand overlap of this slice in the output, which the
     // inverse pass then accumulates into from this slice and the next
@@ -367,65 +419,74 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       if (idx < tk.y_valid) y[tk.y_base + idx] = T(0);
     }
   }
-  __syncthreads();
-  for (int ri = 0; ri < G.nrun; ++ri) {
-    const SynRunDev R = a.runs[G.run0 + ri];
-    const int tot = R.cnt << R.logM;
-    C2<T> v[E];
+  // coefficient addresses of a batch of values (no branches), then every load
+  // of the batch; batches of 8 values per thread bound the registers
+  const SynRunDev R0 = a.runs[G.run0];
+  constexpr int EB = E < 8 ? E : 8;
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = tid + i * nthr;
-      if (e < tot) {
-        const int b = R.k0 - G.ke + (e >> R.logM);
-        v[i] = cs[coef_index(a, tk, boff[b], R.M, e & (R.M - 1))];
+  for (int c = 0; c < E; c += EB) {
+    int idx[EB];
+    if (a.slice_major) {
+#pragma unroll
+      for (int i = 0; i < EB; ++i) idx[i] = tk.m * a.cps + R0.off + imin(tid + (c + i) * nthr, G.total - 1);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EB; ++i) idx[i] = run_coef_index(tk, R0, imin(tid + (c + i) * nthr, G.total - 1));
+      for (int r = 1; r < G.nrun; ++r) {
+        const SynRunDev R = a.runs[G.run0 + r];
+#pragma unroll
+        for (int i = 0; i < EB; ++i) {
+          const int p = imin(tid + (c + i) * nthr, G.total - 1);
+          if (p >= R.lds_off) idx[i] = run_coef_index(tk, R, p);
+        }
       }
     }
+    C2<T> v[EB];
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = tid + i * nthr;
-      if (e < tot) buf[pidx(R.lds_off + e)] = v[i];
+    for (int i = 0; i < EB; ++i) v[i] = cs[idx[i]];
+    if constexpr (TWL) {
+      if (c == 0) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int p = tid + (c + i) * nthr;
+      if (p < G.total) buf[pidx(p)] = v[i];
     }
   }
   __syncthreads();
   for (int ri = 0; ri < G.nrun; ++ri) {
     const SynRunDev R = a.runs[G.run0 + ri];
-    lds_fft<T, -1, CONTIG, E>(buf, R.lds_off, R.logM, R.cnt, 0, a.tw, tid, nthr);
+    if constexpr (TWL) lds_fft<T, -1, CONTIG, E, 8>(buf, R.lds_off, R.logM, R.cnt, 0, TwLds<T>{twl}, tid, nthr);
+    else lds_fft<T, -1, CONTIG, E, 8>(buf, R.lds_off, R.logM, R.cnt, 0, TwGlobal<T>{a.tw}, tid, nthr);
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;
+  const C2<T>* __restrict__ w2 = reinterpret_cast<const C2<T>*>(a.ent2_w);
   for (int j0 = G.lo; j0 < G.hi; j0 += 4 * nthr) {
-    int e0[4], e1[4];
+    I4 ps[4];
+    C2<T> ws[4];
+    int eo[4], ee[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int j = j0 + tid + q * nthr;
-      e0[q] = e1[q] = 0;
-      if (j < G.hi) {
-        e0[q] = a.ent_off[j];
-        e1[q] = a.ent_off[j + 1];
-      }
+      const int j = imin(j0 + tid + q * nthr, G.hi - 1);
+      ps[q] = a.ent2_pos[j];
+      ws[q] = w2[j];
+      eo[q] = a.ent_off[j];
+      ee[q] = a.ent_off[j + 1];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = j0 + tid + q * nthr;
       if (j >= G.hi) continue;
-      C2<T> acc = {T(0), T(0)};
-      for (int e = e0[q]; e < e1[q]; e += 4) {
-        int2 ps[4];
-        T ws[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (e + u < e1[q]) {
-            ps[u] = a.ent_pos[e + u];
-            ws[u] = a.ent_w[e + u];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (e + u < e1[q]) {
-            C2<T> c = buf[pidx(ps[u].x)];
-            if (ps[u].y >= 0) c = cadd(c, cconj(buf[pidx(ps[u].y)]));
-            acc = cadd(acc, cscale(c, ws[u]));
-          }
-        }
+      C2<T> c0 = buf[pidx(ps[q].x)], c1 = buf[pidx(ps[q].z)];
+      const C2<T> m0 = buf[pidx(imax(ps[q].y, 0))], m1 = buf[pidx(imax(ps[q].w, 0))];
+      if (ps[q].y >= 0) c0 = cadd(c0, cconj(m0));
+      if (ps[q].w >= 0) c1 = cadd(c1, cconj(m1));
+      C2<T> acc = cadd(cscale(c0, ws[q].x), cscale(c1, ws[q].y));
+      for (int e = eo[q]; e < ee[q]; ++e) {        // bins covered by more than two bands
+        const int2 pe = a.ent_pos[e];
+        C2<T> c = buf[pidx(pe.x)];
+        if (pe.y >= 0) c = cadd(c, cconj(buf[pidx(pe.y)]));
+        acc = cadd(acc, cscale(c, a.ent_w[e]));
       }
       Z[j] = acc;
     }
@@ -489,7 +550,7 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
     }
   }
   __syncthreads();
-  lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, a.tw, tid, nthr);
+  lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
   const int total = twoP * N1;
   C2<T> tw[kPassE];
@@ -555,7 +616,7 @@ k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __rest
     if (e < total) buf[pidx(e)] = v[i];
   }
   __syncthreads();
-  lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, a.tw, tid, nthr);
+  lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
   T* __restrict__ ys = y + tk.y_base;
   const int ys0 = (int)tk.y_start, yper = (int)tk.y_period, yval = (int)tk.y_valid;
   C2<T> h[kPassE];

@@ -78,14 +78,14 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
   a.ana = reinterpret_cast<const AnaGroupDev*>(base + L.ana);
   a.syn = reinterpret_cast<const SynGroupDev*>(base + L.syn);
   a.runs = reinterpret_cast<const SynRunDev*>(base + L.runs);
+  a.ent2_pos = reinterpret_cast<const I4*>(base + L.ent2_pos);
+  a.ent2_w = reinterpret_cast<const T*>(base + (adjoint ? L.ent2_wadj : L.ent2_wsyn));
   a.ent_off = reinterpret_cast<const int32_t*>(base + L.ent_off);
   a.ent_pos = reinterpret_cast<const int2*>(base + L.ent_pos);
   a.ent_w = reinterpret_cast<const T*>(base + (adjoint ? L.ent_wadj : L.ent_wsyn));
   a.N = (int32_t)p.N;
   a.Mt = (int32_t)p.Mt;
   a.K = p.K;
-  a.n_ana = (int32_t)p.ana.size();
-  a.n_syn = (int32_t)p.syn.size();
   a.N1 = p.N1;
   a.N2 = p.N2;
   a.logN1 = p.logN1;
@@ -106,8 +106,16 @@ template <class T>
 struct Geometry {
   int g1, b1; size_t s1;      // forward pass 1 / inverse pass B: items per slice, threads, LDS bytes
   int g2, b2; size_t s2;      // forward pass 2 / inverse pass A
-  int ga, ba, Ea; size_t sa;  // band analysis (Ea values per thread)
-  int gs, bs, Es; size_t ss;  // band synthesis (Es values per thread)
+  // band analysis: small items [0, ga) with ba threads, E = kSmallE (kernel
+  // bound kAnaThreads), twiddles in LDS if ta; large items [ga, ga + gab) with
+  // bab threads, E = kBigAnaE (bound kAnaBigThreads)
+  int ga, ba; size_t sa; bool ta;
+  int gab, bab; size_t sab;
+  // band synthesis: small items [0, gs), bs threads, E = kSmallE (bound
+  // kSynThreads), twiddles in LDS if ts; large items [gs, gs + gsb), bsb
+  // threads, E = kBigSynE (bound kSynBigThreads)
+  int gs, bs; size_t ss; bool ts;
+  int gsb, bsb; size_t ssb;
   bool ok;                    // every block fits its kernel's launch bound
 };
 
@@ -121,19 +129,58 @@ Geometry<T> geometry(const Plan& p) {
   g.g2 = (p.N2 / 2) / p.P;
   g.b2 = threads_for((int64_t)2 * p.P * p.N1);
   g.s2 = padded(2 * p.P * p.N1) * cb;
-  g.ga = (int)p.ana.size();
-  g.Ea = p.ana_cap > 16 * kAnaThreads ? 32 : 16;
-  g.ba = threads_for(p.ana_cap, g.Ea);
-  g.sa = lds_tail_offset<T>(p.ana_cap) + 256 * sizeof(BandDev);
-  g.gs = (int)p.syn.size();
-  g.Es = p.syn_cap > 16 * 512 ? 32 : 16;
-  g.bs = threads_for(p.syn_cap, g.Es);
-  g.ss = lds_tail_offset<T>(p.syn_cap) + (size_t)p.syn_bands * sizeof(int);
-  g.ok = g.b1 <= kPassThreads && g.b2 <= kPassThreads && g.ba <= kAnaThreads && g.bs <= kSynThreads &&
-         (int64_t)p.C * p.N2 <= 16LL * g.b1 && 2LL * p.P * p.N1 <= 16LL * g.b2 &&
-         p.ana_cap <= g.Ea * g.ba && p.syn_cap <= g.Es * g.bs &&
-         std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss)) <= kMaxLdsBytes;
+  const size_t band_tail = (size_t)kMaxGroupBands * sizeof(I4);
+  g.ga = p.ana_small;
+  g.ba = threads_for(std::max(p.ana_cap_small, 1), kSmallE);
+  g.sa = lds_tail_offset<T>(p.ana_cap_small) + band_tail;
+  g.ta = g.sa + (size_t)p.ana_maxM_small * cb <= kMaxLdsBytes;
+  if (g.ta) g.sa += (size_t)p.ana_maxM_small * cb;
+  g.gab = (int)p.ana.size() - p.ana_small;
+  g.bab = threads_for(std::max(p.ana_cap_big, 1), kBigAnaE);
+  g.sab = lds_tail_offset<T>(p.ana_cap_big) + band_tail;
+  g.gs = p.syn_small;
+  g.bs = threads_for(std::max(p.syn_cap_small, 1), kSmallE);
+  g.ss = lds_tail_offset<T>(p.syn_cap_small);
+  g.ts = g.ss + (size_t)p.syn_maxM_small * cb <= kMaxLdsBytes;
+  if (g.ts) g.ss += (size_t)p.syn_maxM_small * cb;
+  g.gsb = (int)p.syn.size() - p.syn_small;
+  g.bsb = threads_for(std::max(p.syn_cap_big, 1), kBigSynE);
+  g.ssb = lds_tail_offset<T>(p.syn_cap_big);
+  size_t lds = std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss));
+  if (g.gab) lds = std::max(lds, g.sab);
+  if (g.gsb) lds = std::max(lds, g.ssb);
+  g.ok = g.b1 <= kPassThreads && g.b2 <= kPassThreads && (int64_t)p.C * p.N2 <= 16LL * g.b1 &&
+         2LL * p.P * p.N1 <= 16LL * g.b2 &&
+         g.ba <= kAnaThreads && p.ana_cap_small <= kSmallE * g.ba &&
+         (g.gab == 0 || (g.bab <= kAnaBigThreads && p.ana_cap_big <= kBigAnaE * g.bab)) &&
+         g.bs <= kSynThreads && p.syn_cap_small <= kSmallE * g.bs &&
+         (g.gsb == 0 || (g.bsb <= kSynBigThreads && p.syn_cap_big <= kBigSynE * g.bsb)) &&
+         lds <= kMaxLdsBytes;
   return g;
+}
+
+// Band analysis of cnt tasks: one launch per work-item class.
+template <class T, class Launch>
+void launch_band_ana(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
+                     const C2<T>* W2, C2<T>* coef, Launch& L) {
+  if (g.ga) {
+    if (g.ta) L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, true>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0, g.ga);
+    else L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, false>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0, g.ga);
+  }
+  if (g.gab)
+    L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, false>, cnt * g.gab, g.bab, g.sab, a, tasks, W2, coef, g.ga, g.gab);
+}
+
+// Band synthesis (dual or adjoint) of cnt tasks: one launch per work-item class.
+template <class T, class Launch>
+void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
+                     const C2<T>* coef, C2<T>* W2, T* y, Launch& L) {
+  if (g.gs) {
+    if (g.ts) L.launch(k_band_syn<T, kSmallE, kSynThreads, kSmallWaves, true>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
+    else L.launch(k_band_syn<T, kSmallE, kSynThreads, kSmallWaves, false>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
+  }
+  if (g.gsb)
+    L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
 }
 
 // Analysis of tasks [t0, t0 + cnt) (Algorithm 3): slice FFT, band transforms.
@@ -142,8 +189,7 @@ void launch_analysis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, con
                      int64_t cnt, const T* x, C2<T>* coef, C2<T>* W1, C2<T>* W2, Launch& L) {
   L.launch(k_fwd_pass1<T>, cnt * g.g1, g.b1, g.s1, a, tasks, x, W1);
   L.launch(k_fwd_pass2<T>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2);
-  if (g.Ea == 16) L.launch(k_band_ana<T, 16>, cnt * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, coef);
-  else L.launch(k_band_ana<T, 32>, cnt * g.ga, g.ba, g.sa, a, tasks, (const C2<T>*)W2, coef);
+  launch_band_ana(a, g, tasks, cnt, (const C2<T>*)W2, coef, L);
   (void)p;
 }
 
@@ -151,8 +197,7 @@ void launch_analysis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, con
 template <class T, class Launch>
 void launch_synthesis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks,
                       int64_t cnt, const C2<T>* coef, T* y, C2<T>* W1, C2<T>* W2, Launch& L) {
-  if (g.Es == 16) L.launch(k_band_syn<T, 16>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y);
-  else L.launch(k_band_syn<T, 32>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y);
+  launch_band_syn(a, g, tasks, cnt, coef, W2, y, L);
   L.launch(k_inv_passA<T>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1);
   L.launch(k_inv_passB<T>, cnt * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, y);
   (void)p;

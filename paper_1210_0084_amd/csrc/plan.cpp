@@ -21,7 +21,6 @@ namespace slicq {
 
 namespace {
 
-constexpr int kMaxGroupBands = 256;   // band descriptors one work item stages in LDS
 
 int64_t next_pow2(int64_t n) {
   int64_t p = 1;
@@ -134,11 +133,11 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     err = "min_win must be >= 0, dual_kind and coef_layout 0 or 1";
     return -1;
   }
-  if (p.group_cap < 16 || p.group_cap > 4096 || p.lds_cap < p.group_cap || p.lds_cap > 16384 ||
+  if (p.group_cap < 16 || p.group_cap > 4096 || p.lds_cap < 64 || p.lds_cap > kSynMaxValues ||
       p.pass_cap < 64 || p.pass_cap > 4096 ||
       (p.group_cap & (p.group_cap - 1)) || (p.pass_cap & (p.pass_cap - 1))) {
     err = "group_cap and pass_cap must be powers of two in [16, 4096] and [64, 4096], "
-          "lds_cap in [group_cap, 16384]";
+          "lds_cap in [64, 16384]";
     return -1;
   }
   out.prm = p;
@@ -253,10 +252,9 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     out.bands.push_back(b);
   }
   out.coefs_per_slice = off;
-  if (out.max_M > p.lds_cap - 2 * 256 || out.max_M > 8192) {
+  if (out.max_M > 8192) {
     std::snprintf(msg, sizeof msg, "a band needs M_k = %d coefficients per slice; "
-                  "the single-workgroup band transforms support up to %d", out.max_M,
-                  std::min(8192, p.lds_cap - 512));
+                  "the single-workgroup band transforms support up to 8192", out.max_M);
     err = msg;
     return -1;
   }
@@ -350,12 +348,14 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
       int64_t extra = out.bands[k].off - out.bands[ke].off;
       int cnt = 1;
       const int M = out.bands[k].M;
-      while (k + cnt < K + 2 && out.bands[k + cnt].M == M && (cnt + 1) * M <= p.group_cap &&
+      // own bands are added while the item stays within lds_cap values; the
+      // first one is always taken (its item may exceed lds_cap up to kSynMaxValues)
+      while (k + cnt < K + 2 && out.bands[k + cnt].M == M &&
              extra + (int64_t)(cnt + 1) * M <= p.lds_cap && k + cnt - ke < kMaxGroupBands)
         ++cnt;
-      if (extra + (int64_t)cnt * M > p.lds_cap || k + cnt - ke > kMaxGroupBands) {
-        std::snprintf(msg, sizeof msg, "bins near band %d need more than %d coefficients in one "
-                      "synthesis work item; raise lds_cap", k, p.lds_cap);
+      if (extra + (int64_t)cnt * M > kSynMaxValues || k + cnt - ke > kMaxGroupBands) {
+        std::snprintf(msg, sizeof msg, "bins near band %d need more than %d coefficients or %d bands in "
+                      "one synthesis work item", k, kSynMaxValues, kMaxGroupBands);
         err = msg;
         return -1;
       }
@@ -378,6 +378,7 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
         r.M = out.bands[k].M;
         r.logM = out.bands[k].logM;
         r.lds_off = (int32_t)(out.bands[k].off - out.bands[ke].off);
+        r.off = (int32_t)out.bands[k].off;
         int c = 1;
         while (k + c <= kb && out.bands[k + c].M == r.M) ++c;
         r.cnt = c;
@@ -385,10 +386,48 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
         k += c;
       }
       s.nrun = (int32_t)out.runs.size() - s.run0;
+      if (s.nrun > kMaxRuns) {
+        std::snprintf(msg, sizeof msg, "bins near band %d span %d different M_k (at most %d)", ka, s.nrun,
+                      kMaxRuns);
+        err = msg;
+        return -1;
+      }
+      s.maxM = 0;
+      for (int r = s.run0; r < s.run0 + s.nrun; ++r) s.maxM = std::max(s.maxM, out.runs[r].M);
       s.total = (int32_t)(out.bands[kb].off + out.bands[kb].M - out.bands[ke].off);
       out.syn_cap = std::max(out.syn_cap, s.total);
       out.syn_bands = std::max(out.syn_bands, kb - ke + 1);
       out.syn.push_back(s);
+    }
+  }
+
+  // small work items first, then the large ones (each class is one launch)
+  {
+    auto ana_big = [](const AnaGroupDev& G) { return (G.cnt << G.logM) > kAnaSmallValues; };
+    auto syn_big = [](const SynGroupDev& G) { return G.total > kSynSmallValues; };
+    std::stable_partition(out.ana.begin(), out.ana.end(), [&](const AnaGroupDev& G) { return !ana_big(G); });
+    std::stable_partition(out.syn.begin(), out.syn.end(), [&](const SynGroupDev& G) { return !syn_big(G); });
+    out.ana_small = out.syn_small = 0;
+    out.ana_cap_small = out.ana_cap_big = out.syn_cap_small = out.syn_cap_big = 0;
+    out.ana_maxM_small = out.syn_maxM_small = 0;
+    for (const AnaGroupDev& G : out.ana) {
+      const int32_t v = G.cnt << G.logM;
+      if (ana_big(G)) {
+        out.ana_cap_big = std::max(out.ana_cap_big, v);
+      } else {
+        ++out.ana_small;
+        out.ana_cap_small = std::max(out.ana_cap_small, v);
+        out.ana_maxM_small = std::max(out.ana_maxM_small, G.M);
+      }
+    }
+    for (const SynGroupDev& G : out.syn) {
+      if (syn_big(G)) {
+        out.syn_cap_big = std::max(out.syn_cap_big, G.total);
+      } else {
+        ++out.syn_small;
+        out.syn_cap_small = std::max(out.syn_cap_small, G.total);
+        out.syn_maxM_small = std::max(out.syn_maxM_small, G.maxM);
+      }
     }
   }
 
@@ -398,11 +437,16 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
   out.ent_pos.clear();
   out.ent_wsyn.clear();
   out.ent_wadj.clear();
+  out.ent2_pos.assign(4 * (N + 1), 0);
+  out.ent2_wsyn.assign(2 * (N + 1), 0.0);
+  out.ent2_wadj.assign(2 * (N + 1), 0.0);
+  for (int64_t j = 0; j <= N; ++j) out.ent2_pos[4 * j + 1] = out.ent2_pos[4 * j + 3] = -1;
   for (const SynGroupDev& G : out.syn) {
     const int64_t base = out.bands[G.ke].off;
     for (int64_t j = G.lo; j < G.hi; ++j) {
       out.ent_off[j] = (int32_t)out.ent_wsyn.size();
-      for (int k = out.bin_k0[j]; k < out.bin_k0[j] + out.bin_nk[j]; ++k) {
+      int slot = 0;
+      for (int k = out.bin_k0[j]; k < out.bin_k0[j] + out.bin_nk[j]; ++k, ++slot) {
         const BandInfo& b = out.bands[k];
         if (k < G.ke || k > G.kb) {
           err = "synthesis work item misses a band covering one of its bins";
@@ -411,10 +455,20 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
         const int64_t lds = b.off - base;
         const int64_t t = j - b.start;
         const bool selfmirror = (k == 0 || k == K + 1);
-        out.ent_pos.push_back((int32_t)(lds + (j & (b.M - 1))));
-        out.ent_pos.push_back(selfmirror ? (int32_t)(lds + ((-j) & (b.M - 1))) : -1);
-        out.ent_wsyn.push_back((selfmirror ? 0.5 : 1.0) * out.gd[b.goff + t]);
-        out.ent_wadj.push_back(0.5 * out.g[b.goff + t]);
+        const int32_t px = (int32_t)(lds + (j & (b.M - 1)));
+        const int32_t py = selfmirror ? (int32_t)(lds + ((-j) & (b.M - 1))) : -1;
+        const double ws = (selfmirror ? 0.5 : 1.0) * out.gd[b.goff + t], wa = 0.5 * out.g[b.goff + t];
+        if (slot < 2) {
+          out.ent2_pos[4 * j + 2 * slot] = px;
+          out.ent2_pos[4 * j + 2 * slot + 1] = py;
+          out.ent2_wsyn[2 * j + slot] = ws;
+          out.ent2_wadj[2 * j + slot] = wa;
+        } else {
+          out.ent_pos.push_back(px);
+          out.ent_pos.push_back(py);
+          out.ent_wsyn.push_back(ws);
+          out.ent_wadj.push_back(wa);
+        }
       }
     }
   }
@@ -476,15 +530,25 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
   lay.ana = append(blob, p.ana.data(), p.ana.size());
   lay.syn = append(blob, p.syn.data(), p.syn.size());
   lay.runs = append(blob, p.runs.data(), p.runs.size());
+  lay.ent2_pos = append(blob, p.ent2_pos.data(), p.ent2_pos.size());
   lay.ent_off = append(blob, p.ent_off.data(), p.ent_off.size());
-  lay.ent_pos = append(blob, p.ent_pos.data(), p.ent_pos.size());
+  // overflow entries: keep at least one element so every table has an address
+  std::vector<int32_t> epos = p.ent_pos;
+  std::vector<double> ews = p.ent_wsyn, ewa = p.ent_wadj;
+  if (ews.empty()) { epos = {0, -1}; ews = {0.0}; ewa = {0.0}; }
+  lay.ent_pos = append(blob, epos.data(), epos.size());
   if (dtype == 0) {
-    std::vector<float> ws(p.ent_wsyn.begin(), p.ent_wsyn.end()), wa(p.ent_wadj.begin(), p.ent_wadj.end());
+    std::vector<float> w2s(p.ent2_wsyn.begin(), p.ent2_wsyn.end()), w2a(p.ent2_wadj.begin(), p.ent2_wadj.end());
+    std::vector<float> ws(ews.begin(), ews.end()), wa(ewa.begin(), ewa.end());
+    lay.ent2_wsyn = append(blob, w2s.data(), w2s.size());
+    lay.ent2_wadj = append(blob, w2a.data(), w2a.size());
     lay.ent_wsyn = append(blob, ws.data(), ws.size());
     lay.ent_wadj = append(blob, wa.data(), wa.size());
   } else {
-    lay.ent_wsyn = append(blob, p.ent_wsyn.data(), p.ent_wsyn.size());
-    lay.ent_wadj = append(blob, p.ent_wadj.data(), p.ent_wadj.size());
+    lay.ent2_wsyn = append(blob, p.ent2_wsyn.data(), p.ent2_wsyn.size());
+    lay.ent2_wadj = append(blob, p.ent2_wadj.data(), p.ent2_wadj.size());
+    lay.ent_wsyn = append(blob, ews.data(), ews.size());
+    lay.ent_wadj = append(blob, ewa.data(), ewa.size());
   }
   blob.resize((blob.size() + 255) & ~size_t(255));
   lay.total = blob.size();

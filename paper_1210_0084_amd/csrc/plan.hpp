@@ -17,8 +17,8 @@ struct PlanParams {
   int64_t transition = 0;       // M of the Tukey window
   double min_win = 16.0;        // minimal filter length in bins
   int32_t dual_kind = 0;        // 0: canonical dual slice window, 1: indicator of supp h_0
-  int32_t group_cap = 2048;     // coefficients per band work item (own bands)
-  int32_t lds_cap = 9216;       // complex values a synthesis work item may hold
+  int32_t group_cap = 2048;     // coefficients per analysis work item
+  int32_t lds_cap = 4096;       // target complex values per synthesis work item
   int32_t pass_cap = 4096;      // complex values per four-step FFT work item
   int32_t coef_layout = 0;      // 0: band-major, 1: slice-major
 };
@@ -45,7 +45,11 @@ struct Plan {
   std::vector<double> D;                // frame-operator diagonal, 2N bins
   std::vector<double> h0, hd;           // slicing window and dual, index j = t + N
   std::vector<int32_t> bin_k0, bin_nk;  // bands covering each bin of [0, N]
-  std::vector<int32_t> ent_off;         // frequency overlap-add program (see TableLayout)
+  // frequency overlap-add program (see TableLayout): two fixed entries per
+  // bin, then the rest of each bin's entries
+  std::vector<int32_t> ent2_pos;        // (x0, y0, x1, y1) per bin
+  std::vector<double> ent2_wsyn, ent2_wadj;
+  std::vector<int32_t> ent_off;
   std::vector<int32_t> ent_pos;         // pairs (x, y)
   std::vector<double> ent_wsyn, ent_wadj;
   int64_t coefs_per_slice = 0;
@@ -57,6 +61,12 @@ struct Plan {
   std::vector<SynRunDev> runs;
   int32_t ana_cap = 0, syn_cap = 0;     // largest work item, complex values
   int32_t syn_bands = 0;                // most bands in one synthesis work item
+  // Work items are ordered small first: ana[0, ana_small) hold at most
+  // kAnaSmallValues values, the rest more (likewise syn / kSynSmallValues).
+  // The two classes launch as separate kernels sized for each.
+  int32_t ana_small = 0, syn_small = 0;
+  int32_t ana_cap_small = 0, ana_cap_big = 0, syn_cap_small = 0, syn_cap_big = 0;
+  int32_t ana_maxM_small = 0, syn_maxM_small = 0;   // largest M_k in the small items
   int32_t N1 = 0, N2 = 0, logN1 = 0, logN2 = 0;
   int32_t C = 0, P = 0;                 // columns per pass-1 item, row pairs per pass-2 item
 

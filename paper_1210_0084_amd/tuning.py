@@ -1,8 +1,8 @@
 """Work-item autotuner and HIP-graph capture for batched sliCQ calls.
 
 The plan's tuning options choose how the kernels cut the work: the number of
-own-band coefficients per band work item (``group_cap``), the complex values
-a synthesis work item may hold (``lds_cap``), the values per slice-FFT work
+coefficients per analysis work item (``group_cap``), the target complex values
+per synthesis work item (``lds_cap``), the values per slice-FFT work
 item (``pass_cap``) and the coefficient layout. ``autotune`` times every
 candidate on the caller's batch shape with HIP events (content does not
 change the time of the transform) and returns the fastest, cached on disk
@@ -16,12 +16,10 @@ import os
 from typing import Dict, Optional, Sequence
 
 CANDIDATES = [
-    dict(group_cap=g, pass_cap=p, lds_cap=l, layout=lay)
+    dict(group_cap=g, pass_cap=p, lds_cap=l, layout="band")
     for g in (1024, 2048, 4096)
     for p in (2048, 4096)
-    for l in (4096, 9216)
-    for lay in ("band",)
-    if l >= g
+    for l in (2048, 4096, 8192)
 ]
 
 
