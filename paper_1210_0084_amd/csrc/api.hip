@@ -626,16 +626,16 @@ int slicq_profile_stage(slicq_plan plan, slicq_dtype dt, int stage, int64_t n_sl
     C2<T>* W2 = reinterpret_cast<C2<T>*>(wk + w.w2_off);
     const int64_t n = n_slices;
     switch (stage) {
-      case 0: L.launch(k_fwd_pass1<T>, n * g.g1, g.b1, g.s1, a, tasks, static_cast<const T*>(x), W1); break;
-      case 1: L.launch(k_fwd_pass2<T>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2); break;
+      case 0: L.launch(k_fwd_pass1<T, true>, n * g.g1, g.b1, g.s1, a, tasks, static_cast<const T*>(x), W1); break;
+      case 1: L.launch(k_fwd_pass2<T, true>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2); break;
       case 2:
         launch_band_ana(a, g, tasks, n, (const C2<T>*)W2, static_cast<C2<T>*>(coef), L);
         break;
       case 3:
         launch_band_syn(a, g, tasks, n, (const C2<T>*)coef, W2, static_cast<T*>(y), L);
         break;
-      case 4: L.launch(k_inv_passA<T>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1); break;
-      default: L.launch(k_inv_passB<T>, n * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, static_cast<T*>(y)); break;
+      case 4: L.launch(k_inv_passA<T, true>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1); break;
+      default: L.launch(k_inv_passB<T, true>, n * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, static_cast<T*>(y)); break;
     }
   };
   if (dt == SLICQ_F32) go(float{});

@@ -30,7 +30,7 @@
 namespace slicq {
 
 // Largest block each kernel is compiled for (its __launch_bounds__).
-constexpr int kPassThreads = 256;     // k_fwd_pass1/2, k_inv_passA/B
+constexpr int kPassThreads = 512;     // k_fwd_pass1/2, k_inv_passA/B (largest block)
 // Band kernels: items of at most kAnaSmallValues / kSynSmallValues values run
 // with kSmallE values per thread; larger ones with kBigAnaE / kBigSynE values
 // per thread in blocks of up to 1024 threads, all at kSmallWaves waves per
@@ -45,7 +45,8 @@ constexpr int kSynThreads = kSynSmallValues / kSmallE;   // k_band_syn, small it
 constexpr int kSynBigThreads = 1024;                     // k_band_syn, large items
 static_assert(kAnaBigThreads * kBigAnaE >= 8192 && kSynBigThreads * kBigSynE >= kSynMaxValues,
               "large work items must fit one block");
-constexpr int kPassE = 16;            // values per thread in the slice-FFT passes
+constexpr int kPassE = 8;             // values per thread in the slice-FFT passes
+constexpr int kPassWaves = 4;         // their waves per SIMD
 // Largest padded length and coefficient count of one signal: offsets inside a
 // signal are 32-bit.
 constexpr int64_t kMaxSignalElems = 0x7fffffffLL;
@@ -119,9 +120,12 @@ __device__ __forceinline__ C2<T> load_sample_pair(const T* __restrict__ xs, cons
 // Forward FFT of a slice, pass 1: columns. The N complex values
 // z[n] = x_m[2n] + i x_m[2n+1] are indexed n = n1 + N1 n2; this item takes the
 // C columns n1 in [cb C, cb C + C), transforms each over n2 (length N2),
-// applies e^{-2 pi i n1 k2 / N} and stores W1[k2 N1 + n1].
-template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// applies e^{-2 pi i n1 k2 / N} and stores W1[k2 N1 + n1]. Samples outside
+// the support of h_0 are not read (their pair index is clamped into it and the
+// window, zero there, drops them). TWL stages the FFT twiddles in LDS.
+// LDS: values (padded) | twiddles.
+template <class T, bool TWL>
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict__ x, C2<T>* __restrict__ W1) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -131,50 +135,53 @@ k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict
   if (tk.S == 0) return;                              // unused task slot
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = a.C * a.N2;
-  const int jlo = (a.N - a.Mt) / 2 + 1;              // first non-zero sample of h_0
-  const int jhi = a.N + (a.N + a.Mt) / 2 - 1;        // last non-zero sample of h_0
+  C2<T>* twl = buf + padded(total);
+  // even sample pairs (j, j + 1) meeting the support (N-M)/2 < j - N + ... of h_0
+  const int jlo = ((a.N - a.Mt) / 2) & ~1;           // first pair touching the support
+  const int jhi = (a.N + (a.N + a.Mt) / 2 - 1) & ~1;  // last pair touching it
   const T* __restrict__ xs = x + tk.x_base;
   const SliceIn si = slice_in(tk);
-  C2<T> v[kPassE];
-  // two batches of loads keep the register budget of three waves per SIMD
+  // whole window inside the valid, unwrapped part of the signal: plain loads
+  const bool plain = si.even && si.start >= 0 && si.start + 2 * a.N <= imin(si.valid, si.period);
+  C2<T> s2[kPassE], h2[kPassE], w[kPassE];
+  if (plain) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    C2<T> s2[kPassE / 2], h2[kPassE / 2];
-#pragma unroll
-    for (int q = 0; q < kPassE / 2; ++q) {
-      const int e = tid + (h * kPassE / 2 + q) * nthr;
-      s2[q] = h2[q] = {T(0), T(0)};
-      if (e < total) {
-        const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
-        if (j + 1 >= jlo && j <= jhi) {
-          s2[q] = load_sample_pair(xs, si, j);
-          h2[q] = *reinterpret_cast<const C2<T>*>(a.h0 + j);
-        }
-      }
+    for (int i = 0; i < kPassE; ++i) {
+      const int e = imin(tid + i * nthr, total - 1);
+      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
+      s2[i] = *reinterpret_cast<const C2<T>*>(xs + si.start + imin(imax(j, jlo), jhi));
     }
+  } else {
 #pragma unroll
-    for (int q = 0; q < kPassE / 2; ++q) {
-      const int e = tid + (h * kPassE / 2 + q) * nthr;
-      if (e < total) buf[pidx(e)] = {s2[q].x * h2[q].x, s2[q].y * h2[q].y};
+    for (int i = 0; i < kPassE; ++i) {
+      const int e = imin(tid + i * nthr, total - 1);
+      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
+      s2[i] = load_sample_pair(xs, si, imin(imax(j, jlo), jhi));
     }
   }
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = imin(tid + i * nthr, total - 1);
+    const int n1 = cb * a.C + (e & (a.C - 1)), k2 = e >> a.logC;
+    h2[i] = *reinterpret_cast<const C2<T>*>(a.h0 + 2 * (n1 + a.N1 * k2));
+    w[i] = twiddle<T, -1>(a.tw, a.N, (n1 * k2) & (a.N - 1));
+  }
+  if constexpr (TWL) stage_twiddles(twl, a.tw, a.N2, tid, nthr);
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[pidx(e)] = {s2[i].x * h2[i].x, s2[i].y * h2[i].y};
+  }
   __syncthreads();
-  lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwLds<T>{twl}, tid, nthr);
+  else lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
     const int e = tid + i * nthr;
     if (e < total) {
       const int n1 = cb * a.C + (e & (a.C - 1)), k2 = e >> a.logC;
-      v[i] = twiddle<T, -1>(a.tw, a.N, (n1 * k2) & (a.N - 1));
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) {
-      const int n1 = cb * a.C + (e & (a.C - 1)), k2 = e >> a.logC;
-      out[k2 * a.N1 + n1] = cmul(buf[pidx(e)], v[i]);
+      out[k2 * a.N1 + n1] = cmul(buf[pidx(e)], w[i]);
     }
   }
 }
@@ -235,9 +242,10 @@ __device__ __forceinline__ void real_split(C2<T> za, C2<T> zb, C2<T> w, T s, C2<
 
 // Forward pass 2: rows. Each item takes P row pairs, transforms them over n1
 // (length N1), giving Zc[N2 k1 + k2], and splits pairs (k, N - k) into the
-// real spectrum X[0..N] of the slice (W2).
-template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// real spectrum X[0..N] of the slice (W2). TWL stages the FFT twiddles in LDS.
+// LDS: values (padded) | twiddles.
+template <class T, bool TWL>
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -245,34 +253,32 @@ k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
   const int task = blockIdx.x / nRB, rb = blockIdx.x - task * nRB;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int P = a.P, twoP = 2 * a.P, logTwoP = a.logP + 1;
-  const int total = twoP * a.N1;
+  const int total = twoP * a.N1, N = a.N, units = P * a.N1;
+  C2<T>* twl = buf + padded(total);
   const C2<T>* in = W1 + (int64_t)task * a.ws1;
-  C2<T> v[kPassE];
+  constexpr int U = kPassE / 2;
+  C2<T> v[kPassE], w[U];
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) v[i] = in[pass2_row(rb, e >> a.logN1, P, a.N2) * a.N1 + (e & (a.N1 - 1))];
+    const int e = imin(tid + i * nthr, total - 1);
+    v[i] = in[pass2_row(rb, e >> a.logN1, P, a.N2) * a.N1 + (e & (a.N1 - 1))];
   }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const PairIdx q = pass2_pair(imin(tid + i * nthr, units - 1), rb, P, a.logP, a.N1, a.N2, logTwoP);
+    w[i] = twiddle<T, -1>(a.tw, 2 * N, q.k);
+  }
+  const C2<T> w2 = twiddle<T, -1>(a.tw, 2 * N, N / 2);
+  if constexpr (TWL) stage_twiddles(twl, a.tw, a.N1, tid, nthr);
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
     const int e = tid + i * nthr;
     if (e < total) buf[pidx(((e & (a.N1 - 1)) << logTwoP) + (e >> a.logN1))] = v[i];
   }
   __syncthreads();
-  lds_fft<T, -1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwLds<T>{twl}, tid, nthr);
+  else lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* X = W2 + (int64_t)task * a.ws2;
-  const int N = a.N, units = P * a.N1;
-  constexpr int U = kPassE / 2;
-  C2<T> w[U], w2 = {T(0), T(0)};
-#pragma unroll
-  for (int i = 0; i < U; ++i) {
-    const int t = tid + i * nthr;
-    if (t < units) {
-      const PairIdx q = pass2_pair(t, rb, P, a.logP, a.N1, a.N2, logTwoP);
-      w[i] = twiddle<T, -1>(a.tw, 2 * N, q.k);
-      if (q.la2 >= 0) w2 = twiddle<T, -1>(a.tw, 2 * N, N / 2);
-    }
-  }
 #pragma unroll
   for (int i = 0; i < U; ++i) {
     const int t = tid + i * nthr;
@@ -506,8 +512,9 @@ __device__ __forceinline__ void herm_pack(C2<T> a, C2<T> b, C2<T> u, C2<T>& zk, 
   znk = cconj(csub(Pp, mul_mi<T, 1>(Q)));         // conj(P - iQ)
 }
 
-template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
+template <class T, bool TWL>
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -516,24 +523,27 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int P = a.P, twoP = 2 * a.P, logTwoP = a.logP + 1;
   const int N = a.N, N1 = a.N1, N2 = a.N2;
+  const int units = P * N1, total = twoP * N1;
+  C2<T>* twl = buf + padded(total);
   const C2<T>* Z = W2 + (int64_t)task * a.ws2;
-  const int units = P * N1;
   constexpr int U = kPassE / 2;
-  C2<T> za[U], zb[U], w[U], zh = {T(0), T(0)}, wh = {T(0), T(0)};
+  // every load first: spectrum pairs, their twiddles, the inter-step twiddles
+  C2<T> za[U], zb[U], w[U], tw[kPassE];
 #pragma unroll
   for (int i = 0; i < U; ++i) {
-    const int t = tid + i * nthr;
-    if (t < units) {
-      const PairIdx q = pass2_pair(t, rb, P, a.logP, N1, N2, logTwoP);
-      za[i] = Z[q.k];
-      zb[i] = Z[N - q.k];
-      w[i] = twiddle<T, 1>(a.tw, 2 * N, q.k);
-      if (q.la2 >= 0) {
-        zh = Z[N / 2];
-        wh = twiddle<T, 1>(a.tw, 2 * N, N / 2);
-      }
-    }
+    const PairIdx q = pass2_pair(imin(tid + i * nthr, units - 1), rb, P, a.logP, N1, N2, logTwoP);
+    za[i] = Z[q.k];
+    zb[i] = Z[N - q.k];
+    w[i] = twiddle<T, 1>(a.tw, 2 * N, q.k);
   }
+  const C2<T> zh = Z[N / 2], wh = twiddle<T, 1>(a.tw, 2 * N, N / 2);
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = imin(tid + i * nthr, total - 1);
+    const int row = pass2_row(rb, e >> a.logN1, P, N2);
+    tw[i] = twiddle<T, 1>(a.tw, N, ((e & (N1 - 1)) * row) & (N - 1));
+  }
+  if constexpr (TWL) stage_twiddles(twl, a.tw, N1, tid, nthr);
 #pragma unroll
   for (int i = 0; i < U; ++i) {
     const int t = tid + i * nthr;
@@ -550,18 +560,9 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
     }
   }
   __syncthreads();
-  lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwLds<T>{twl}, tid, nthr);
+  else lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
-  const int total = twoP * N1;
-  C2<T> tw[kPassE];
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) {
-      const int row = pass2_row(rb, e >> a.logN1, P, N2);
-      tw[i] = twiddle<T, 1>(a.tw, N, ((e & (N1 - 1)) * row) & (N - 1));
-    }
-  }
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
     const int e = tid + i * nthr;
@@ -591,9 +592,10 @@ __device__ __forceinline__ void ola_store(T* __restrict__ ys, int ystart, int yp
 
 // Inverse pass B: columns n1 in [cb C, cb C + C): transform over k2 (length
 // N2, e^+), giving z[n1 + N1 n2] = y[2n] + i y[2n+1]; scale, multiply by the
-// synthesis slice window and overlap-add (Algorithm 4).
-template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// synthesis slice window and overlap-add (Algorithm 4). TWL stages the FFT
+// twiddles in LDS. LDS: values (padded) | twiddles.
+template <class T, bool TWL>
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W1, T* __restrict__ y) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -603,31 +605,30 @@ k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __rest
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = a.C * a.N2;
+  C2<T>* twl = buf + padded(total);
   const C2<T>* in = W1 + (int64_t)task * a.ws1;
-  C2<T> v[kPassE];
+  C2<T> v[kPassE], h[kPassE];
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) v[i] = in[(e >> a.logC) * a.N1 + cb * a.C + (e & (a.C - 1))];
+    const int e = imin(tid + i * nthr, total - 1);
+    v[i] = in[(e >> a.logC) * a.N1 + cb * a.C + (e & (a.C - 1))];
   }
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = imin(tid + i * nthr, total - 1);
+    h[i] = *reinterpret_cast<const C2<T>*>(a.hsyn + 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC)));
+  }
+  if constexpr (TWL) stage_twiddles(twl, a.tw, a.N2, tid, nthr);
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
     const int e = tid + i * nthr;
     if (e < total) buf[pidx(e)] = v[i];
   }
   __syncthreads();
-  lds_fft<T, 1, INTERLEAVED>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwLds<T>{twl}, tid, nthr);
+  else lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
   T* __restrict__ ys = y + tk.y_base;
   const int ys0 = (int)tk.y_start, yper = (int)tk.y_period, yval = (int)tk.y_valid;
-  C2<T> h[kPassE];
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) {
-      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
-      h[i] = *reinterpret_cast<const C2<T>*>(a.hsyn + j);
-    }
-  }
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
     const int e = tid + i * nthr;

@@ -124,11 +124,11 @@ Geometry<T> geometry(const Plan& p) {
   Geometry<T> g{};
   const size_t cb = sizeof(C2<T>);
   g.g1 = p.N1 / p.C;
-  g.b1 = threads_for((int64_t)p.C * p.N2);
-  g.s1 = padded(p.C * p.N2) * cb;
+  g.b1 = threads_for((int64_t)p.C * p.N2, kPassE);
+  g.s1 = (padded(p.C * p.N2) + p.N2) * cb;          // values, twiddles up to N2
   g.g2 = (p.N2 / 2) / p.P;
-  g.b2 = threads_for((int64_t)2 * p.P * p.N1);
-  g.s2 = padded(2 * p.P * p.N1) * cb;
+  g.b2 = threads_for((int64_t)2 * p.P * p.N1, kPassE);
+  g.s2 = (padded(2 * p.P * p.N1) + p.N1) * cb;      // values, twiddles up to N1
   const size_t band_tail = (size_t)kMaxGroupBands * sizeof(I4);
   g.ga = p.ana_small;
   g.ba = threads_for(std::max(p.ana_cap_small, 1), kSmallE);
@@ -149,8 +149,8 @@ Geometry<T> geometry(const Plan& p) {
   size_t lds = std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss));
   if (g.gab) lds = std::max(lds, g.sab);
   if (g.gsb) lds = std::max(lds, g.ssb);
-  g.ok = g.b1 <= kPassThreads && g.b2 <= kPassThreads && (int64_t)p.C * p.N2 <= 16LL * g.b1 &&
-         2LL * p.P * p.N1 <= 16LL * g.b2 &&
+  g.ok = g.b1 <= kPassThreads && g.b2 <= kPassThreads && (int64_t)p.C * p.N2 <= (int64_t)kPassE * g.b1 &&
+         2LL * p.P * p.N1 <= (int64_t)kPassE * g.b2 &&
          g.ba <= kAnaThreads && p.ana_cap_small <= kSmallE * g.ba &&
          (g.gab == 0 || (g.bab <= kAnaBigThreads && p.ana_cap_big <= kBigAnaE * g.bab)) &&
          g.bs <= kSynThreads && p.syn_cap_small <= kSmallE * g.bs &&
@@ -187,8 +187,8 @@ void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* t
 template <class T, class Launch>
 void launch_analysis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks,
                      int64_t cnt, const T* x, C2<T>* coef, C2<T>* W1, C2<T>* W2, Launch& L) {
-  L.launch(k_fwd_pass1<T>, cnt * g.g1, g.b1, g.s1, a, tasks, x, W1);
-  L.launch(k_fwd_pass2<T>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2);
+  L.launch(k_fwd_pass1<T, true>, cnt * g.g1, g.b1, g.s1, a, tasks, x, W1);
+  L.launch(k_fwd_pass2<T, true>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2);
   launch_band_ana(a, g, tasks, cnt, (const C2<T>*)W2, coef, L);
   (void)p;
 }
@@ -198,8 +198,8 @@ template <class T, class Launch>
 void launch_synthesis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks,
                       int64_t cnt, const C2<T>* coef, T* y, C2<T>* W1, C2<T>* W2, Launch& L) {
   launch_band_syn(a, g, tasks, cnt, coef, W2, y, L);
-  L.launch(k_inv_passA<T>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1);
-  L.launch(k_inv_passB<T>, cnt * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, y);
+  L.launch(k_inv_passA<T, true>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1);
+  L.launch(k_inv_passB<T, true>, cnt * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, y);
   (void)p;
 }
 
