@@ -50,7 +50,7 @@ def stage_bytes(plan, n_slices: int, b: int) -> dict:
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "common.hpp"):
+    for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "common.hpp", "plan.hpp", "plan.cpp"):
         with open(os.path.join(ROOT, "paper_1210_0084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

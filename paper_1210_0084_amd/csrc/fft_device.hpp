@@ -261,4 +261,93 @@ __device__ __forceinline__ void lds_fft(C2<T>* buf, int base, int logn, int nseq
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same Stockham FFT for the CONTIG layout with the length fixed at compile
+// time (n = 2^LOGN): every stride is a constant, so the padded LDS addresses of
+// a butterfly are one computed base plus immediate offsets.
+
+// Padded position of base + r * S for a constant stride S: for S a multiple of
+// 16 the pad count grows by S / 16 per step.
+template <int S>
+__device__ __forceinline__ int pidx_step(int pb, int p0, int r) {
+  if constexpr (S % 16 == 0) return pb + r * (S + S / 16);
+  else return pidx(p0 + r * S);
+}
+
+template <class T, int DIR, int R, int E, int LOGN, int LOGNS, class TW>
+__device__ __forceinline__ void stockham_pass_c(C2<T>* buf, int base, int nseq, const TW& tws, int tid, int nthr) {
+  constexpr int U = E / R;
+  constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  constexpr int LUNITS = LOGN - LR;           // log2 of units per sequence
+  constexpr int NS = 1 << LOGNS;
+  constexpr int SREAD = 1 << LUNITS;          // read stride of a unit's values
+  const int total = nseq << LUNITS;
+  C2<T> v[U][R];
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = imin(tid + i * nthr, total - 1);
+    const int s = u >> LUNITS, j = u & (SREAD - 1);
+    const int p0 = base + (s << LOGN) + j;
+    const int pb = pidx(p0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[i][r] = buf[pidx_step<SREAD>(pb, p0, r)];
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    if constexpr (NS > 1) {
+      const int u = imin(tid + i * nthr, total - 1);
+      C2<T> w[R];
+      twiddle_powers<T, DIR, R>(tws, NS * R, u & (NS - 1), w);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
+    }
+    dft_reg<T, R, DIR>(v[i]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = tid + i * nthr;
+    if (u < total) {
+      const int s = u >> LUNITS, j = u & (SREAD - 1);
+      const int p0 = base + (s << LOGN) + ((j >> LOGNS) << (LOGNS + LR)) + (j & (NS - 1));
+      const int pb = pidx(p0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx_step<NS>(pb, p0, r)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW>
+__device__ __forceinline__ void lds_fft_c(C2<T>* buf, int base, int nseq, const TW& tw, int tid, int nthr) {
+  if constexpr (LOGNS < LOGN) {
+    constexpr int REM = LOGN - LOGNS;
+    constexpr int LR = (RMAX >= 16 && REM >= 4) ? 4 : (RMAX >= 8 && REM >= 3) ? 3 : (RMAX >= 4 && REM >= 2) ? 2 : 1;
+    stockham_pass_c<T, DIR, (1 << LR), E, LOGN, LOGNS, TW>(buf, base, nseq, tw, tid, nthr);
+    lds_fft_c<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW>(buf, base, nseq, tw, tid, nthr);
+  }
+}
+
+// Batched CONTIG FFT of nseq sequences of length 2^logn, 1 <= logn <= 13,
+// dispatched to the compile-time variant (same contract as lds_fft).
+template <class T, int DIR, int E, int RMAX, class TW>
+__device__ __forceinline__ void lds_fft_contig(C2<T>* buf, int base, int logn, int nseq, const TW& tw, int tid,
+                                               int nthr) {
+  switch (logn) {
+    case 1: lds_fft_c<T, DIR, E, RMAX, 1, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 2: lds_fft_c<T, DIR, E, RMAX, 2, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 3: lds_fft_c<T, DIR, E, RMAX, 3, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 4: lds_fft_c<T, DIR, E, RMAX, 4, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 5: lds_fft_c<T, DIR, E, RMAX, 5, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 6: lds_fft_c<T, DIR, E, RMAX, 6, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 7: lds_fft_c<T, DIR, E, RMAX, 7, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 8: lds_fft_c<T, DIR, E, RMAX, 8, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 9: lds_fft_c<T, DIR, E, RMAX, 9, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 10: lds_fft_c<T, DIR, E, RMAX, 10, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 11: lds_fft_c<T, DIR, E, RMAX, 11, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 12: lds_fft_c<T, DIR, E, RMAX, 12, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    default: lds_fft_c<T, DIR, E, RMAX, 13, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+  }
+}
+
 }  // namespace slicq

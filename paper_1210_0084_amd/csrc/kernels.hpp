@@ -39,6 +39,8 @@ constexpr int kSmallE = 8;
 constexpr int kBigAnaE = 8;
 constexpr int kBigSynE = 16;
 constexpr int kSmallWaves = 4;
+template <class T>
+constexpr int kSynSmallWaves = sizeof(T) == 4 ? 6 : 4;   // small synthesis items (FP32: 3 blocks of 512 per CU)
 constexpr int kAnaThreads = kAnaSmallValues / kSmallE;   // k_band_ana, small items
 constexpr int kAnaBigThreads = 1024;                     // k_band_ana, large items
 constexpr int kSynThreads = kSynSmallValues / kSmallE;   // k_band_syn, small items
@@ -373,8 +375,8 @@ k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
     }
   }
   __syncthreads();
-  if constexpr (TWL) lds_fft<T, 1, CONTIG, E, 8>(buf, 0, G.logM, G.cnt, 0, TwLds<T>{twl}, tid, nthr);
-  else lds_fft<T, 1, CONTIG, E, 8>(buf, 0, G.logM, G.cnt, 0, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft_contig<T, 1, E, 8>(buf, 0, G.logM, G.cnt, TwLds<T>{twl}, tid, nthr);
+  else lds_fft_contig<T, 1, E, 8>(buf, 0, G.logM, G.cnt, TwGlobal<T>{a.tw}, tid, nthr);
   // bands k0.. are consecutive with equal M: off_k = off_k0 + (k - k0) M
   C2<T>* __restrict__ cs = coef + tk.coef_base;
   const int off0 = a.bands[G.k0].off;
@@ -462,26 +464,27 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
   __syncthreads();
   for (int ri = 0; ri < G.nrun; ++ri) {
     const SynRunDev R = a.runs[G.run0 + ri];
-    if constexpr (TWL) lds_fft<T, -1, CONTIG, E, 8>(buf, R.lds_off, R.logM, R.cnt, 0, TwLds<T>{twl}, tid, nthr);
-    else lds_fft<T, -1, CONTIG, E, 8>(buf, R.lds_off, R.logM, R.cnt, 0, TwGlobal<T>{a.tw}, tid, nthr);
+    if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, tid, nthr);
+    else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, tid, nthr);
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;
   const C2<T>* __restrict__ w2 = reinterpret_cast<const C2<T>*>(a.ent2_w);
-  for (int j0 = G.lo; j0 < G.hi; j0 += 4 * nthr) {
-    I4 ps[4];
-    C2<T> ws[4];
-    int eo[4], ee[4];
+  constexpr int QB = 2;                         // owned bins per thread per round
+  for (int j0 = G.lo + tid; j0 < G.hi; j0 += QB * nthr) {
+    I4 ps[QB];
+    C2<T> ws[QB];
+    int eo[QB], ee[QB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = imin(j0 + tid + q * nthr, G.hi - 1);
+    for (int q = 0; q < QB; ++q) {
+      const int j = imin(j0 + q * nthr, G.hi - 1);
       ps[q] = a.ent2_pos[j];
       ws[q] = w2[j];
       eo[q] = a.ent_off[j];
       ee[q] = a.ent_off[j + 1];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + tid + q * nthr;
+    for (int q = 0; q < QB; ++q) {
+      const int j = j0 + q * nthr;
       if (j >= G.hi) continue;
       C2<T> c0 = buf[pidx(ps[q].x)], c1 = buf[pidx(ps[q].z)];
       const C2<T> m0 = buf[pidx(imax(ps[q].y, 0))], m1 = buf[pidx(imax(ps[q].w, 0))];

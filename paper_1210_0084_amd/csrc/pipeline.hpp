@@ -176,8 +176,8 @@ template <class T, class Launch>
 void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
                      const C2<T>* coef, C2<T>* W2, T* y, Launch& L) {
   if (g.gs) {
-    if (g.ts) L.launch(k_band_syn<T, kSmallE, kSynThreads, kSmallWaves, true>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
-    else L.launch(k_band_syn<T, kSmallE, kSynThreads, kSmallWaves, false>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
+    if (g.ts) L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, true>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
+    else L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
   }
   if (g.gsb)
     L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
