@@ -328,6 +328,88 @@ __device__ __forceinline__ void lds_fft_c(C2<T>* buf, int base, int nseq, const 
   }
 }
 
+// INTERLEAVED layout with the length fixed at compile time: element e of
+// sequence s at e * nseq + s (nseq = 2^lognseq at run time). Strides of 16 or
+// more elements use one base plus offsets.
+__device__ __forceinline__ int pidx_run(int pb, int p0, int r, int S) {
+  return (S & 15) == 0 ? pb + r * (S + (S >> 4)) : pidx(p0 + r * S);
+}
+
+template <class T, int DIR, int R, int E, int LOGN, int LOGNS, class TW>
+__device__ __forceinline__ void stockham_pass_ci(C2<T>* buf, int lognseq, const TW& tws, int tid, int nthr) {
+  constexpr int U = E / R;
+  constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  constexpr int LUNITS = LOGN - LR;
+  constexpr int NS = 1 << LOGNS;
+  const int total = 1 << (lognseq + LUNITS);
+  const int sread = 1 << (LUNITS + lognseq), swrite = NS << lognseq;
+  const int smask = (1 << lognseq) - 1;
+  C2<T> v[U][R];
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = imin(tid + i * nthr, total - 1);
+    const int s = u & smask, j = u >> lognseq;
+    const int p0 = (j << lognseq) + s;
+    const int pb = pidx(p0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[i][r] = buf[pidx_run(pb, p0, r, sread)];
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    if constexpr (NS > 1) {
+      const int u = imin(tid + i * nthr, total - 1);
+      C2<T> w[R];
+      twiddle_powers<T, DIR, R>(tws, NS * R, (u >> lognseq) & (NS - 1), w);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
+    }
+    dft_reg<T, R, DIR>(v[i]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = tid + i * nthr;
+    if (u < total) {
+      const int s = u & smask, j = u >> lognseq;
+      const int e0 = ((j >> LOGNS) << (LOGNS + LR)) + (j & (NS - 1));
+      const int p0 = (e0 << lognseq) + s;
+      const int pb = pidx(p0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx_run(pb, p0, r, swrite)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW>
+__device__ __forceinline__ void lds_fft_ci(C2<T>* buf, int lognseq, const TW& tw, int tid, int nthr) {
+  if constexpr (LOGNS < LOGN) {
+    constexpr int REM = LOGN - LOGNS;
+    constexpr int LR = (RMAX >= 16 && REM >= 4) ? 4 : (RMAX >= 8 && REM >= 3) ? 3 : (RMAX >= 4 && REM >= 2) ? 2 : 1;
+    stockham_pass_ci<T, DIR, (1 << LR), E, LOGN, LOGNS, TW>(buf, lognseq, tw, tid, nthr);
+    lds_fft_ci<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW>(buf, lognseq, tw, tid, nthr);
+  }
+}
+
+// Batched INTERLEAVED FFT (2^lognseq sequences of length 2^logn, 1 <= logn
+// <= 10, at LDS base 0), dispatched to the compile-time variant.
+template <class T, int DIR, int E, int RMAX, class TW>
+__device__ __forceinline__ void lds_fft_interleaved(C2<T>* buf, int logn, int lognseq, const TW& tw, int tid,
+                                                    int nthr) {
+  switch (logn) {
+    case 1: lds_fft_ci<T, DIR, E, RMAX, 1, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 2: lds_fft_ci<T, DIR, E, RMAX, 2, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 3: lds_fft_ci<T, DIR, E, RMAX, 3, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 4: lds_fft_ci<T, DIR, E, RMAX, 4, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 5: lds_fft_ci<T, DIR, E, RMAX, 5, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 6: lds_fft_ci<T, DIR, E, RMAX, 6, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 7: lds_fft_ci<T, DIR, E, RMAX, 7, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 8: lds_fft_ci<T, DIR, E, RMAX, 8, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    case 9: lds_fft_ci<T, DIR, E, RMAX, 9, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+    default: lds_fft_ci<T, DIR, E, RMAX, 10, 0, TW>(buf, lognseq, tw, tid, nthr); break;
+  }
+}
+
 // Batched CONTIG FFT of nseq sequences of length 2^logn, 1 <= logn <= 13,
 // dispatched to the compile-time variant (same contract as lds_fft).
 template <class T, int DIR, int E, int RMAX, class TW>

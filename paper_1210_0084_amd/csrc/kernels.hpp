@@ -48,7 +48,7 @@ constexpr int kSynBigThreads = 1024;                     // k_band_syn, large it
 static_assert(kAnaBigThreads * kBigAnaE >= 8192 && kSynBigThreads * kBigSynE >= kSynMaxValues,
               "large work items must fit one block");
 constexpr int kPassE = 8;             // values per thread in the slice-FFT passes
-constexpr int kPassWaves = 4;         // their waves per SIMD
+constexpr int kPassWaves = 4;         // their waves per SIMD (at least)
 // Largest padded length and coefficient count of one signal: offsets inside a
 // signal are 32-bit.
 constexpr int64_t kMaxSignalElems = 0x7fffffffLL;
@@ -175,8 +175,8 @@ k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict
     if (e < total) buf[pidx(e)] = {s2[i].x * h2[i].x, s2[i].y * h2[i].y};
   }
   __syncthreads();
-  if constexpr (TWL) lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwLds<T>{twl}, tid, nthr);
-  else lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN2, a.logC, TwLds<T>{twl}, tid, nthr);
+  else lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN2, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
@@ -278,8 +278,8 @@ k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
     if (e < total) buf[pidx(((e & (a.N1 - 1)) << logTwoP) + (e >> a.logN1))] = v[i];
   }
   __syncthreads();
-  if constexpr (TWL) lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwLds<T>{twl}, tid, nthr);
-  else lds_fft<T, -1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN1, logTwoP, TwLds<T>{twl}, tid, nthr);
+  else lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN1, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* X = W2 + (int64_t)task * a.ws2;
 #pragma unroll
   for (int i = 0; i < U; ++i) {
@@ -563,8 +563,8 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
     }
   }
   __syncthreads();
-  if constexpr (TWL) lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwLds<T>{twl}, tid, nthr);
-  else lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN1, twoP, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN1, logTwoP, TwLds<T>{twl}, tid, nthr);
+  else lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN1, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
@@ -628,8 +628,8 @@ k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __rest
     if (e < total) buf[pidx(e)] = v[i];
   }
   __syncthreads();
-  if constexpr (TWL) lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwLds<T>{twl}, tid, nthr);
-  else lds_fft<T, 1, INTERLEAVED, kPassE>(buf, 0, a.logN2, a.C, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
+  if constexpr (TWL) lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN2, a.logC, TwLds<T>{twl}, tid, nthr);
+  else lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN2, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
   T* __restrict__ ys = y + tk.y_base;
   const int ys0 = (int)tk.y_start, yper = (int)tk.y_period, yval = (int)tk.y_valid;
 #pragma unroll
