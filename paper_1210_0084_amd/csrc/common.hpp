@@ -49,19 +49,21 @@ struct alignas(16) AnaGroupDev {
   int32_t k0, cnt, M, logM;
 };
 
-// Synthesis work item: bins [lo, hi) of the half spectrum, built from bands
-// ke .. kb whose coefficients are transformed in runs of equal M_k (at most
-// kMaxRuns runs); maxM is the largest M_k among them.
-struct alignas(16) SynGroupDev {
-  int32_t ke, kb, lo, hi;
-  int32_t run0, nrun, total, maxM;
-};
-
 // A run: bands k0 .. k0 + cnt - 1 with M_k = M, packed from offset off of the
 // slice's coefficients, held at LDS position lds_off of the work item.
 struct alignas(16) SynRunDev {
   int32_t k0, cnt, M, logM;
   int32_t lds_off, off, pad0_, pad1_;
+};
+
+// Synthesis work item: bins [lo, hi) of the half spectrum, built from bands
+// ke .. kb whose coefficients are transformed in runs of equal M_k (at most
+// kMaxRuns runs, runs[run0 ..]); maxM is the largest M_k among them. The
+// first two runs are repeated inline (read with the item, no second lookup).
+struct alignas(16) SynGroupDev {
+  int32_t ke, kb, lo, hi;
+  int32_t run0, nrun, total, maxM;
+  SynRunDev r[2];
 };
 
 constexpr int kMaxRuns = 8;

@@ -318,13 +318,28 @@ __device__ __forceinline__ void stockham_pass_c(C2<T>* buf, int base, int nseq, 
   __syncthreads();
 }
 
-template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW>
+// log2 of the radix of the pass that starts at Ns = 2^logns (greedy, largest first).
+__host__ __device__ constexpr int pass_log_radix(int logn, int logns, int rmax) {
+  return (rmax >= 16 && logn - logns >= 4) ? 4 : (rmax >= 8 && logn - logns >= 3) ? 3
+         : (rmax >= 4 && logn - logns >= 2) ? 2 : 1;
+}
+
+// log2 Ns of the last pass of a length-2^logn FFT.
+__host__ __device__ constexpr int last_pass_logns(int logn, int rmax) {
+  int ns = 0;
+  while (ns + pass_log_radix(logn, ns, rmax) < logn) ns += pass_log_radix(logn, ns, rmax);
+  return ns;
+}
+
+// Passes of the CONTIG FFT from Ns = 2^LOGNS while Ns < 2^STOP (the whole
+// transform with the defaults).
+template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW, int STOP = LOGN>
 __device__ __forceinline__ void lds_fft_c(C2<T>* buf, int base, int nseq, const TW& tw, int tid, int nthr) {
-  if constexpr (LOGNS < LOGN) {
+  if constexpr (LOGNS < LOGN && LOGNS < STOP) {
     constexpr int REM = LOGN - LOGNS;
     constexpr int LR = (RMAX >= 16 && REM >= 4) ? 4 : (RMAX >= 8 && REM >= 3) ? 3 : (RMAX >= 4 && REM >= 2) ? 2 : 1;
     stockham_pass_c<T, DIR, (1 << LR), E, LOGN, LOGNS, TW>(buf, base, nseq, tw, tid, nthr);
-    lds_fft_c<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW>(buf, base, nseq, tw, tid, nthr);
+    lds_fft_c<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW, STOP>(buf, base, nseq, tw, tid, nthr);
   }
 }
 

@@ -313,13 +313,128 @@ __device__ __forceinline__ void stage_twiddles(C2<T>* twl, const C2<T>* __restri
   }
 }
 
+// Band analysis of one work item with M_k = 2^LOGN (bands k0 .. k0 + cnt - 1).
+// The first FFT pass is fused with the gather: a thread takes the R values of
+// one first-pass butterfly (all in one band), forms X[j] g_k[j] for them,
+// transforms in registers and writes LDS. Middle passes run in LDS. The last
+// pass stores its outputs straight to the coefficients. DIR = +1 (e^{+}).
+template <class T, int E, int LOGN, class TW>
+__device__ __forceinline__ void band_ana_fft(const KArgs<T>& a, const SliceTask& tk, const AnaGroupDev& G,
+                                             const C2<T>* __restrict__ X, C2<T>* __restrict__ cs, C2<T>* buf,
+                                             const TW& tws, int tid, int nthr) {
+  constexpr int M = 1 << LOGN, MASK = M - 1;
+  constexpr int LR1 = pass_log_radix(LOGN, 0, 8), R1 = 1 << LR1, U1 = E / R1;
+  constexpr int LU1 = LOGN - LR1;               // log2 first-pass units per band
+  constexpr int LAST = last_pass_logns(LOGN, 8);
+  const int units1 = G.cnt << LU1;
+  // gather in first-pass order: unit u of band s holds slots j + r 2^LU1
+  int xi[U1][R1], wi[U1][R1];
+#pragma unroll
+  for (int i = 0; i < U1; ++i) {
+    const int u = imin(tid + i * nthr, units1 - 1);
+    const int sb = u >> LU1, j = u & ((1 << LU1) - 1);
+    const BandDev B = a.bands[G.k0 + sb];
+    const bool live = tid + i * nthr < units1;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int slot = j + (r << LU1);
+      const int t = (slot - B.start) & MASK;
+      const int jb = B.start + t;                 // signed bin, -N < jb < 2N
+      const bool in = live && t < B.len;
+      const int jj = jb < 0 ? -jb : (jb > a.N ? 2 * a.N - jb : jb);
+      const bool cj = jb < 0 || jb > a.N;
+      xi[i][r] = in ? (cj ? ~jj : jj) : 0;          // ~jj (< 0) marks a conjugate
+      wi[i][r] = in ? B.goff + t : -1;
+    }
+  }
+  C2<T> v[U1][R1];
+  T gv[U1][R1];
+#pragma unroll
+  for (int i = 0; i < U1; ++i) {
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      v[i][r] = X[xi[i][r] < 0 ? ~xi[i][r] : xi[i][r]];
+      gv[i][r] = a.g[imax(wi[i][r], 0)];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < U1; ++i) {
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const T w = wi[i][r] < 0 ? T(0) : gv[i][r];
+      v[i][r] = {v[i][r].x * w, (xi[i][r] < 0 ? -v[i][r].y : v[i][r].y) * w};
+    }
+    dft_reg<T, R1, 1>(v[i]);
+  }
+  // band-major: c(k0 + s, m, n) at S off_{k0+s} + m M + n; slice-major: m cps + off_{k0+s} + n
+  const int off0 = a.bands[G.k0].off;
+  const int cbase = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * M;
+  const int bstride = a.slice_major ? M : tk.S * M;   // band k0 + s starts s bstride later
+  if constexpr (LAST == 0) {
+    // a single pass: outputs n = r of unit j = 0
+#pragma unroll
+    for (int i = 0; i < U1; ++i) {
+      const int u = tid + i * nthr;
+      if (u < units1) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) cs[cbase + u * bstride + r] = v[i][r];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < U1; ++i) {
+      const int u = tid + i * nthr;
+      if (u < units1) {
+        const int sb = u >> LU1, j = u & ((1 << LU1) - 1);
+        const int p0 = (sb << LOGN) + (j << LR1);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buf[pidx(p0 + r)] = v[i][r];
+      }
+    }
+    __syncthreads();
+    lds_fft_c<T, 1, E, 8, LOGN, LR1, TW, LAST>(buf, 0, G.cnt, tws, tid, nthr);
+    // last pass: LDS -> registers -> coefficients
+    constexpr int LRL = LOGN - LAST, RL = 1 << LRL, UL = E / RL, NS = 1 << LAST;
+    constexpr int LUL = LOGN - LRL;
+    const int unitsL = G.cnt << LUL;
+    C2<T> q[UL][RL];
+#pragma unroll
+    for (int i = 0; i < UL; ++i) {
+      const int u = imin(tid + i * nthr, unitsL - 1);
+      const int sb = u >> LUL, j = u & ((1 << LUL) - 1);
+      const int p0 = (sb << LOGN) + j;
+      const int pb = pidx(p0);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) q[i][r] = buf[pidx_step<(1 << LUL)>(pb, p0, r)];
+    }
+#pragma unroll
+    for (int i = 0; i < UL; ++i) {
+      const int u = imin(tid + i * nthr, unitsL - 1);
+      C2<T> w[RL];
+      twiddle_powers<T, 1, RL>(tws, NS * RL, u & (NS - 1), w);
+#pragma unroll
+      for (int r = 1; r < RL; ++r) q[i][r] = cmul(q[i][r], w[r]);
+      dft_reg<T, RL, 1>(q[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < UL; ++i) {
+      const int u = tid + i * nthr;
+      if (u < unitsL) {
+        // LAST + LRL = LOGN: unit j < NS writes outputs n = j + r NS of its band
+        const int sb = u >> LUL, j = u & ((1 << LUL) - 1);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) cs[cbase + sb * bstride + j + r * NS] = q[i][r];
+      }
+    }
+  }
+}
+
 // Band analysis: bands k0 .. k0 + cnt - 1 of one slice. Slot r of band k
 // holds X[j] g_k[j] for the bin j of J_k with j = r (mod M_k), or 0; the
 // inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff). Bins
 // outside [0, N] read the half spectrum by conjugate symmetry.
 // Block b takes work item g0 + b mod ng of task b / ng. TWL stages the
-// twiddles of lengths up to M in LDS.
-// LDS: values (padded) | per band (start, len, goff) | twiddles.
+// twiddles of lengths up to M in LDS. LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef,
@@ -331,62 +446,27 @@ k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int total = G.cnt << G.logM, mask = G.M - 1;
-  I4* bd = reinterpret_cast<I4*>(smem + lds_tail_offset<T>(total));
-  C2<T>* twl = reinterpret_cast<C2<T>*>(bd + G.cnt);
-  {
-    const BandDev B = a.bands[G.k0 + imin(tid, G.cnt - 1)];
-    if constexpr (TWL) stage_twiddles(twl, a.tw, G.M, tid, nthr);
-    if (tid < G.cnt) bd[tid] = {B.start, B.len, B.goff, 0};
-    for (int b = tid + nthr; b < G.cnt; b += nthr) {
-      const BandDev B2 = a.bands[G.k0 + b];
-      bd[b] = {B2.start, B2.len, B2.goff, 0};
-    }
-  }
-  __syncthreads();
-  // gather: all addresses first (no branches), then every load, then the products
+  C2<T>* twl = reinterpret_cast<C2<T>*>(smem + lds_tail_offset<T>(G.cnt << G.logM));
+  if constexpr (TWL) stage_twiddles(twl, a.tw, G.M, tid, nthr);
   const C2<T>* __restrict__ X = W2 + (int64_t)task * a.ws2;
-  int xi[E], wi[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = imin(tid + i * nthr, total - 1);
-    const I4 B = bd[e >> G.logM];
-    const int t = ((e & mask) - B.x) & mask;
-    const int j = B.x + t;                               // signed bin, -N < j < 2N
-    const bool in = tid + i * nthr < total && t < B.y;
-    const int jj = j < 0 ? -j : (j > a.N ? 2 * a.N - j : j);
-    const bool cj = j < 0 || j > a.N;
-    xi[i] = in ? (cj ? ~jj : jj) : 0;                    // ~jj (< 0) marks a conjugate
-    wi[i] = in ? B.z + t : -1;
-  }
-  C2<T> xv[E];
-  T gv[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    xv[i] = X[xi[i] < 0 ? ~xi[i] : xi[i]];
-    gv[i] = a.g[imax(wi[i], 0)];
-  }
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) {
-      const T w = wi[i] < 0 ? T(0) : gv[i];
-      buf[pidx(e)] = {xv[i].x * w, (xi[i] < 0 ? -xv[i].y : xv[i].y) * w};
-    }
-  }
-  __syncthreads();
-  if constexpr (TWL) lds_fft_contig<T, 1, E, 8>(buf, 0, G.logM, G.cnt, TwLds<T>{twl}, tid, nthr);
-  else lds_fft_contig<T, 1, E, 8>(buf, 0, G.logM, G.cnt, TwGlobal<T>{a.tw}, tid, nthr);
-  // bands k0.. are consecutive with equal M: off_k = off_k0 + (k - k0) M
   C2<T>* __restrict__ cs = coef + tk.coef_base;
-  const int off0 = a.bands[G.k0].off;
-  const int base = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * G.M;
-  const int bstride = a.slice_major ? G.M : tk.S * G.M;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) cs[base + (e >> G.logM) * bstride + (e & mask)] = buf[pidx(e)];
+  const TwGlobal<T> twg{a.tw};
+  const TwLds<T> tws{twl};
+#define SLICQ_ANA_CASE(L)                                                                  \
+  case L:                                                                                  \
+    if constexpr (TWL) band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, tws, tid, nthr);        \
+    else band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, twg, tid, nthr);                      \
+    break;
+  switch (G.logM) {
+    SLICQ_ANA_CASE(1) SLICQ_ANA_CASE(2) SLICQ_ANA_CASE(3) SLICQ_ANA_CASE(4) SLICQ_ANA_CASE(5)
+    SLICQ_ANA_CASE(6) SLICQ_ANA_CASE(7) SLICQ_ANA_CASE(8) SLICQ_ANA_CASE(9) SLICQ_ANA_CASE(10)
+    SLICQ_ANA_CASE(11) SLICQ_ANA_CASE(12)
+    default:
+      if constexpr (TWL) band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, tws, tid, nthr);
+      else band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, twg, tid, nthr);
+      break;
   }
+#undef SLICQ_ANA_CASE
 }
 
 // Element index of LDS position p of a synthesis item inside run R: band
@@ -429,7 +509,7 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
   }
   // coefficient addresses of a batch of values (no branches), then every load
   // of the batch; batches of 8 values per thread bound the registers
-  const SynRunDev R0 = a.runs[G.run0];
+  const SynRunDev R0 = G.r[0];
   constexpr int EB = E < 8 ? E : 8;
 #pragma unroll
   for (int c = 0; c < E; c += EB) {
@@ -441,7 +521,9 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
 #pragma unroll
       for (int i = 0; i < EB; ++i) idx[i] = run_coef_index(tk, R0, imin(tid + (c + i) * nthr, G.total - 1));
       for (int r = 1; r < G.nrun; ++r) {
-        const SynRunDev R = a.runs[G.run0 + r];
+        SynRunDev R;
+        if (r == 1) R = G.r[1];
+        else R = a.runs[G.run0 + r];
 #pragma unroll
         for (int i = 0; i < EB; ++i) {
           const int p = imin(tid + (c + i) * nthr, G.total - 1);
@@ -463,7 +545,10 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
   }
   __syncthreads();
   for (int ri = 0; ri < G.nrun; ++ri) {
-    const SynRunDev R = a.runs[G.run0 + ri];
+    SynRunDev R;
+    if (ri == 0) R = G.r[0];
+    else if (ri == 1) R = G.r[1];
+    else R = a.runs[G.run0 + ri];
     if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, tid, nthr);
     else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, tid, nthr);
   }

@@ -129,15 +129,14 @@ Geometry<T> geometry(const Plan& p) {
   g.g2 = (p.N2 / 2) / p.P;
   g.b2 = threads_for((int64_t)2 * p.P * p.N1, kPassE);
   g.s2 = (padded(2 * p.P * p.N1) + p.N1) * cb;      // values, twiddles up to N1
-  const size_t band_tail = (size_t)kMaxGroupBands * sizeof(I4);
   g.ga = p.ana_small;
   g.ba = threads_for(std::max(p.ana_cap_small, 1), kSmallE);
-  g.sa = lds_tail_offset<T>(p.ana_cap_small) + band_tail;
+  g.sa = lds_tail_offset<T>(p.ana_cap_small);
   g.ta = g.sa + (size_t)p.ana_maxM_small * cb <= kMaxLdsBytes;
   if (g.ta) g.sa += (size_t)p.ana_maxM_small * cb;
   g.gab = (int)p.ana.size() - p.ana_small;
   g.bab = threads_for(std::max(p.ana_cap_big, 1), kBigAnaE);
-  g.sab = lds_tail_offset<T>(p.ana_cap_big) + band_tail;
+  g.sab = lds_tail_offset<T>(p.ana_cap_big);
   g.gs = p.syn_small;
   g.bs = threads_for(std::max(p.syn_cap_small, 1), kSmallE);
   g.ss = lds_tail_offset<T>(p.syn_cap_small);

@@ -394,6 +394,7 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
       }
       s.maxM = 0;
       for (int r = s.run0; r < s.run0 + s.nrun; ++r) s.maxM = std::max(s.maxM, out.runs[r].M);
+      for (int r = 0; r < 2; ++r) s.r[r] = r < s.nrun ? out.runs[s.run0 + r] : SynRunDev{};
       s.total = (int32_t)(out.bands[kb].off + out.bands[kb].M - out.bands[ke].off);
       out.syn_cap = std::max(out.syn_cap, s.total);
       out.syn_bands = std::max(out.syn_bands, kb - ke + 1);
