@@ -425,6 +425,25 @@ __device__ __forceinline__ void lds_fft_interleaved(C2<T>* buf, int logn, int lo
   }
 }
 
+// The passes after a first radix-8 pass done by the caller (3 <= logn <= 13).
+template <class T, int DIR, int E, class TW>
+__device__ __forceinline__ void lds_fft_contig_after8(C2<T>* buf, int base, int logn, int nseq, const TW& tw,
+                                                      int tid, int nthr) {
+  switch (logn) {
+    case 3: break;
+    case 4: lds_fft_c<T, DIR, E, 8, 4, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 5: lds_fft_c<T, DIR, E, 8, 5, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 6: lds_fft_c<T, DIR, E, 8, 6, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 7: lds_fft_c<T, DIR, E, 8, 7, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 8: lds_fft_c<T, DIR, E, 8, 8, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 9: lds_fft_c<T, DIR, E, 8, 9, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 10: lds_fft_c<T, DIR, E, 8, 10, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 11: lds_fft_c<T, DIR, E, 8, 11, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 12: lds_fft_c<T, DIR, E, 8, 12, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    default: lds_fft_c<T, DIR, E, 8, 13, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+  }
+}
+
 // Batched CONTIG FFT of nseq sequences of length 2^logn, 1 <= logn <= 13,
 // dispatched to the compile-time variant (same contract as lds_fft).
 template <class T, int DIR, int E, int RMAX, class TW>

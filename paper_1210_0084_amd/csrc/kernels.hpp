@@ -69,7 +69,7 @@ struct KArgs {
   const int2* ent_pos;
   const T* ent_w;
   int32_t N, Mt, K, N1;
-  int32_t N2, logN1, pad0_, pad1_;
+  int32_t N2, logN1, min_M, pad1_;  // min_M: smallest M_k of the plan
   int32_t logN2, C, logC, P;
   int32_t logP, zero_ola;   // zero_ola: band_syn zeroes the output overlaps
   // coefficient layout: coefficient n of band k (packing offset off_k) of
@@ -507,50 +507,92 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       if (idx < tk.y_valid) y[tk.y_base + idx] = T(0);
     }
   }
-  // coefficient addresses of a batch of values (no branches), then every load
-  // of the batch; batches of 8 values per thread bound the registers
-  const SynRunDev R0 = G.r[0];
-  constexpr int EB = E < 8 ? E : 8;
+  if (E == 8 && a.min_M >= 8) {
+    // first radix-8 pass fused with the loads: unit u (all runs flattened,
+    // u = p / 8) takes slots j + r M/8 of one band, r = 0..7
+    const int units = G.total >> 3;
 #pragma unroll
-  for (int c = 0; c < E; c += EB) {
-    int idx[EB];
-    if (a.slice_major) {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) idx[i] = tk.m * a.cps + R0.off + imin(tid + (c + i) * nthr, G.total - 1);
-    } else {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) idx[i] = run_coef_index(tk, R0, imin(tid + (c + i) * nthr, G.total - 1));
+    for (int i = 0; i < E / 8; ++i) {
+      const int u = imin(tid + i * nthr, units - 1);
+      const int p = u << 3;
+      int lds_off = G.r[0].lds_off, off = G.r[0].off, M = G.r[0].M, logM = G.r[0].logM;
       for (int r = 1; r < G.nrun; ++r) {
         SynRunDev R;
         if (r == 1) R = G.r[1];
         else R = a.runs[G.run0 + r];
+        if (p >= R.lds_off) { lds_off = R.lds_off; off = R.off; M = R.M; logM = R.logM; }
+      }
+      const int lu = logM - 3, q = (p - lds_off) >> 3;
+      const int sb = q >> lu, j = q & ((1 << lu) - 1);
+      const int cbase = a.slice_major ? tk.m * a.cps + off + sb * M + j : tk.S * (off + sb * M) + tk.m * M + j;
+      C2<T> v[8];
 #pragma unroll
-        for (int i = 0; i < EB; ++i) {
-          const int p = imin(tid + (c + i) * nthr, G.total - 1);
-          if (p >= R.lds_off) idx[i] = run_coef_index(tk, R, p);
-        }
+      for (int r = 0; r < 8; ++r) v[r] = cs[cbase + (r << lu)];
+      if constexpr (TWL) {
+        if (i == 0) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+      }
+      dft_reg<T, 8, -1>(v);
+      if (tid + i * nthr < units) {
+        const int p0 = lds_off + (sb << logM) + (j << 3);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) buf[pidx(p0 + r)] = v[r];
       }
     }
-    C2<T> v[EB];
-#pragma unroll
-    for (int i = 0; i < EB; ++i) v[i] = cs[idx[i]];
-    if constexpr (TWL) {
-      if (c == 0) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+    __syncthreads();
+    for (int ri = 0; ri < G.nrun; ++ri) {
+      SynRunDev R;
+      if (ri == 0) R = G.r[0];
+      else if (ri == 1) R = G.r[1];
+      else R = a.runs[G.run0 + ri];
+      if constexpr (TWL) lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, tid, nthr);
+      else lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, tid, nthr);
     }
+  } else {
+    // coefficient addresses of a batch of values (no branches), then every load
+    // of the batch; batches of 8 values per thread bound the registers
+    const SynRunDev R0 = G.r[0];
+    constexpr int EB = E < 8 ? E : 8;
 #pragma unroll
-    for (int i = 0; i < EB; ++i) {
-      const int p = tid + (c + i) * nthr;
-      if (p < G.total) buf[pidx(p)] = v[i];
+    for (int c = 0; c < E; c += EB) {
+      int idx[EB];
+      if (a.slice_major) {
+#pragma unroll
+        for (int i = 0; i < EB; ++i) idx[i] = tk.m * a.cps + R0.off + imin(tid + (c + i) * nthr, G.total - 1);
+      } else {
+#pragma unroll
+        for (int i = 0; i < EB; ++i) idx[i] = run_coef_index(tk, R0, imin(tid + (c + i) * nthr, G.total - 1));
+        for (int r = 1; r < G.nrun; ++r) {
+          SynRunDev R;
+          if (r == 1) R = G.r[1];
+          else R = a.runs[G.run0 + r];
+#pragma unroll
+          for (int i = 0; i < EB; ++i) {
+            const int p = imin(tid + (c + i) * nthr, G.total - 1);
+            if (p >= R.lds_off) idx[i] = run_coef_index(tk, R, p);
+          }
+        }
+      }
+      C2<T> v[EB];
+#pragma unroll
+      for (int i = 0; i < EB; ++i) v[i] = cs[idx[i]];
+      if constexpr (TWL) {
+        if (c == 0) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+      }
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int p = tid + (c + i) * nthr;
+        if (p < G.total) buf[pidx(p)] = v[i];
+      }
     }
-  }
-  __syncthreads();
-  for (int ri = 0; ri < G.nrun; ++ri) {
-    SynRunDev R;
-    if (ri == 0) R = G.r[0];
-    else if (ri == 1) R = G.r[1];
-    else R = a.runs[G.run0 + ri];
-    if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, tid, nthr);
-    else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, tid, nthr);
+    __syncthreads();
+    for (int ri = 0; ri < G.nrun; ++ri) {
+      SynRunDev R;
+      if (ri == 0) R = G.r[0];
+      else if (ri == 1) R = G.r[1];
+      else R = a.runs[G.run0 + ri];
+      if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, tid, nthr);
+      else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, tid, nthr);
+    }
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;
   const C2<T>* __restrict__ w2 = reinterpret_cast<const C2<T>*>(a.ent2_w);

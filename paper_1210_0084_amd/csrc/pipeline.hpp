@@ -84,6 +84,8 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
   a.ent_pos = reinterpret_cast<const int2*>(base + L.ent_pos);
   a.ent_w = reinterpret_cast<const T*>(base + (adjoint ? L.ent_wadj : L.ent_wsyn));
   a.N = (int32_t)p.N;
+  a.min_M = 1 << 30;
+  for (const BandInfo& b : p.bands) a.min_M = std::min<int32_t>(a.min_M, b.M);
   a.Mt = (int32_t)p.Mt;
   a.K = p.K;
   a.N1 = p.N1;
