@@ -23,6 +23,13 @@ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
 }
 template <class T>
 __device__ __forceinline__ C2<T> cconj(C2<T> a) { return {a.x, -a.y}; }
+// a * b rounded by itself: the compiler cannot contract it into a following
+// add, so the value does not depend on how the surrounding code is compiled.
+template <class T>
+__device__ __forceinline__ T mul_rn(T a, T b) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, 0.0f);
+  else return __builtin_fma(a, b, 0.0);
+}
 template <class T>
 __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
 // multiply by -i (forward) or +i (inverse)
@@ -396,13 +403,119 @@ __device__ __forceinline__ void stockham_pass_ci(C2<T>* buf, int lognseq, const 
   __syncthreads();
 }
 
-template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW>
+template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW, int STOP = LOGN>
 __device__ __forceinline__ void lds_fft_ci(C2<T>* buf, int lognseq, const TW& tw, int tid, int nthr) {
-  if constexpr (LOGNS < LOGN) {
+  if constexpr (LOGNS < LOGN && LOGNS < STOP) {
     constexpr int REM = LOGN - LOGNS;
     constexpr int LR = (RMAX >= 16 && REM >= 4) ? 4 : (RMAX >= 8 && REM >= 3) ? 3 : (RMAX >= 4 && REM >= 2) ? 2 : 1;
     stockham_pass_ci<T, DIR, (1 << LR), E, LOGN, LOGNS, TW>(buf, lognseq, tw, tid, nthr);
-    lds_fft_ci<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW>(buf, lognseq, tw, tid, nthr);
+    lds_fft_ci<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW, STOP>(buf, lognseq, tw, tid, nthr);
+  }
+}
+
+// Unit u of a pass with 2^logj units per sequence over 2^lognseq sequences:
+// sequence-fastest (s = u mod 2^lognseq) or, with JF, unit-fastest
+// (j = u mod 2^logj), which makes global accesses of one sequence coalesce.
+template <bool JF>
+__device__ __forceinline__ void ci_unit(int u, int lognseq, int logj, int& s, int& j) {
+  if constexpr (JF) { j = u & ((1 << logj) - 1); s = u >> logj; }
+  else { s = u & ((1 << lognseq) - 1); j = u >> lognseq; }
+}
+
+// FFT of length 2^LOGN over 2^lognseq sequences (INTERLEAVED in LDS between
+// passes, radix <= 8) whose first pass takes its inputs from load(s, e)
+// (element e of sequence s) and whose last pass gives its outputs to
+// store(i, r, s, e, value) instead of LDS: FIRST and LAST select which of the
+// two are fused (an unfused first pass reads LDS, an unfused last pass writes
+// LDS). Output e of the last pass is held by unit u = tid + i nthr with
+// (s, j) = ci_unit<JF>(u, lognseq, L), e = j + r 2^L, L = last_pass_logns,
+// so a caller can fetch per-output data before the transform. JF orders the
+// fused passes' units unit-fastest (coalesced when a sequence is contiguous
+// in global memory). The caller synchronises after an unfused last pass; a
+// fused first pass needs no synchronisation before it.
+template <class T, int DIR, int E, int LOGN, bool FIRST, bool LASTF, bool JF, class TW, class LD, class ST>
+__device__ __forceinline__ void fft_ci_fused(C2<T>* buf, int lognseq, const TW& tw, int tid, int nthr, LD load,
+                                             ST store) {
+  constexpr int LR1 = pass_log_radix(LOGN, 0, 8), R1 = 1 << LR1, U1 = E / R1;
+  constexpr int LAST = last_pass_logns(LOGN, 8);
+  if constexpr (FIRST) {
+    const int units = 1 << (lognseq + LOGN - LR1);
+    C2<T> v[U1][R1];
+#pragma unroll
+    for (int i = 0; i < U1; ++i) {
+      int s, j;
+      ci_unit<JF>(imin(tid + i * nthr, units - 1), lognseq, LOGN - LR1, s, j);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[i][r] = load(s, j + (r << (LOGN - LR1)));
+    }
+#pragma unroll
+    for (int i = 0; i < U1; ++i) dft_reg<T, R1, DIR>(v[i]);
+    if constexpr (LASTF && LAST == 0) {
+#pragma unroll
+      for (int i = 0; i < U1; ++i) {
+        const int u = tid + i * nthr;
+        if (u < units) {
+          int s, j;
+          ci_unit<JF>(u, lognseq, 0, s, j);
+#pragma unroll
+          for (int r = 0; r < R1; ++r) store(i, r, s, j + r, v[i][r]);
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < U1; ++i) {
+      const int u = tid + i * nthr;
+      if (u < units) {
+        int s, j;
+        ci_unit<JF>(u, lognseq, LOGN - LR1, s, j);
+        const int p0 = ((j << LR1) << lognseq) + s;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buf[pidx(p0 + (r << lognseq))] = v[i][r];
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (LASTF) {
+    if constexpr (FIRST) lds_fft_ci<T, DIR, E, 8, LOGN, LR1, TW, LAST>(buf, lognseq, tw, tid, nthr);
+    else lds_fft_ci<T, DIR, E, 8, LOGN, 0, TW, LAST>(buf, lognseq, tw, tid, nthr);
+    constexpr int LRL = LOGN - LAST, RL = 1 << LRL, UL = E / RL, NS = 1 << LAST;
+    const int units = 1 << (lognseq + LAST);
+    C2<T> q[UL][RL];
+#pragma unroll
+    for (int i = 0; i < UL; ++i) {
+      int s, j;
+      ci_unit<JF>(imin(tid + i * nthr, units - 1), lognseq, LAST, s, j);
+      const int p0 = (j << lognseq) + s;
+      const int pb = pidx(p0);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) q[i][r] = buf[pidx_run(pb, p0, r, NS << lognseq)];
+    }
+#pragma unroll
+    for (int i = 0; i < UL; ++i) {
+      if constexpr (NS > 1) {
+        int s, j;
+        ci_unit<JF>(imin(tid + i * nthr, units - 1), lognseq, LAST, s, j);
+        C2<T> w[RL];
+        twiddle_powers<T, DIR, RL>(tw, NS * RL, j, w);
+#pragma unroll
+        for (int r = 1; r < RL; ++r) q[i][r] = cmul(q[i][r], w[r]);
+      }
+      dft_reg<T, RL, DIR>(q[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < UL; ++i) {
+      const int u = tid + i * nthr;
+      if (u < units) {
+        int s, j;
+        ci_unit<JF>(u, lognseq, LAST, s, j);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) store(i, r, s, j + r * NS, q[i][r]);
+      }
+    }
+  } else {
+    if constexpr (FIRST) lds_fft_ci<T, DIR, E, 8, LOGN, LR1, TW>(buf, lognseq, tw, tid, nthr);
+    else lds_fft_ci<T, DIR, E, 8, LOGN, 0, TW>(buf, lognseq, tw, tid, nthr);
   }
 }
 

@@ -119,13 +119,67 @@ __device__ __forceinline__ C2<T> load_sample_pair(const T* __restrict__ xs, cons
 }
 
 // ---------------------------------------------------------------------------
+// Dispatches a runtime FFT length 2^logn (1..10) to BODY<L>(args...).
+#define SLICQ_LOGN_SWITCH(logn, CALL)                                                              \
+  switch (logn) {                                                                                 \
+    case 1: CALL(1); break;                                                                       \
+    case 2: CALL(2); break;                                                                       \
+    case 3: CALL(3); break;                                                                       \
+    case 4: CALL(4); break;                                                                       \
+    case 5: CALL(5); break;                                                                       \
+    case 6: CALL(6); break;                                                                       \
+    case 7: CALL(7); break;                                                                       \
+    case 8: CALL(8); break;                                                                       \
+    case 9: CALL(9); break;                                                                       \
+    default: CALL(10); break;                                                                     \
+  }
+
 // Forward FFT of a slice, pass 1: columns. The N complex values
 // z[n] = x_m[2n] + i x_m[2n+1] are indexed n = n1 + N1 n2; this item takes the
-// C columns n1 in [cb C, cb C + C), transforms each over n2 (length N2),
-// applies e^{-2 pi i n1 k2 / N} and stores W1[k2 N1 + n1]. Samples outside
-// the support of h_0 are not read (their pair index is clamped into it and the
-// window, zero there, drops them). TWL stages the FFT twiddles in LDS.
-// LDS: values (padded) | twiddles.
+// C columns n1 in [cb C, cb C + C), transforms each over n2 (length N2 =
+// 2^LOGN), applies e^{-2 pi i n1 k2 / N} and stores W1[k2 N1 + n1]. The first
+// FFT pass reads the windowed samples directly and the last one stores to W1.
+// Samples outside the support of h_0 are not read (their pair index is
+// clamped into it and the window, zero there, drops them). plain (uniform):
+// the whole window lies inside the valid, unwrapped part of the signal, so
+// pairs are single vector loads; only the loads differ between the two cases,
+// the arithmetic is one code path (a signal's result does not depend on where
+// it sits in a batch).
+template <class T, int LOGN, class TW>
+__device__ __forceinline__ void fwd_pass1_body(const KArgs<T>& a, const SliceTask& tk, int cb, C2<T>* buf,
+                                               const TW& tws, const T* __restrict__ x, C2<T>* __restrict__ out,
+                                               bool plain, int tid, int nthr) {
+  constexpr int LAST = last_pass_logns(LOGN, 8), RL = 1 << (LOGN - LAST), UL = kPassE / RL, NS = 1 << LAST;
+  const int jlo = ((a.N - a.Mt) / 2) & ~1;           // first sample pair touching the support of h_0
+  const int jhi = (a.N + (a.N + a.Mt) / 2 - 1) & ~1;  // last one
+  const T* __restrict__ xs = x + tk.x_base;
+  const SliceIn si = slice_in(tk);
+  const int c0 = cb * a.C, smask = a.C - 1;
+  // inter-step twiddles of this thread's outputs, fetched before the transform
+  C2<T> w[UL][RL];
+  const int unitsL = 1 << (a.logC + LAST);
+#pragma unroll
+  for (int i = 0; i < UL; ++i) {
+    const int u = imin(tid + i * nthr, unitsL - 1);
+    const int n1 = c0 + (u & smask), j = u >> a.logC;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) w[i][r] = twiddle<T, -1>(a.tw, a.N, (n1 * (j + r * NS)) & (a.N - 1));
+  }
+  auto load = [&](int s, int e) -> C2<T> {
+    const int j = 2 * (c0 + s + a.N1 * e);
+    const int jc = imin(imax(j, jlo), jhi);
+    C2<T> x2;
+    if (plain) x2 = *reinterpret_cast<const C2<T>*>(xs + si.start + jc);
+    else x2 = load_sample_pair(xs, si, jc);
+    const C2<T> h2 = *reinterpret_cast<const C2<T>*>(a.h0 + j);
+    // rounded by itself: the same value whichever load path (and code) fed it
+    return {mul_rn(x2.x, h2.x), mul_rn(x2.y, h2.y)};
+  };
+  auto store = [&](int i, int r, int s, int e, C2<T> v) { out[e * a.N1 + c0 + s] = cmul(v, w[i][r]); };
+  fft_ci_fused<T, -1, kPassE, LOGN, true, true, false>(buf, a.logC, tws, tid, nthr, load, store);
+}
+
+// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
 __global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict__ x, C2<T>* __restrict__ W1) {
@@ -136,56 +190,18 @@ k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;                              // unused task slot
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int total = a.C * a.N2;
-  C2<T>* twl = buf + padded(total);
-  // even sample pairs (j, j + 1) meeting the support (N-M)/2 < j - N + ... of h_0
-  const int jlo = ((a.N - a.Mt) / 2) & ~1;           // first pair touching the support
-  const int jhi = (a.N + (a.N + a.Mt) / 2 - 1) & ~1;  // last pair touching it
-  const T* __restrict__ xs = x + tk.x_base;
-  const SliceIn si = slice_in(tk);
-  // whole window inside the valid, unwrapped part of the signal: plain loads
-  const bool plain = si.even && si.start >= 0 && si.start + 2 * a.N <= imin(si.valid, si.period);
-  C2<T> s2[kPassE], h2[kPassE], w[kPassE];
-  if (plain) {
-#pragma unroll
-    for (int i = 0; i < kPassE; ++i) {
-      const int e = imin(tid + i * nthr, total - 1);
-      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
-      s2[i] = *reinterpret_cast<const C2<T>*>(xs + si.start + imin(imax(j, jlo), jhi));
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < kPassE; ++i) {
-      const int e = imin(tid + i * nthr, total - 1);
-      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
-      s2[i] = load_sample_pair(xs, si, imin(imax(j, jlo), jhi));
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = imin(tid + i * nthr, total - 1);
-    const int n1 = cb * a.C + (e & (a.C - 1)), k2 = e >> a.logC;
-    h2[i] = *reinterpret_cast<const C2<T>*>(a.h0 + 2 * (n1 + a.N1 * k2));
-    w[i] = twiddle<T, -1>(a.tw, a.N, (n1 * k2) & (a.N - 1));
-  }
+  C2<T>* twl = buf + padded(a.C * a.N2);
   if constexpr (TWL) stage_twiddles(twl, a.tw, a.N2, tid, nthr);
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) buf[pidx(e)] = {s2[i].x * h2[i].x, s2[i].y * h2[i].y};
-  }
-  __syncthreads();
-  if constexpr (TWL) lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN2, a.logC, TwLds<T>{twl}, tid, nthr);
-  else lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN2, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
+  const SliceIn si = slice_in(tk);
+  const bool plain = si.even && si.start >= 0 && si.start + 2 * a.N <= imin(si.valid, si.period);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) {
-      const int n1 = cb * a.C + (e & (a.C - 1)), k2 = e >> a.logC;
-      out[k2 * a.N1 + n1] = cmul(buf[pidx(e)], w[i]);
-    }
-  }
+  const TwLds<T> tl{twl};
+  const TwGlobal<T> tg{a.tw};
+#define SLICQ_P1(L)                                                                      \
+  if constexpr (TWL) fwd_pass1_body<T, L>(a, tk, cb, buf, tl, x, out, plain, tid, nthr);  \
+  else fwd_pass1_body<T, L>(a, tk, cb, buf, tg, x, out, plain, tid, nthr);
+  SLICQ_LOGN_SWITCH(a.logN2, SLICQ_P1)
+#undef SLICQ_P1
 }
 
 // Rows handled by a pass-2 item rb: sequence s < P is the row rb P + s,
@@ -243,9 +259,18 @@ __device__ __forceinline__ void real_split(C2<T> za, C2<T> zb, C2<T> w, T s, C2<
 }
 
 // Forward pass 2: rows. Each item takes P row pairs, transforms them over n1
-// (length N1), giving Zc[N2 k1 + k2], and splits pairs (k, N - k) into the
-// real spectrum X[0..N] of the slice (W2). TWL stages the FFT twiddles in LDS.
-// LDS: values (padded) | twiddles.
+// (length N1 = 2^LOGN), giving Zc[N2 k1 + k2], and splits pairs (k, N - k)
+// into the real spectrum X[0..N] of the slice (W2). The rows are read in
+// natural order (coalesced) into LDS first: a fused first pass would read
+// them coalesced only in an order whose LDS writes conflict on one bank.
+template <class T, int LOGN, class TW>
+__device__ __forceinline__ void fwd_pass2_fft(int logTwoP, C2<T>* buf, const TW& tws, int tid, int nthr) {
+  auto none_ld = [](int, int) { return C2<T>{T(0), T(0)}; };
+  auto none_st = [](int, int, int, int, C2<T>) {};
+  fft_ci_fused<T, -1, kPassE, LOGN, false, false, false>(buf, logTwoP, tws, tid, nthr, none_ld, none_st);
+}
+
+// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
 __global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
@@ -259,18 +284,19 @@ k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
   C2<T>* twl = buf + padded(total);
   const C2<T>* in = W1 + (int64_t)task * a.ws1;
   constexpr int U = kPassE / 2;
-  C2<T> v[kPassE], w[U];
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = imin(tid + i * nthr, total - 1);
-    v[i] = in[pass2_row(rb, e >> a.logN1, P, a.N2) * a.N1 + (e & (a.N1 - 1))];
-  }
+  C2<T> w[U];
 #pragma unroll
   for (int i = 0; i < U; ++i) {
     const PairIdx q = pass2_pair(imin(tid + i * nthr, units - 1), rb, P, a.logP, a.N1, a.N2, logTwoP);
     w[i] = twiddle<T, -1>(a.tw, 2 * N, q.k);
   }
   const C2<T> w2 = twiddle<T, -1>(a.tw, 2 * N, N / 2);
+  C2<T> v[kPassE];
+#pragma unroll
+  for (int i = 0; i < kPassE; ++i) {
+    const int e = imin(tid + i * nthr, total - 1);
+    v[i] = in[pass2_row(rb, e >> a.logN1, P, a.N2) * a.N1 + (e & (a.N1 - 1))];
+  }
   if constexpr (TWL) stage_twiddles(twl, a.tw, a.N1, tid, nthr);
 #pragma unroll
   for (int i = 0; i < kPassE; ++i) {
@@ -278,8 +304,13 @@ k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
     if (e < total) buf[pidx(((e & (a.N1 - 1)) << logTwoP) + (e >> a.logN1))] = v[i];
   }
   __syncthreads();
-  if constexpr (TWL) lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN1, logTwoP, TwLds<T>{twl}, tid, nthr);
-  else lds_fft_interleaved<T, -1, kPassE, 8>(buf, a.logN1, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
+  const TwLds<T> tl{twl};
+  const TwGlobal<T> tg{a.tw};
+#define SLICQ_P2(L)                                                   \
+  if constexpr (TWL) fwd_pass2_fft<T, L>(logTwoP, buf, tl, tid, nthr); \
+  else fwd_pass2_fft<T, L>(logTwoP, buf, tg, tid, nthr);
+  SLICQ_LOGN_SWITCH(a.logN1, SLICQ_P2)
+#undef SLICQ_P2
   C2<T>* X = W2 + (int64_t)task * a.ws2;
 #pragma unroll
   for (int i = 0; i < U; ++i) {
@@ -642,6 +673,29 @@ __device__ __forceinline__ void herm_pack(C2<T> a, C2<T> b, C2<T> u, C2<T>& zk, 
   znk = cconj(csub(Pp, mul_mi<T, 1>(Q)));         // conj(P - iQ)
 }
 
+// Row IFFTs of inverse pass A (length N1 = 2^LOGN) from the packed spectrum in
+// LDS; the last FFT pass applies e^{+2 pi i n1 k2 / N} and stores W1.
+template <class T, int LOGN, class TW>
+__device__ __forceinline__ void inv_passA_fft(const KArgs<T>& a, int rb, int logTwoP, C2<T>* buf, const TW& tws,
+                                              C2<T>* __restrict__ out, int tid, int nthr) {
+  constexpr int LAST = last_pass_logns(LOGN, 8), RL = 1 << (LOGN - LAST), UL = kPassE / RL, NS = 1 << LAST;
+  const int unitsL = 1 << (logTwoP + LAST);
+  C2<T> tw[UL][RL];
+#pragma unroll
+  for (int i = 0; i < UL; ++i) {
+    int s, j;
+    ci_unit<true>(imin(tid + i * nthr, unitsL - 1), logTwoP, LAST, s, j);
+    const int row = pass2_row(rb, s, a.P, a.N2);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) tw[i][r] = twiddle<T, 1>(a.tw, a.N, ((j + r * NS) * row) & (a.N - 1));
+  }
+  auto none = [](int, int) { return C2<T>{T(0), T(0)}; };
+  auto store = [&](int i, int r, int s, int e, C2<T> v) {
+    out[pass2_row(rb, s, a.P, a.N2) * a.N1 + e] = cmul(v, tw[i][r]);
+  };
+  fft_ci_fused<T, 1, kPassE, LOGN, false, true, true>(buf, logTwoP, tws, tid, nthr, none, store);
+}
+
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
 __global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
@@ -657,8 +711,8 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   C2<T>* twl = buf + padded(total);
   const C2<T>* Z = W2 + (int64_t)task * a.ws2;
   constexpr int U = kPassE / 2;
-  // every load first: spectrum pairs, their twiddles, the inter-step twiddles
-  C2<T> za[U], zb[U], w[U], tw[kPassE];
+  // every load first: spectrum pairs and their twiddles
+  C2<T> za[U], zb[U], w[U];
 #pragma unroll
   for (int i = 0; i < U; ++i) {
     const PairIdx q = pass2_pair(imin(tid + i * nthr, units - 1), rb, P, a.logP, N1, N2, logTwoP);
@@ -667,12 +721,6 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
     w[i] = twiddle<T, 1>(a.tw, 2 * N, q.k);
   }
   const C2<T> zh = Z[N / 2], wh = twiddle<T, 1>(a.tw, 2 * N, N / 2);
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = imin(tid + i * nthr, total - 1);
-    const int row = pass2_row(rb, e >> a.logN1, P, N2);
-    tw[i] = twiddle<T, 1>(a.tw, N, ((e & (N1 - 1)) * row) & (N - 1));
-  }
   if constexpr (TWL) stage_twiddles(twl, a.tw, N1, tid, nthr);
 #pragma unroll
   for (int i = 0; i < U; ++i) {
@@ -690,18 +738,14 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
     }
   }
   __syncthreads();
-  if constexpr (TWL) lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN1, logTwoP, TwLds<T>{twl}, tid, nthr);
-  else lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN1, logTwoP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) {
-      const int s = e >> a.logN1, n1 = e & (N1 - 1);
-      const int row = pass2_row(rb, s, P, N2);
-      out[row * N1 + n1] = cmul(buf[pidx((n1 << logTwoP) + s)], tw[i]);
-    }
-  }
+  const TwLds<T> tl{twl};
+  const TwGlobal<T> tg{a.tw};
+#define SLICQ_PA(L)                                                          \
+  if constexpr (TWL) inv_passA_fft<T, L>(a, rb, logTwoP, buf, tl, out, tid, nthr); \
+  else inv_passA_fft<T, L>(a, rb, logTwoP, buf, tg, out, tid, nthr);
+  SLICQ_LOGN_SWITCH(a.logN1, SLICQ_PA)
+#undef SLICQ_PA
 }
 
 // Adds v at window position j of the slice into the output: plain stores where
@@ -721,9 +765,36 @@ __device__ __forceinline__ void ola_store(T* __restrict__ ys, int ystart, int yp
 }
 
 // Inverse pass B: columns n1 in [cb C, cb C + C): transform over k2 (length
-// N2, e^+), giving z[n1 + N1 n2] = y[2n] + i y[2n+1]; scale, multiply by the
-// synthesis slice window and overlap-add (Algorithm 4). TWL stages the FFT
-// twiddles in LDS. LDS: values (padded) | twiddles.
+// N2 = 2^LOGN, e^+; the first FFT pass reads W1 directly), giving
+// z[n1 + N1 n2] = y[2n] + i y[2n+1]; the last pass scales, multiplies by the
+// synthesis slice window and overlap-adds into the output (Algorithm 4).
+template <class T, int LOGN, class TW>
+__device__ __forceinline__ void inv_passB_body(const KArgs<T>& a, const SliceTask& tk, int cb, C2<T>* buf,
+                                               const TW& tws, const C2<T>* __restrict__ in, T* __restrict__ y,
+                                               int tid, int nthr) {
+  constexpr int LAST = last_pass_logns(LOGN, 8), RL = 1 << (LOGN - LAST), UL = kPassE / RL, NS = 1 << LAST;
+  const int c0 = cb * a.C, smask = a.C - 1, unitsL = 1 << (a.logC + LAST);
+  // synthesis window at this thread's outputs, fetched before the transform
+  C2<T> h[UL][RL];
+#pragma unroll
+  for (int i = 0; i < UL; ++i) {
+    const int u = imin(tid + i * nthr, unitsL - 1);
+    const int n1 = c0 + (u & smask), j = u >> a.logC;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) h[i][r] = *reinterpret_cast<const C2<T>*>(a.hsyn + 2 * (n1 + a.N1 * (j + r * NS)));
+  }
+  T* __restrict__ ys = y + tk.y_base;
+  const int ys0 = (int)tk.y_start, yper = (int)tk.y_period, yval = (int)tk.y_valid;
+  auto load = [&](int s, int e) -> C2<T> { return in[e * a.N1 + c0 + s]; };
+  auto store = [&](int i, int r, int s, int e, C2<T> z) {
+    const int j = 2 * (c0 + s + a.N1 * e);
+    ola_store(ys, ys0, yper, yval, j, z.x * a.scale * h[i][r].x, a.N, a.Mt);
+    ola_store(ys, ys0, yper, yval, j + 1, z.y * a.scale * h[i][r].y, a.N, a.Mt);
+  };
+  fft_ci_fused<T, 1, kPassE, LOGN, true, true, false>(buf, a.logC, tws, tid, nthr, load, store);
+}
+
+// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
 __global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W1, T* __restrict__ y) {
@@ -734,41 +805,16 @@ k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __rest
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int total = a.C * a.N2;
-  C2<T>* twl = buf + padded(total);
-  const C2<T>* in = W1 + (int64_t)task * a.ws1;
-  C2<T> v[kPassE], h[kPassE];
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = imin(tid + i * nthr, total - 1);
-    v[i] = in[(e >> a.logC) * a.N1 + cb * a.C + (e & (a.C - 1))];
-  }
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = imin(tid + i * nthr, total - 1);
-    h[i] = *reinterpret_cast<const C2<T>*>(a.hsyn + 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC)));
-  }
+  C2<T>* twl = buf + padded(a.C * a.N2);
   if constexpr (TWL) stage_twiddles(twl, a.tw, a.N2, tid, nthr);
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) buf[pidx(e)] = v[i];
-  }
-  __syncthreads();
-  if constexpr (TWL) lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN2, a.logC, TwLds<T>{twl}, tid, nthr);
-  else lds_fft_interleaved<T, 1, kPassE, 8>(buf, a.logN2, a.logC, TwGlobal<T>{a.tw}, tid, nthr);
-  T* __restrict__ ys = y + tk.y_base;
-  const int ys0 = (int)tk.y_start, yper = (int)tk.y_period, yval = (int)tk.y_valid;
-#pragma unroll
-  for (int i = 0; i < kPassE; ++i) {
-    const int e = tid + i * nthr;
-    if (e < total) {
-      const int j = 2 * (cb * a.C + (e & (a.C - 1)) + a.N1 * (e >> a.logC));
-      const C2<T> z = buf[pidx(e)];
-      ola_store(ys, ys0, yper, yval, j, z.x * a.scale * h[i].x, a.N, a.Mt);
-      ola_store(ys, ys0, yper, yval, j + 1, z.y * a.scale * h[i].y, a.N, a.Mt);
-    }
-  }
+  const C2<T>* in = W1 + (int64_t)task * a.ws1;
+  const TwLds<T> tl{twl};
+  const TwGlobal<T> tg{a.tw};
+#define SLICQ_PB(L)                                                              \
+  if constexpr (TWL) inv_passB_body<T, L>(a, tk, cb, buf, tl, in, y, tid, nthr); \
+  else inv_passB_body<T, L>(a, tk, cb, buf, tg, in, y, tid, nthr);
+  SLICQ_LOGN_SWITCH(a.logN2, SLICQ_PB)
+#undef SLICQ_PB
 }
 
 // Zeroes the right-hand output overlap of every task (used when slices are
