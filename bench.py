@@ -70,24 +70,24 @@ def measured_traffic(kernel: str, workload: str = "c2"):
     return int(rec["kernels"][kernel]["traffic_bytes"])
 
 
-def time_stages(plan, n_slices, x, coef, y, reps=20):
+def time_stages(plan, n_slices, x, coef, y, reps=20, layout=None):
     import torch
     out = {}
     for s, name in enumerate(STAGES):
-        plan.profile_stage(s, n_slices, x, coef, y)
+        plan.profile_stage(s, n_slices, x, coef, y, layout=layout)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            plan.profile_stage(s, n_slices, x, coef, y)
+            plan.profile_stage(s, n_slices, x, coef, y, layout=layout)
         e1.record()
         torch.cuda.synchronize()
         out[name] = e0.elapsed_time(e1) / reps
     return out
 
 
-def _stage_report(plan, n_slices, x, coef, y, reps):
-    ms = time_stages(plan, n_slices, x, coef, y, reps)
+def _stage_report(plan, n_slices, x, coef, y, reps, layout=None):
+    ms = time_stages(plan, n_slices, x, coef, y, reps, layout)
     sb = stage_bytes(plan, n_slices, 4)
     return {k: {"ms": round(ms[k], 4), "GBs": round(sb[k] / (ms[k] * 1e-3) / 1e9, 1)} for k in STAGES}
 
@@ -169,7 +169,7 @@ def bench_batched(args):
     err = float((y - x).abs().max())
     ms_eager = _time(lambda: (plan.analyze_batched(x, out=coef, layout=lay),
                               plan.synthesize_batched(coef, out=y, layout=lay)), args.steps, args.warmup)
-    stages = _stage_report(plan, lay.total_slices, x, coef, y, args.stage_reps)
+    stages = _stage_report(plan, lay.total_slices, x, coef, y, args.stage_reps, lay)
     offs = lay.x_off
     cofs = lay.coef_off
     views = [(x[offs[i]:offs[i + 1]], coef[cofs[i]:cofs[i] + lay.slices[i] * plan.coefs_per_slice],
@@ -230,7 +230,7 @@ def bench_differentiable(args):
     ms_adj = _time(lambda: plan.synthesize_batched(coef, out=yy, layout=lay, adjoint=True), args.steps, args.warmup)
     plan.analyze_batched(xf, out=coef, layout=lay)
     plan.synthesize_batched(coef, out=yy, layout=lay)
-    stages = _stage_report(plan, lay.total_slices, xf, coef, yy, args.stage_reps)
+    stages = _stage_report(plan, lay.total_slices, xf, coef, yy, args.stage_reps, lay)
     samples = B * T
     rate = lambda ms: round(samples / (ms * 1e-3) / 1e6, 1)
     return {"metric": METRIC, "value": rate(ms_fb), "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
@@ -406,7 +406,7 @@ def main():
 
     # per-kernel timing of the pipeline the last step launched (HIP events on the same stream)
     S = lay.total_slices
-    stage_ms = time_stages(plan, S, x, coef, y, args.stage_reps)
+    stage_ms = time_stages(plan, S, x, coef, y, args.stage_reps, lay)
     sbytes = stage_bytes(plan, S, 4)
     stages = {k: {"ms": round(stage_ms[k], 4), "GBs": round(sbytes[k] / (stage_ms[k] * 1e-3) / 1e9, 1)}
               for k in STAGES}

@@ -177,6 +177,33 @@ int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dtype, const void* coef, 
                           int32_t nsig, int64_t total_slices, void* work, size_t work_bytes,
                           void* hip_stream);
 
+/* Prepared batches: the slice task table of a ragged batch built once and
+ * reused by any number of transforms of batches with the same offsets (the
+ * batched calls above rebuild it on every call). slicq_batch_tasks_bytes
+ * gives the size of the caller-owned device buffer `tasks`.
+ * slicq_batch_create enqueues the build on hip_stream (offsets as for the
+ * batched calls; x_len and coef_len bound the signal and coefficient ranges
+ * the tasks may address) and returns a host handle that keeps the plan, the
+ * tasks pointer and these bounds; the offsets may be freed once the build has
+ * run. slicq_*_batch then run the transform with the prepared tasks: buffers
+ * must be at least x_len / coef_len long (SLICQ_ESIZE otherwise) and the
+ * tasks buffer must stay alive and unmodified. A workspace smaller than
+ * slicq_workspace_size(total_slices) is processed in chunks. The handle is
+ * immutable after creation; destroy it with slicq_batch_destroy (host memory
+ * only). Per-signal results are identical to the other calls. */
+typedef struct slicq_batch_s* slicq_batch;
+size_t slicq_batch_tasks_bytes(int64_t total_slices);
+int slicq_batch_create(slicq_plan plan, const int64_t* x_off, const int64_t* coef_off, int32_t nsig,
+                       int64_t total_slices, int64_t x_len, int64_t coef_len, void* tasks, size_t tasks_bytes,
+                       void* hip_stream, slicq_batch* out);
+void slicq_batch_destroy(slicq_batch batch);
+int slicq_analyze_batch(slicq_batch batch, slicq_dtype dtype, const void* x, int64_t x_len, void* coef,
+                        int64_t coef_len, void* work, size_t work_bytes, void* hip_stream);
+int slicq_synthesize_batch(slicq_batch batch, slicq_dtype dtype, const void* coef, int64_t coef_len, void* y,
+                           int64_t y_len, void* work, size_t work_bytes, void* hip_stream);
+int slicq_adjoint_batch(slicq_batch batch, slicq_dtype dtype, const void* coef, int64_t coef_len, void* y,
+                        int64_t y_len, void* work, size_t work_bytes, void* hip_stream);
+
 /* ---- Streaming service (real-time streams, continuously batched) ----------
  * Each stream is the linear sliCQ of an unbounded signal that is zero before
  * sample 0: slice m is centred on sample mN (Algorithm 3) and becomes ready
@@ -242,6 +269,12 @@ int slicq_stream_restore(slicq_stream_server server, int32_t id, const void* buf
  * samples of y, which stage 3 zeroes). */
 int slicq_profile_stage(slicq_plan plan, slicq_dtype dtype, int stage, int64_t n_slices, const void* x,
                         void* coef, void* y, void* work, size_t work_bytes, void* hip_stream);
+/* The same for a prepared batch: re-launches one stage over all of its
+ * slices, reading what the preceding slicq_*_batch call left in `work`
+ * (buffers at least as long as the batch was prepared for). */
+int slicq_profile_stage_batch(slicq_batch batch, slicq_dtype dtype, int stage, const void* x, int64_t x_len,
+                              void* coef, int64_t coef_len, void* y, int64_t y_len, void* work, size_t work_bytes,
+                              void* hip_stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* slicq_last_error(void);

@@ -91,6 +91,13 @@ def load_library():
         "slicq_synthesize_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_adjoint_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_profile_stage": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, I64, P, P, P, P, SZ, P]),
+        "slicq_batch_tasks_bytes": (SZ, [I64]),
+        "slicq_profile_stage_batch": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
+        "slicq_batch_create": (ctypes.c_int, [P, P, P, I32, I64, I64, I64, P, SZ, P, ctypes.POINTER(P)]),
+        "slicq_batch_destroy": (None, [P]),
+        "slicq_analyze_batch": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_synthesize_batch": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_adjoint_batch": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
         "slicq_stream_server_create": (ctypes.c_int, [P, ctypes.c_int, I32, I32, SZ, ctypes.POINTER(P)]),
         "slicq_stream_server_destroy": (None, [P]),
         "slicq_stream_open": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
@@ -161,6 +168,7 @@ class BatchLayout:
         self.total_slices = int(S.sum())
         self.coef_len = int(c_sz.sum())
         self._dev = {}
+        self._plan = plan          # a prepared task table is only valid for this plan
 
     @property
     def nsig(self) -> int:
@@ -172,6 +180,37 @@ class BatchLayout:
             torch = _torch()
             self._dev[key] = (torch.as_tensor(self.x_off, device=dev), torch.as_tensor(self.coef_off, device=dev))
         return self._dev[key]
+
+    def prepared(self, plan, dev):
+        """Handle of this batch's slice task table on dev (built once, on the current stream)."""
+        key = ("tasks", str(dev))
+        if key not in self._dev:
+            torch = _torch()
+            lib = plan._lib
+            d_xoff, d_coff = self.device(dev)
+            nb = lib.slicq_batch_tasks_bytes(self.total_slices)
+            tasks = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=dev)
+            h = ctypes.c_void_p()
+            _check(lib.slicq_batch_create(plan._h, ctypes.c_void_p(d_xoff.data_ptr()),
+                                          ctypes.c_void_p(d_coff.data_ptr()), self.nsig, self.total_slices,
+                                          int(self.x_off[-1]), self.coef_len, ctypes.c_void_p(tasks.data_ptr()),
+                                          tasks.numel(), ctypes.c_void_p(_stream_ptr(dev)), ctypes.byref(h)))
+            self._dev[key] = (tasks, _BatchHandle(lib, h))
+        return self._dev[key][1].h
+
+    @property
+    def is_preparable(self) -> bool:
+        return self.nsig > 0 and self.total_slices > 0
+
+
+class _BatchHandle:
+    def __init__(self, lib, h):
+        self.lib, self.h = lib, h
+
+    def __del__(self):
+        if self.h is not None and self.h.value:
+            self.lib.slicq_batch_destroy(self.h)
+            self.h = None
 
 
 class Plan:
@@ -218,6 +257,7 @@ class Plan:
                                    self.lengths.ctypes.data, self.fc.ctypes.data, self.bw.ctypes.data))
         self._tables = {}
         self._work = {}
+        self._tasks_in = {}       # (dtype, device) -> slices whose task table the internal workspace holds
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -264,6 +304,7 @@ class Plan:
         if w is None or w.numel() < need:
             w = torch.empty(need, dtype=torch.uint8, device=device)
             self._work[key] = w
+            self._tasks_in.pop(key, None)
         return w, w.numel()
 
     # -- shapes -------------------------------------------------------------
@@ -306,7 +347,12 @@ class Plan:
         _check(self._lib.slicq_analyze(self._h, dt, ctypes.c_void_p(x.data_ptr()), T,
                                        ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(w.data_ptr()),
                                        wb, ctypes.c_void_p(_stream_ptr(x.device))))
+        self._note_tasks(dt, x.device, S, work)
         return out
+
+    def _note_tasks(self, dt, device, n, work):
+        if work is None:
+            self._tasks_in[(dt, str(device))] = int(n)
 
     def _synth(self, coef, T, adjoint, out, work):
         torch = _torch()
@@ -322,6 +368,7 @@ class Plan:
         fn = self._lib.slicq_adjoint if adjoint else self._lib.slicq_synthesize
         _check(fn(self._h, dt, ctypes.c_void_p(coef.data_ptr()), coef.numel(), ctypes.c_void_p(out.data_ptr()),
                   int(T), ctypes.c_void_p(w.data_ptr()), wb, ctypes.c_void_p(_stream_ptr(coef.device))))
+        self._note_tasks(dt, coef.device, S, work)
         return out
 
     def synthesize(self, coef, T: int, out=None, work=None):
@@ -357,14 +404,22 @@ class Plan:
         if out is None:
             out = torch.empty(max(lay.coef_len, 1), dtype=ctype, device=x_packed.device)
         _require_cuda(out, "out")
-        d_xoff, d_coff = lay.device(x_packed.device)
         self._ensure_tables(dt, x_packed.device)
         w, wb = self._workspace(dt, lay.total_slices, x_packed.device, work)
+        if layout is not None and lay.is_preparable and lay._plan is self:
+            # the task table of a reused layout is built once (slicq_batch_create)
+            _check(self._lib.slicq_analyze_batch(
+                lay.prepared(self, x_packed.device), dt, ctypes.c_void_p(x_packed.data_ptr()), x_packed.numel(),
+                ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(w.data_ptr()), wb,
+                ctypes.c_void_p(_stream_ptr(x_packed.device))))
+            return out
+        d_xoff, d_coff = lay.device(x_packed.device)
         _check(self._lib.slicq_analyze_batched(
             self._h, dt, ctypes.c_void_p(x_packed.data_ptr()), x_packed.numel(), ctypes.c_void_p(d_xoff.data_ptr()),
             lay.nsig, lay.total_slices, ctypes.c_void_p(out.data_ptr()), out.numel(),
             ctypes.c_void_p(d_coff.data_ptr()), ctypes.c_void_p(w.data_ptr()), wb,
             ctypes.c_void_p(_stream_ptr(x_packed.device))))
+        self._note_tasks(dt, x_packed.device, lay.total_slices, work)
         return out
 
     def synthesize_batched(self, coef, lengths=None, out=None, work=None, layout: Optional[BatchLayout] = None,
@@ -378,19 +433,36 @@ class Plan:
         if out is None:
             out = torch.empty(max(int(lay.x_off[-1]), 1), dtype=rtype, device=coef.device)
         _require_cuda(out, "out")
-        d_xoff, d_coff = lay.device(coef.device)
         self._ensure_tables(dt, coef.device)
         w, wb = self._workspace(dt, lay.total_slices, coef.device, work)
+        if layout is not None and lay.is_preparable and lay._plan is self:
+            fn = self._lib.slicq_adjoint_batch if adjoint else self._lib.slicq_synthesize_batch
+            _check(fn(lay.prepared(self, coef.device), dt, ctypes.c_void_p(coef.data_ptr()), coef.numel(),
+                      ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(w.data_ptr()), wb,
+                      ctypes.c_void_p(_stream_ptr(coef.device))))
+            return out
+        d_xoff, d_coff = lay.device(coef.device)
         fn = self._lib.slicq_adjoint_batched if adjoint else self._lib.slicq_synthesize_batched
         _check(fn(self._h, dt, ctypes.c_void_p(coef.data_ptr()), coef.numel(), ctypes.c_void_p(d_coff.data_ptr()),
                   ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(d_xoff.data_ptr()), lay.nsig,
                   lay.total_slices, ctypes.c_void_p(w.data_ptr()), wb, ctypes.c_void_p(_stream_ptr(coef.device))))
+        self._note_tasks(dt, coef.device, lay.total_slices, work)
         return out
 
-    def profile_stage(self, stage: int, n_slices: int, x, coef, y, work=None):
-        """Enqueues one kernel of the preceding call's pipeline (measurement hook)."""
+    def profile_stage(self, stage: int, n_slices: int, x, coef, y, work=None, layout: Optional[BatchLayout] = None):
+        """Enqueues one kernel of the preceding call's pipeline (measurement hook). Pass the
+        layout if the preceding call was a batched call with a reused layout."""
         dt = _dtype_code(x)
         w, wb = self._workspace(dt, n_slices, x.device, work)
+        if layout is not None and layout.is_preparable and layout._plan is self:
+            _check(self._lib.slicq_profile_stage_batch(
+                layout.prepared(self, x.device), dt, int(stage), ctypes.c_void_p(x.data_ptr()), x.numel(),
+                ctypes.c_void_p(coef.data_ptr()), coef.numel(), ctypes.c_void_p(y.data_ptr()), y.numel(),
+                ctypes.c_void_p(w.data_ptr()), wb, ctypes.c_void_p(_stream_ptr(x.device))))
+            return
+        if work is None and self._tasks_in.get((dt, str(x.device)), -1) != int(n_slices):
+            raise SlicqError("profile_stage: the workspace does not hold the task table of a preceding call over "
+                             f"{n_slices} slices (pass the layout of a prepared batch)")
         _check(self._lib.slicq_profile_stage(self._h, dt, int(stage), int(n_slices), ctypes.c_void_p(x.data_ptr()),
                                              ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                              ctypes.c_void_p(w.data_ptr()), wb,

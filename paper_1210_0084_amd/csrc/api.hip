@@ -19,6 +19,14 @@ struct slicq_plan_s {
   std::vector<unsigned char> blob[2];   // packed tables, kept alive for async uploads
 };
 
+// A prepared ragged batch: its task table (caller-owned device memory) and
+// the bounds the tasks were validated against.
+struct slicq_batch_s {
+  slicq_plan plan;
+  slicq::SliceTask* tasks;
+  int64_t total, x_len, coef_len;
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -602,19 +610,79 @@ int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dt, const void* coef, int
                               work_bytes, stream);
 }
 
-int slicq_profile_stage(slicq_plan plan, slicq_dtype dt, int stage, int64_t n_slices, const void* x, void* coef,
-                        void* y, void* work, size_t work_bytes, void* stream) {
-  int rc = check_plan(plan, dt);
-  if (rc) return rc;
+size_t slicq_batch_tasks_bytes(int64_t total_slices) {
+  return total_slices < 0 ? 0 : slicq::tasks_bytes(total_slices) + 256;   // tasks, then two status words
+}
+
+int slicq_batch_create(slicq_plan plan, const int64_t* x_off, const int64_t* coef_off, int32_t nsig,
+                       int64_t total, int64_t x_len, int64_t coef_len, void* tasks, size_t tasks_bytes,
+                       void* stream, slicq_batch* out) {
+  if (!out) return fail(SLICQ_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!plan) return fail(SLICQ_EINVAL, "null plan");
+  if (nsig <= 0 || total <= 0) return fail(SLICQ_EINVAL, "a prepared batch needs nsig > 0 and total_slices > 0");
+  if (x_len < 0 || coef_len < 0) return fail(SLICQ_EINVAL, "x_len and coef_len must be >= 0");
+  if (!x_off || !coef_off || !tasks) return fail(SLICQ_EINVAL, "null buffer");
+  if (tasks_bytes < slicq_batch_tasks_bytes(total)) return fail(SLICQ_ESIZE, "tasks buffer too small");
   slicq::Plan& p = plan->p;
-  if (stage < 0 || stage > 5) return fail(SLICQ_EINVAL, "stage must be in 0..5");
-  if (n_slices <= 0 || !x || !coef || !y || !work) return fail(SLICQ_EINVAL, "bad argument");
+  auto* t = static_cast<slicq::SliceTask*>(tasks);
+  auto* status = reinterpret_cast<int32_t*>(static_cast<char*>(tasks) + slicq::tasks_bytes(total));
+  batched_tasks(p, x_off, nsig, total, x_len, coef_off, coef_len, t, status, static_cast<hipStream_t>(stream));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "task table launch");
+  *out = new (std::nothrow) slicq_batch_s{plan, t, total, x_len, coef_len};
+  return *out ? SLICQ_OK : fail(SLICQ_ENOMEM, "out of host memory");
+}
+
+void slicq_batch_destroy(slicq_batch batch) { delete batch; }
+
+int slicq_analyze_batch(slicq_batch b, slicq_dtype dt, const void* x, int64_t x_len, void* coef, int64_t coef_len,
+                        void* work, size_t work_bytes, void* stream) {
+  if (!b) return fail(SLICQ_EINVAL, "null batch");
+  int rc = check_plan(b->plan, dt);
+  if (rc) return rc;
+  if (!x || !coef || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (x_len < b->x_len || coef_len < b->coef_len)
+    return fail(SLICQ_ESIZE, "buffers are shorter than the batch was prepared for");
+  slicq::Plan& p = b->plan->p;
   slicq::WorkLayout w;
-  if ((rc = layout_or_fail(p, dt, n_slices, work_bytes, w))) return rc;
-  if (w.chunk < n_slices) return fail(SLICQ_ESIZE, "profiling needs a workspace for all slices at once");
+  if ((rc = layout_or_fail(p, dt, b->total, work_bytes, w))) return rc;
   char* wk = static_cast<char*>(work);
-  const auto* tasks = reinterpret_cast<const slicq::SliceTask*>(wk + w.tasks_off);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  return dt == SLICQ_F32 ? run_analysis<float>(p, dt, b->tasks, b->total, x, coef, w, wk, st)
+                         : run_analysis<double>(p, dt, b->tasks, b->total, x, coef, w, wk, st);
+}
+
+static int synth_batch_common(slicq_batch b, slicq_dtype dt, bool adjoint, const void* coef, int64_t coef_len,
+                              void* y, int64_t y_len, void* work, size_t work_bytes, void* stream) {
+  if (!b) return fail(SLICQ_EINVAL, "null batch");
+  int rc = check_plan(b->plan, dt);
+  if (rc) return rc;
+  if (!coef || !y || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (y_len < b->x_len || coef_len < b->coef_len)
+    return fail(SLICQ_ESIZE, "buffers are shorter than the batch was prepared for");
+  slicq::Plan& p = b->plan->p;
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, b->total, work_bytes, w))) return rc;
+  char* wk = static_cast<char*>(work);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dt == SLICQ_F32 ? run_synthesis<float>(p, dt, adjoint, b->tasks, b->total, coef, y, w, wk, st)
+                         : run_synthesis<double>(p, dt, adjoint, b->tasks, b->total, coef, y, w, wk, st);
+}
+
+int slicq_synthesize_batch(slicq_batch b, slicq_dtype dt, const void* coef, int64_t coef_len, void* y, int64_t y_len,
+                           void* work, size_t work_bytes, void* stream) {
+  return synth_batch_common(b, dt, false, coef, coef_len, y, y_len, work, work_bytes, stream);
+}
+
+int slicq_adjoint_batch(slicq_batch b, slicq_dtype dt, const void* coef, int64_t coef_len, void* y, int64_t y_len,
+                        void* work, size_t work_bytes, void* stream) {
+  return synth_batch_common(b, dt, true, coef, coef_len, y, y_len, work, work_bytes, stream);
+}
+
+static int profile_stage_impl(slicq::Plan& p, slicq_dtype dt, int stage, int64_t n_slices,
+                              const slicq::SliceTask* tasks, const void* x, void* coef, void* y,
+                              const slicq::WorkLayout& w, char* wk, hipStream_t st) {
   HipLaunch L{st};
   auto go = [&](auto tag) {
     using T = decltype(tag);
@@ -642,6 +710,38 @@ int slicq_profile_stage(slicq_plan plan, slicq_dtype dt, int stage, int64_t n_sl
   else go(double{});
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SLICQ_OK : hip_fail(e, "stage launch");
+}
+
+int slicq_profile_stage(slicq_plan plan, slicq_dtype dt, int stage, int64_t n_slices, const void* x, void* coef,
+                        void* y, void* work, size_t work_bytes, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (stage < 0 || stage > 5) return fail(SLICQ_EINVAL, "stage must be in 0..5");
+  if (n_slices <= 0 || !x || !coef || !y || !work) return fail(SLICQ_EINVAL, "bad argument");
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, n_slices, work_bytes, w))) return rc;
+  if (w.chunk < n_slices) return fail(SLICQ_ESIZE, "profiling needs a workspace for all slices at once");
+  char* wk = static_cast<char*>(work);
+  const auto* tasks = reinterpret_cast<const slicq::SliceTask*>(wk + w.tasks_off);
+  return profile_stage_impl(p, dt, stage, n_slices, tasks, x, coef, y, w, wk, static_cast<hipStream_t>(stream));
+}
+
+int slicq_profile_stage_batch(slicq_batch b, slicq_dtype dt, int stage, const void* x, int64_t x_len, void* coef,
+                              int64_t coef_len, void* y, int64_t y_len, void* work, size_t work_bytes, void* stream) {
+  if (!b) return fail(SLICQ_EINVAL, "null batch");
+  int rc = check_plan(b->plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = b->plan->p;
+  if (stage < 0 || stage > 5) return fail(SLICQ_EINVAL, "stage must be in 0..5");
+  if (!x || !coef || !y || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (x_len < b->x_len || y_len < b->x_len || coef_len < b->coef_len)
+    return fail(SLICQ_ESIZE, "buffers are shorter than the batch was prepared for");
+  slicq::WorkLayout w;
+  if ((rc = layout_or_fail(p, dt, b->total, work_bytes, w))) return rc;
+  if (w.chunk < b->total) return fail(SLICQ_ESIZE, "profiling needs a workspace for all slices at once");
+  return profile_stage_impl(p, dt, stage, b->total, b->tasks, x, coef, y, w, static_cast<char*>(work),
+                            static_cast<hipStream_t>(stream));
 }
 
 const char* slicq_last_error(void) { return g_err.c_str(); }

@@ -68,3 +68,29 @@ def test_calls_before_upload_fail_cleanly(lib):
     assert lib.slicq_workspace_size(p._h, 0, 10, ctypes.byref(b)) == 0 and b.value > 0
     assert lib.nsgt_plan_table_bytes(p._h, 1, ctypes.byref(b)) == 0 and b.value > 0
     assert lib.slicq_workspace_size(p._h, 7, 10, ctypes.byref(b)) == -1
+
+
+def test_prepared_batch_validation_host_only(lib):
+    # every check of slicq_batch_create that fails returns before any device work
+    import paper_1210_0084_amd as sq
+    p = sq.Plan(44100, 110, 11025, 12, 8192, 1024)
+    P = ctypes.c_void_p
+    h = P()
+    dummy = P(16)                         # never dereferenced: the calls below fail validation first
+    assert lib.slicq_batch_tasks_bytes(-1) == 0
+    need = lib.slicq_batch_tasks_bytes(10)
+    assert need >= 10 * 96
+    # nsig <= 0 / total <= 0
+    assert lib.slicq_batch_create(p._h, dummy, dummy, 0, 10, 100, 100, dummy, need, None, ctypes.byref(h)) == -1
+    assert lib.slicq_batch_create(p._h, dummy, dummy, 2, 0, 100, 100, dummy, need, None, ctypes.byref(h)) == -1
+    # negative bounds, null buffers, null handle output
+    assert lib.slicq_batch_create(p._h, dummy, dummy, 2, 10, -1, 100, dummy, need, None, ctypes.byref(h)) == -1
+    assert lib.slicq_batch_create(p._h, None, dummy, 2, 10, 100, 100, dummy, need, None, ctypes.byref(h)) == -1
+    assert lib.slicq_batch_create(p._h, dummy, dummy, 2, 10, 100, 100, dummy, need, None, None) == -1
+    # tasks buffer too small
+    assert lib.slicq_batch_create(p._h, dummy, dummy, 2, 10, 100, 100, dummy, need - 1, None, ctypes.byref(h)) == -4
+    assert h.value is None
+    # calls on a null batch handle
+    assert lib.slicq_analyze_batch(None, 0, dummy, 1, dummy, 1, dummy, 1 << 20, None) == -1
+    assert lib.slicq_synthesize_batch(None, 0, dummy, 1, dummy, 1, dummy, 1 << 20, None) == -1
+    lib.slicq_batch_destroy(None)

@@ -166,6 +166,55 @@ def test_small_workspace_runs_in_chunks(sq, dev):
     assert torch.equal(c_full, c_chunk) and torch.equal(y_full, y_chunk)
 
 
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_prepared_batch_equals_batched_calls(sq, dev, dt):
+    # a reused layout runs on its prepared task table (slicq_*_batch); results are
+    # bitwise those of the calls that rebuild the table, also with a chunked workspace
+    import torch
+    for kw, lens in ((TINY2, [300, 0, 128, 1, 777, 64]), (preset("c4"), [20000, 70001, 44100])):
+        plan, _ = gpu_plan(sq, kw)
+        tdt = torch_dtype(dt)
+        xs = [np.random.default_rng(i + 60).standard_normal(n) for i, n in enumerate(lens)]
+        xp = torch.tensor(np.concatenate(xs), dtype=tdt, device=dev)
+        c_ref = plan.analyze_batched(xp, lens).clone()           # rebuilds the task table
+        y_ref = plan.synthesize_batched(c_ref, lens).clone()
+        a_ref = plan.synthesize_batched(c_ref, lens, adjoint=True).clone()
+        lay = plan.batch_layout(lens)
+        c = plan.analyze_batched(xp, layout=lay)
+        y = plan.synthesize_batched(c, layout=lay)
+        adj = plan.synthesize_batched(c, layout=lay, adjoint=True)
+        assert torch.equal(c, c_ref) and torch.equal(y, y_ref) and torch.equal(adj, a_ref)
+        S = lay.total_slices
+        cb = 16 if dt == "f64" else 8
+        small = plan.workspace_bytes(0 if dt == "f32" else 1, S) - max(S - 2, 0) * (2 * plan.N + 64) * cb
+        work = torch.empty(small, dtype=torch.uint8, device=dev)
+        c2 = plan.analyze_batched(xp, layout=lay, work=work)
+        y2 = plan.synthesize_batched(c2, layout=lay, work=work)
+        assert torch.equal(c2, c_ref) and torch.equal(y2, y_ref)
+
+
+def test_prepared_batch_rejects_short_buffers(sq, dev):
+    import ctypes
+    import torch
+    plan, _ = gpu_plan(sq, TINY2)
+    lens = [300, 500]
+    lay = plan.batch_layout(lens)
+    xp = torch.zeros(800, dtype=torch.float32, device=dev)
+    c = plan.analyze_batched(xp, layout=lay)
+    h = lay.prepared(plan, xp.device)
+    w, wb = plan._workspace(0, lay.total_slices, xp.device, None)
+    lib = plan._lib
+    P = ctypes.c_void_p
+    st = P(torch.cuda.current_stream(dev).cuda_stream)
+    assert lib.slicq_analyze_batch(h, 0, P(xp.data_ptr()), 799, P(c.data_ptr()), c.numel(), P(w.data_ptr()), wb,
+                                   st) == -4
+    assert lib.slicq_synthesize_batch(h, 0, P(c.data_ptr()), c.numel() - 1, P(xp.data_ptr()), 800,
+                                      P(w.data_ptr()), wb, st) == -4
+    assert lib.slicq_analyze_batch(h, 0, P(xp.data_ptr()), 800, P(c.data_ptr()), c.numel(), P(w.data_ptr()), 64,
+                                   st) == -4
+    torch.cuda.synchronize()
+
+
 def test_size_errors(sq, dev):
     import torch
     plan, _ = gpu_plan(sq, TINY2)
