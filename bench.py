@@ -346,6 +346,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the step's launches as one HIP graph (same speed on c2)")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (scale for HBM byte counters)")
@@ -383,9 +384,15 @@ def main():
     coef = torch.empty(lay.coef_len, dtype=torch.complex64, device=dev)
     y = torch.empty(2 * T, dtype=torch.float32, device=dev)
 
-    def step():
+    def eager():
         plan.analyze_batched(x, out=coef, layout=lay)
         plan.synthesize_batched(coef, out=y, layout=lay)
+
+    step = eager
+    if args.graph:
+        # the step's 12 launches (analysis + synthesis) captured once, replayed as one graph launch
+        from paper_1210_0084_amd.tuning import BatchGraph
+        step = BatchGraph(plan, x, coef, y, lay).replay
 
     for _ in range(args.warmup):
         step()
@@ -427,7 +434,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "60 s stereo 44.1 kHz pink noise + harmonic tones; B=48, 32.7-22050 Hz, "
-                               "2N=65536, M=8192; analysis+synthesis",
+                               "2N=65536, M=8192; analysis+synthesis" + (" (one HIP graph)" if args.graph else ""),
                    "signals": 2, "samples_per_signal": T, "slices": S, "coefs_per_slice": plan.coefs_per_slice},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
