@@ -42,10 +42,12 @@ __device__ __forceinline__ C2<T> mul_mi(C2<T> a) {
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
-// LDS index with one pad slot every 16 complex values (bank spreading for the
-// strided Stockham stores).
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int padded(int n) { return n + (n >> 4) + 1; }
+// LDS index with one pad slot every 2^kPadShift complex values (bank
+// spreading for the strided Stockham stores; one pad per 8 values measured no
+// faster than one per 16).
+constexpr int kPadShift = 4;
+__device__ __forceinline__ int pidx(int i) { return i + (i >> kPadShift); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> kPadShift) + 1; }
 
 // e^{DIR 2 pi i k / R} for small constant R, as constants.
 template <class T, int R, int DIR>
@@ -274,10 +276,10 @@ __device__ __forceinline__ void lds_fft(C2<T>* buf, int base, int logn, int nseq
 // a butterfly are one computed base plus immediate offsets.
 
 // Padded position of base + r * S for a constant stride S: for S a multiple of
-// 16 the pad count grows by S / 16 per step.
+// the pad run the pad count grows by S >> kPadShift per step.
 template <int S>
 __device__ __forceinline__ int pidx_step(int pb, int p0, int r) {
-  if constexpr (S % 16 == 0) return pb + r * (S + S / 16);
+  if constexpr (S % (1 << kPadShift) == 0) return pb + r * (S + (S >> kPadShift));
   else return pidx(p0 + r * S);
 }
 
@@ -351,10 +353,10 @@ __device__ __forceinline__ void lds_fft_c(C2<T>* buf, int base, int nseq, const 
 }
 
 // INTERLEAVED layout with the length fixed at compile time: element e of
-// sequence s at e * nseq + s (nseq = 2^lognseq at run time). Strides of 16 or
-// more elements use one base plus offsets.
+// sequence s at e * nseq + s (nseq = 2^lognseq at run time). Strides that are
+// multiples of the pad run use one base plus offsets.
 __device__ __forceinline__ int pidx_run(int pb, int p0, int r, int S) {
-  return (S & 15) == 0 ? pb + r * (S + (S >> 4)) : pidx(p0 + r * S);
+  return (S & ((1 << kPadShift) - 1)) == 0 ? pb + r * (S + (S >> kPadShift)) : pidx(p0 + r * S);
 }
 
 template <class T, int DIR, int R, int E, int LOGN, int LOGNS, class TW>
