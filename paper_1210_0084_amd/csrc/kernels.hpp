@@ -538,7 +538,7 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       if (idx < tk.y_valid) y[tk.y_base + idx] = T(0);
     }
   }
-  if (E == 8 && a.min_M >= 8) {
+  if ((E == 8 || E == 16) && a.min_M >= 8) {
     // first radix-8 pass fused with the loads: unit u (all runs flattened,
     // u = p / 8) takes slots j + r M/8 of one band, r = 0..7
     const int units = G.total >> 3;
@@ -575,8 +575,12 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       if (ri == 0) R = G.r[0];
       else if (ri == 1) R = G.r[1];
       else R = a.runs[G.run0 + ri];
-      if constexpr (TWL) lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, tid, nthr);
-      else lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, tid, nthr);
+      // an opaque copy of the thread index: keeps the compiler from hoisting
+      // the address arithmetic of every FFT length out of this loop (registers)
+      int t = tid;
+      asm volatile("" : "+v"(t));
+      if constexpr (TWL) lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, t, nthr);
+      else lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, t, nthr);
     }
   } else {
     // coefficient addresses of a batch of values (no branches), then every load
@@ -621,8 +625,10 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       if (ri == 0) R = G.r[0];
       else if (ri == 1) R = G.r[1];
       else R = a.runs[G.run0 + ri];
-      if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, tid, nthr);
-      else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, tid, nthr);
+      int t = tid;
+      asm volatile("" : "+v"(t));
+      if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, t, nthr);
+      else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, t, nthr);
     }
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;

@@ -117,7 +117,7 @@ struct Geometry {
   // kSynThreads), twiddles in LDS if ts; large items [gs, gs + gsb), bsb
   // threads, E = kBigSynE (bound kSynBigThreads)
   int gs, bs; size_t ss; bool ts;
-  int gsb, bsb; size_t ssb;
+  int gsb, bsb; size_t ssb; bool tsb;
   bool ok;                    // every block fits its kernel's launch bound
 };
 
@@ -147,6 +147,10 @@ Geometry<T> geometry(const Plan& p) {
   g.gsb = (int)p.syn.size() - p.syn_small;
   g.bsb = threads_for(std::max(p.syn_cap_big, 1), kBigSynE);
   g.ssb = lds_tail_offset<T>(p.syn_cap_big);
+  int32_t big_maxM = 0;
+  for (int i = p.syn_small; i < (int)p.syn.size(); ++i) big_maxM = std::max(big_maxM, p.syn[i].maxM);
+  g.tsb = g.ssb + (size_t)big_maxM * cb <= kMaxLdsBytes;     // one block per CU anyway: LDS is free
+  if (g.tsb) g.ssb += (size_t)big_maxM * cb;
   size_t lds = std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss));
   if (g.gab) lds = std::max(lds, g.sab);
   if (g.gsb) lds = std::max(lds, g.ssb);
@@ -180,8 +184,10 @@ void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* t
     if (g.ts) L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, true>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
     else L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
   }
-  if (g.gsb)
-    L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
+  if (g.gsb) {
+    if (g.tsb) L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, true>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
+    else L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
+  }
 }
 
 // Analysis of tasks [t0, t0 + cnt) (Algorithm 3): slice FFT, band transforms.
