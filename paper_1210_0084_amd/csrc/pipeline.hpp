@@ -109,17 +109,27 @@ struct Geometry {
   int g1, b1; size_t s1;      // forward pass 1 / inverse pass B: items per slice, threads, LDS bytes
   int g2, b2; size_t s2;      // forward pass 2 / inverse pass A
   // band analysis: small items [0, ga) with ba threads, E = kSmallE (kernel
-  // bound kAnaThreads), twiddles in LDS if ta; large items [ga, ga + gab) with
-  // bab threads, E = kBigAnaE (bound kAnaBigThreads)
-  int ga, ba; size_t sa; bool ta;
-  int gab, bab; size_t sab;
+  // bound kAnaThreads); large items [ga, ga + gab) with bab threads,
+  // E = kBigAnaE (bound kAnaBigThreads). Small items read the twiddle pyramid
+  // from global memory (cached): an LDS copy per block would cost residency,
+  // which measured slower; large items stage it in LDS where that costs no
+  // residency (tab, tsb).
+  int ga, ba; size_t sa;
+  int gab, bab; size_t sab; bool tab;
   // band synthesis: small items [0, gs), bs threads, E = kSmallE (bound
-  // kSynThreads), twiddles in LDS if ts; large items [gs, gs + gsb), bsb
-  // threads, E = kBigSynE (bound kSynBigThreads)
-  int gs, bs; size_t ss; bool ts;
+  // kSynThreads); large items [gs, gs + gsb), bsb threads, E = kBigSynE
+  // (bound kSynBigThreads)
+  int gs, bs; size_t ss;
   int gsb, bsb; size_t ssb; bool tsb;
   bool ok;                    // every block fits its kernel's launch bound
 };
+
+// An LDS copy of the twiddles (tw bytes) for blocks of lds bytes only where it
+// costs no resident block per CU (measured: the copy does not pay for lost
+// residency).
+inline bool lds_twiddles_pay(size_t lds, size_t tw) {
+  return lds + tw <= kMaxLdsBytes && kMaxLdsBytes / (lds + tw) >= kMaxLdsBytes / std::max<size_t>(lds, 1);
+}
 
 template <class T>
 Geometry<T> geometry(const Plan& p) {
@@ -134,22 +144,22 @@ Geometry<T> geometry(const Plan& p) {
   g.ga = p.ana_small;
   g.ba = threads_for(std::max(p.ana_cap_small, 1), kSmallE);
   g.sa = lds_tail_offset<T>(p.ana_cap_small);
-  g.ta = g.sa + (size_t)p.ana_maxM_small * cb <= kMaxLdsBytes;
-  if (g.ta) g.sa += (size_t)p.ana_maxM_small * cb;
   g.gab = (int)p.ana.size() - p.ana_small;
   g.bab = threads_for(std::max(p.ana_cap_big, 1), kBigAnaE);
   g.sab = lds_tail_offset<T>(p.ana_cap_big);
+  int32_t big_ana_M = 0;
+  for (int i = p.ana_small; i < (int)p.ana.size(); ++i) big_ana_M = std::max(big_ana_M, p.ana[i].M);
+  g.tab = lds_twiddles_pay(g.sab, (size_t)big_ana_M * cb);
+  if (g.tab) g.sab += (size_t)big_ana_M * cb;
   g.gs = p.syn_small;
   g.bs = threads_for(std::max(p.syn_cap_small, 1), kSmallE);
   g.ss = lds_tail_offset<T>(p.syn_cap_small);
-  g.ts = g.ss + (size_t)p.syn_maxM_small * cb <= kMaxLdsBytes;
-  if (g.ts) g.ss += (size_t)p.syn_maxM_small * cb;
   g.gsb = (int)p.syn.size() - p.syn_small;
   g.bsb = threads_for(std::max(p.syn_cap_big, 1), kBigSynE);
   g.ssb = lds_tail_offset<T>(p.syn_cap_big);
   int32_t big_maxM = 0;
   for (int i = p.syn_small; i < (int)p.syn.size(); ++i) big_maxM = std::max(big_maxM, p.syn[i].maxM);
-  g.tsb = g.ssb + (size_t)big_maxM * cb <= kMaxLdsBytes;     // one block per CU anyway: LDS is free
+  g.tsb = lds_twiddles_pay(g.ssb, (size_t)big_maxM * cb);
   if (g.tsb) g.ssb += (size_t)big_maxM * cb;
   size_t lds = std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss));
   if (g.gab) lds = std::max(lds, g.sab);
@@ -168,22 +178,18 @@ Geometry<T> geometry(const Plan& p) {
 template <class T, class Launch>
 void launch_band_ana(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
                      const C2<T>* W2, C2<T>* coef, Launch& L) {
-  if (g.ga) {
-    if (g.ta) L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, true>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0, g.ga);
-    else L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, false>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0, g.ga);
+  if (g.ga) L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, false>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0, g.ga);
+  if (g.gab) {
+    if (g.tab) L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, true>, cnt * g.gab, g.bab, g.sab, a, tasks, W2, coef, g.ga, g.gab);
+    else L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, false>, cnt * g.gab, g.bab, g.sab, a, tasks, W2, coef, g.ga, g.gab);
   }
-  if (g.gab)
-    L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, false>, cnt * g.gab, g.bab, g.sab, a, tasks, W2, coef, g.ga, g.gab);
 }
 
 // Band synthesis (dual or adjoint) of cnt tasks: one launch per work-item class.
 template <class T, class Launch>
 void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
                      const C2<T>* coef, C2<T>* W2, T* y, Launch& L) {
-  if (g.gs) {
-    if (g.ts) L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, true>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
-    else L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
-  }
+  if (g.gs) L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
   if (g.gsb) {
     if (g.tsb) L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, true>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
     else L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
