@@ -48,7 +48,12 @@ constexpr int kSynBigThreads = 1024;                     // k_band_syn, large it
 static_assert(kAnaBigThreads * kBigAnaE >= 8192 && kSynBigThreads * kBigSynE >= kSynMaxValues,
               "large work items must fit one block");
 constexpr int kPassE = 8;             // values per thread in the slice-FFT passes
-constexpr int kPassWaves = 4;         // their waves per SIMD (at least)
+// Waves per SIMD the slice-FFT passes are compiled for: the row passes fit
+// 64 VGPRs in FP32 (4 blocks of 512 per CU); the column passes hold their
+// prefetched per-output data across the transform and would spill there.
+template <class T>
+constexpr int kRowPassWaves = sizeof(T) == 4 ? 8 : 4;
+constexpr int kColPassWaves = 4;
 // Largest padded length and coefficient count of one signal: offsets inside a
 // signal are 32-bit.
 constexpr int64_t kMaxSignalElems = 0x7fffffffLL;
@@ -181,7 +186,7 @@ __device__ __forceinline__ void fwd_pass1_body(const KArgs<T>& a, const SliceTas
 
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
-__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kColPassWaves)))
 k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict__ x, C2<T>* __restrict__ W1) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -272,7 +277,7 @@ __device__ __forceinline__ void fwd_pass2_fft(int logTwoP, C2<T>* buf, const TW&
 
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
-__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kRowPassWaves<T>)))
 k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -704,7 +709,7 @@ __device__ __forceinline__ void inv_passA_fft(const KArgs<T>& a, int rb, int log
 
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
-__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kRowPassWaves<T>)))
 k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -802,7 +807,7 @@ __device__ __forceinline__ void inv_passB_body(const KArgs<T>& a, const SliceTas
 
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
-__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kColPassWaves)))
 k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W1, T* __restrict__ y) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
