@@ -51,8 +51,7 @@ constexpr int kPassE = 8;             // values per thread in the slice-FFT pass
 // Waves per SIMD the slice-FFT passes are compiled for: the row passes fit
 // 64 VGPRs in FP32 (4 blocks of 512 per CU); the column passes hold their
 // prefetched per-output data across the transform and would spill there.
-template <class T>
-constexpr int kRowPassWaves = sizeof(T) == 4 ? 8 : 4;
+constexpr int kRowPassWavesF32 = 8;
 constexpr int kColPassWaves = 4;
 // Largest padded length and coefficient count of one signal: offsets inside a
 // signal are 32-bit.
@@ -277,7 +276,7 @@ __device__ __forceinline__ void fwd_pass2_fft(int logTwoP, C2<T>* buf, const TW&
 
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
-__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kRowPassWaves<T>)))
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? kRowPassWavesF32 : 4)))
 k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -709,7 +708,7 @@ __device__ __forceinline__ void inv_passA_fft(const KArgs<T>& a, int rb, int log
 
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
 template <class T, bool TWL>
-__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kRowPassWaves<T>)))
+__global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? kRowPassWavesF32 : 4)))
 k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);

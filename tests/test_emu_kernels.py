@@ -92,3 +92,17 @@ def test_emu_streaming_server():
     alone, _ = H.stream(kw, sig, hop=32, dtype=1, mode=2, max_streams=4, max_batch=6)
     assert np.array_equal(alone[0], ys[1])
     assert stats[0] == 4 and stats[1] == 0 and stats[2] > 0      # 3 streams + the snapshot replay
+
+
+@pytest.mark.parametrize("opts", [dict(group_cap=64, lds_cap=512, pass_cap=256),
+                                  dict(group_cap=4096, lds_cap=16384, pass_cap=1024)], ids=["small", "large"])
+def test_emu_tuning_options(opts):
+    # other work-item decompositions of the c4 shape (FP32): many small items and
+    # lone large synthesis items; the largest items and wide slice-pass items
+    kw = C4
+    pl = OraclePlan(**kw)
+    T = 9000
+    x = np.random.default_rng(8).standard_normal(T)
+    ref = pack(pl, analyze(pl, x))
+    assert rel(H.analyze(kw, x, 0, **opts), ref) <= 1e-5
+    assert rel(H.synthesize(kw, ref, T, 0, **opts), x) <= 1e-5

@@ -94,6 +94,41 @@ def test_preset_shapes_f32(sq, dev, name, T):
     check_roundtrip(sq, dev, preset(name), x, "f32", check_adjoint=(name == "c4"))
 
 
+OPTION_SETS = [
+    dict(group_cap=64, lds_cap=512, pass_cap=256),        # many small items; large synthesis items alone
+    dict(group_cap=4096, lds_cap=16384, pass_cap=1024),   # the largest items; wide slice-pass items
+    dict(group_cap=512, lds_cap=2048, pass_cap=4096, layout="slice"),
+]
+
+
+@pytest.mark.parametrize("opts", OPTION_SETS, ids=["small", "large", "slice-major"])
+@pytest.mark.parametrize("name,T,dt", [("c4", 100000, "f32"), ("c5", 60000, "f32"), ("c1", 70000, "f64")])
+def test_tuning_options(sq, dev, opts, name, T, dt):
+    # every work-item decomposition gives the oracle's coefficients (in its layout),
+    # reconstruction and adjoint
+    import torch
+    kw = preset(name)
+    _, opl = gpu_plan(sq, kw)
+    plan = sq.Plan(**kw, **opts)
+    print(f"case {name} T={T} {dt} {opts}", flush=True)
+    x = pink_plus_tones(T, kw["fs"], 91)
+    c_ref = analyze(opl, x)
+    S = num_slices(T, opl.two_n)
+    slice_major = opts.get("layout") == "slice"
+    ref = (np.concatenate([np.concatenate([ck[m] for ck in c_ref]) for m in range(S)]) if slice_major
+           else pack(opl, c_ref))
+    xd = torch.tensor(x, dtype=torch_dtype(dt), device=dev)
+    c = plan.analyze(xd)
+    y = plan.synthesize(c, T)
+    assert rel(c.cpu().numpy(), ref) <= TOL[dt]
+    assert rel(y.cpu().numpy(), x) <= TOL[dt]
+    if not slice_major:
+        g = np.random.default_rng(5)
+        cr = g.standard_normal(len(ref)) + 1j * g.standard_normal(len(ref))
+        crd = torch.tensor(cr, dtype=torch.complex64 if dt == "f32" else torch.complex128, device=dev)
+        assert rel(plan.adjoint(crd, T).cpu().numpy(), adjoint(opl, unpack(opl, cr, S), T)) <= TOL[dt]
+
+
 def test_c2_full_stereo_f32(sq, dev):
     # the benchmarked workload at its full size: 60 s stereo, batched launch
     import torch
