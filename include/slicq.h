@@ -240,10 +240,20 @@ int slicq_stream_open(slicq_stream_server server, int32_t* id);
 /* Appends n samples; push_gap appends n zeros for a hop that never arrived. */
 int slicq_stream_push(slicq_stream_server server, int32_t id, const void* samples, int64_t n);
 int slicq_stream_push_gap(slicq_stream_server server, int32_t id, int64_t n);
+/* A whole round of hops in one call: stream ids[i] receives counts[i]
+ * samples, taken in order from the packed `samples`. Every id and count is
+ * checked before any sample is appended. */
+int slicq_stream_push_many(slicq_stream_server server, int32_t n_ids, const int32_t* ids, const void* samples,
+                           const int64_t* counts);
 /* One batch over all streams; *n_slices receives the slices processed. */
 int slicq_stream_tick(slicq_stream_server server, int64_t* n_slices);
 /* Moves up to max final output samples of stream id into out; *n receives the count. */
 int slicq_stream_poll(slicq_stream_server server, int32_t id, void* out, int64_t max, int64_t* n);
+/* The final output of streams ids[i], packed in order into out (host memory
+ * of cap samples); counts[i] receives each stream's count. Streams past the
+ * capacity get what still fits (possibly 0) and keep the rest. */
+int slicq_stream_poll_many(slicq_stream_server server, int32_t n_ids, const int32_t* ids, void* out, int64_t cap,
+                           int64_t* counts);
 /* Ends a stream (also mid-slice); its slot is cleared before reuse. */
 int slicq_stream_close(slicq_stream_server server, int32_t id);
 /* Coefficients of stream id's most recent slice (slice-major c^m: band k at

@@ -103,6 +103,8 @@ def load_library():
         "slicq_stream_open": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
         "slicq_stream_push": (ctypes.c_int, [P, I32, P, I64]),
         "slicq_stream_push_gap": (ctypes.c_int, [P, I32, I64]),
+        "slicq_stream_push_many": (ctypes.c_int, [P, I32, P, P, P]),
+        "slicq_stream_poll_many": (ctypes.c_int, [P, I32, P, P, I64, P]),
         "slicq_stream_tick": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "slicq_stream_poll": (ctypes.c_int, [P, I32, P, I64, ctypes.POINTER(I64)]),
         "slicq_stream_close": (ctypes.c_int, [P, I32]),
@@ -507,6 +509,31 @@ class StreamServer:
     def push(self, sid: int, samples) -> None:
         a = np.ascontiguousarray(samples, dtype=self.np_dtype)
         _check(self._lib.slicq_stream_push(self._h, int(sid), a.ctypes.data, a.size))
+
+    def push_many(self, ids, hops) -> None:
+        """One hop (array) per stream id, in one call."""
+        counts = np.array([len(h) for h in hops], dtype=np.int64)
+        self.push_packed(ids, np.concatenate(hops) if len(hops) else np.zeros(0), counts)
+
+    def push_packed(self, ids, packed, counts) -> None:
+        """Hops packed back to back (counts[i] samples for ids[i]), in one call."""
+        ids_a = np.ascontiguousarray(ids, dtype=np.int32)
+        counts = np.ascontiguousarray(counts, dtype=np.int64)
+        if ids_a.size != counts.size or int(counts.sum()) > np.size(packed):
+            raise SlicqError("push_packed: ids, counts and samples do not match")
+        packed = np.ascontiguousarray(packed, dtype=self.np_dtype)
+        _check(self._lib.slicq_stream_push_many(self._h, ids_a.size, ids_a.ctypes.data, packed.ctypes.data,
+                                                counts.ctypes.data))
+
+    def poll_many(self, ids, cap: int = 1 << 22):
+        """Final output of each stream id (a list of arrays, at most cap samples in all)."""
+        ids_a = np.ascontiguousarray(ids, dtype=np.int32)
+        counts = np.zeros(ids_a.size, dtype=np.int64)
+        out = np.empty(int(cap), dtype=self.np_dtype)
+        _check(self._lib.slicq_stream_poll_many(self._h, ids_a.size, ids_a.ctypes.data, out.ctypes.data, out.size,
+                                                counts.ctypes.data))
+        ends = np.cumsum(counts)
+        return [out[e - c:e] for e, c in zip(ends, counts)]
 
     def push_gap(self, sid: int, n: int) -> None:
         _check(self._lib.slicq_stream_push_gap(self._h, int(sid), int(n)))

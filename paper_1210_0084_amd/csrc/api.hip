@@ -311,6 +311,27 @@ int slicq_stream_push(slicq_stream_server s, int32_t id, const void* samples, in
   });
 }
 
+int slicq_stream_push_many(slicq_stream_server s, int32_t n_ids, const int32_t* ids, const void* samples,
+                           const int64_t* counts) {
+  return with_server(s, [&](auto& srv) -> int {
+    using T = std::remove_pointer_t<decltype(srv.ring_type())>;
+    if (n_ids < 0 || (n_ids > 0 && (!ids || !counts))) return fail(SLICQ_EINVAL, "bad id list");
+    int64_t total = 0;
+    for (int32_t i = 0; i < n_ids; ++i) {
+      if (!srv.valid(ids[i])) return fail(SLICQ_ESTATE, "stream is not open");
+      if (counts[i] < 0) return fail(SLICQ_EINVAL, "bad count");
+      total += counts[i];
+    }
+    if (total > 0 && !samples) return fail(SLICQ_EINVAL, "bad samples");
+    const T* x = static_cast<const T*>(samples);
+    for (int32_t i = 0; i < n_ids; ++i) {
+      srv.push(ids[i], x, counts[i]);
+      x += counts[i];
+    }
+    return SLICQ_OK;
+  });
+}
+
 int slicq_stream_push_gap(slicq_stream_server s, int32_t id, int64_t n) {
   return with_server(s, [&](auto& srv) -> int {
     if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
@@ -334,6 +355,26 @@ int slicq_stream_poll(slicq_stream_server s, int32_t id, void* out, int64_t max,
     if (!srv.valid(id)) return fail(SLICQ_ESTATE, "stream is not open");
     if (!n || max < 0 || (max > 0 && !out)) return fail(SLICQ_EINVAL, "bad output buffer");
     *n = srv.poll(id, static_cast<T*>(out), max);
+    return SLICQ_OK;
+  });
+}
+
+int slicq_stream_poll_many(slicq_stream_server s, int32_t n_ids, const int32_t* ids, void* out, int64_t cap,
+                           int64_t* counts) {
+  return with_server(s, [&](auto& srv) -> int {
+    using T = std::remove_pointer_t<decltype(srv.ring_type())>;
+    if (n_ids < 0 || (n_ids > 0 && (!ids || !counts))) return fail(SLICQ_EINVAL, "bad id list");
+    if (cap < 0 || (cap > 0 && !out)) return fail(SLICQ_EINVAL, "bad output buffer");
+    for (int32_t i = 0; i < n_ids; ++i)
+      if (!srv.valid(ids[i])) return fail(SLICQ_ESTATE, "stream is not open");
+    T* y = static_cast<T*>(out);
+    int64_t left = cap;
+    for (int32_t i = 0; i < n_ids; ++i) {
+      const int64_t got = left > 0 ? srv.poll(ids[i], y, left) : 0;
+      counts[i] = got;
+      y += got;
+      left -= got;
+    }
     return SLICQ_OK;
   });
 }

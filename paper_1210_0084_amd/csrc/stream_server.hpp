@@ -41,6 +41,40 @@ struct StreamStats {
   double busy_seconds = 0;                                    // host time inside ticks
 };
 
+// FIFO of samples in one contiguous vector with a read offset (bulk append
+// and bulk read with memcpy; the consumed front is dropped once it is the
+// larger half).
+template <class T>
+class SampleFifo {
+ public:
+  int64_t size() const { return (int64_t)(buf_.size() - head_); }
+  const T* data() const { return buf_.data() + head_; }
+  void append(const T* x, int64_t n) {
+    if (n > 0) buf_.insert(buf_.end(), x, x + n);
+  }
+  // Moves the first n (<= size()) samples to y.
+  void read(T* y, int64_t n) {
+    if (n <= 0) return;
+    std::memcpy(y, buf_.data() + head_, (size_t)n * sizeof(T));
+    head_ += (size_t)n;
+    if (head_ == buf_.size()) {
+      buf_.clear();
+      head_ = 0;
+    } else if (head_ >= 4096 && 2 * head_ >= buf_.size()) {
+      buf_.erase(buf_.begin(), buf_.begin() + (std::ptrdiff_t)head_);
+      head_ = 0;
+    }
+  }
+  void assign(const T* x, int64_t n) {
+    buf_.assign(x, x + n);
+    head_ = 0;
+  }
+
+ private:
+  std::vector<T> buf_;
+  size_t head_ = 0;
+};
+
 template <class T, class Backend>
 class StreamServer {
  public:
@@ -50,8 +84,8 @@ class StreamServer {
     int64_t on_device = 0;     // samples moved into the device input ring
     int64_t next_slice = 0;    // m of the next slice to process
     int64_t released = 0;      // output samples moved to `out`
-    std::deque<T> pending;     // pushed, not yet on the device
-    std::deque<T> out;         // final output samples, not yet polled
+    SampleFifo<T> pending;     // pushed, not yet on the device
+    SampleFifo<T> out;         // final output samples, not yet polled
     std::deque<std::pair<int64_t, double>> arrivals;   // (pushed after a push, time)
     int64_t last_m = -1;       // most recent processed slice
     int64_t last_task = -1;    // its index in the last tick's coefficient buffer
@@ -139,7 +173,7 @@ class StreamServer {
     const double t = now();
     std::lock_guard<std::mutex> lk(mu_);
     Stream& s = streams_[id];
-    s.pending.insert(s.pending.end(), x, x + n);
+    s.pending.append(x, n);
     s.pushed += n;
     s.arrivals.emplace_back(s.pushed, t);
     st_.samples_in += n;
@@ -157,9 +191,8 @@ class StreamServer {
   int64_t poll(int id, T* y, int64_t max) {
     std::lock_guard<std::mutex> lk(mu_);
     Stream& s = streams_[id];
-    const int64_t n = std::min<int64_t>(max, (int64_t)s.out.size());
-    for (int64_t i = 0; i < n; ++i) y[i] = s.out[i];
-    s.out.erase(s.out.begin(), s.out.begin() + n);
+    const int64_t n = std::min<int64_t>(max, s.out.size());
+    s.out.read(y, n);
     return n;
   }
 
@@ -189,10 +222,9 @@ class StreamServer {
         if (!s.active) continue;
         // input ring holds samples [(next_slice - 1) N, (next_slice - 1) N + R)
         const int64_t limit = (s.next_slice - 1) * N_ + R_;
-        const int64_t n = std::min<int64_t>((int64_t)s.pending.size(), limit - s.on_device);
+        const int64_t n = std::min<int64_t>(s.pending.size(), limit - s.on_device);
         if (n > 0 && staged + n <= staging_cap_) {
-          for (int64_t i = 0; i < n; ++i) stage_h_[staged + i] = s.pending[i];
-          s.pending.erase(s.pending.begin(), s.pending.begin() + n);
+          s.pending.read(stage_h_ + staged, n);
           in_copies.push_back({id, (int32_t)n, s.on_device & (R_ - 1), staged});
           staged += n;
           s.on_device += n;
@@ -284,7 +316,7 @@ class StreamServer {
       for (const RingCopy& c : out_copies) {
         Stream& s = streams_[c.slot];
         if (!s.active) continue;
-        s.out.insert(s.out.end(), stage_h_ + c.off, stage_h_ + c.off + c.count);
+        s.out.append(stage_h_ + c.off, c.count);
         s.released += c.count;
         st_.samples_out += c.count;
       }
@@ -339,8 +371,8 @@ class StreamServer {
     be_.d2h(yr.data(), yring_ + (int64_t)id * R_, R_ * sizeof(T));
     if (!be_.sync()) return false;
     int64_t hdr[8] = {0x51494c53, R_, (int64_t)sizeof(T), s.pushed, s.on_device, s.next_slice, s.released,
-                      (int64_t)s.pending.size()};
-    const int64_t nout = (int64_t)s.out.size();
+                      s.pending.size()};
+    const int64_t nout = s.out.size();
     blob.clear();
     auto put = [&](const void* p, size_t n) {
       if (n == 0) return;
@@ -352,9 +384,8 @@ class StreamServer {
     put(&nout, sizeof nout);
     put(xr.data(), R_ * sizeof(T));
     put(yr.data(), R_ * sizeof(T));
-    std::vector<T> q(s.pending.begin(), s.pending.end()), o(s.out.begin(), s.out.end());
-    put(q.data(), q.size() * sizeof(T));
-    put(o.data(), o.size() * sizeof(T));
+    put(s.pending.data(), (size_t)s.pending.size() * sizeof(T));
+    put(s.out.data(), (size_t)nout * sizeof(T));
     return true;
   }
 
@@ -385,8 +416,8 @@ class StreamServer {
     s.next_slice = hdr[5];
     s.released = hdr[6];
     const T* q = reinterpret_cast<const T*>(p);
-    s.pending.assign(q, q + hdr[7]);
-    s.out.assign(q + hdr[7], q + hdr[7] + nout);
+    s.pending.assign(q, hdr[7]);
+    s.out.assign(q + hdr[7], nout);
     s.arrivals.emplace_back(s.pushed, now());
     return true;
   }

@@ -159,3 +159,39 @@ def test_gap_and_close_midstream(sq, plan):
     z = pink_plus_tones(50000, 48000.0, 5_000_301)
     outs, _ = feed(srv, [b], [z])
     assert rel(outs[b], z) <= 1e-5
+
+
+def test_push_many_and_poll_many_match_single_calls(sq, plan):
+    # a whole round of hops in one call gives the same output as one call per stream
+    sigs = [pink_plus_tones(60000 + 1000 * i, 48000.0, 5_000_400 + i) for i in range(5)]
+    one = sq.StreamServer(plan, "f32", max_streams=8, max_batch=64)
+    ids1 = [one.open() for _ in sigs]
+    ref, _ = feed(one, ids1, sigs)
+    many = sq.StreamServer(plan, "f32", max_streams=8, max_batch=64)
+    ids = [many.open() for _ in sigs]
+    flush = plan.N + plan.transition
+    total = [len(s) + flush for s in sigs]
+    fed = [0] * len(sigs)
+    outs = [[] for _ in sigs]
+    while any(f < t for f, t in zip(fed, total)):
+        live, hops = [], []
+        for i, s in enumerate(sigs):
+            if fed[i] >= total[i]:
+                continue
+            n = min(HOP, total[i] - fed[i])
+            h = np.zeros(n)
+            lo, hi = fed[i], min(fed[i] + n, len(s))
+            if hi > lo:
+                h[:hi - lo] = s[lo:hi]
+            live.append(ids[i])
+            hops.append(h)
+            fed[i] += n
+        many.push_many(live, hops)
+        many.tick()
+        for i, y in zip(range(len(sigs)), many.poll_many(ids)):
+            outs[i].append(y.copy())
+    for i, s in enumerate(sigs):
+        y = np.concatenate(outs[i])[:len(s)]
+        assert np.array_equal(y, ref[ids1[i]])
+    with pytest.raises(sq.SlicqError):
+        many.push_many([ids[0], 99], [np.zeros(4), np.zeros(4)])   # 99 is not open: nothing is appended
