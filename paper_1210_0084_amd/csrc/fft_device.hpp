@@ -134,6 +134,23 @@ struct TwLds {
   __device__ __forceinline__ C2<T> get(int n, int k) const { return tw[(n >> 1) - 1 + k]; }
 };
 
+// Four-step twiddles e^{DIR 2 pi i m / N}, 0 <= m < N = N1 N2, as the product
+// of e^{-2 pi i (m >> log N2) / N1} (hi, N1 entries) and e^{-2 pi i (m mod N2) / N}
+// (lo, N2 entries), both staged in LDS: two small tables instead of gathers
+// from the N-entry level of the pyramid (error within one more rounding).
+template <class T>
+struct InterTw {
+  const C2<T>* hi;
+  const C2<T>* lo;
+  int logN2;
+  template <int DIR>
+  __device__ __forceinline__ C2<T> get(int m) const {
+    C2<T> w = cmul(hi[m >> logN2], lo[m & ((1 << logN2) - 1)]);
+    if constexpr (DIR > 0) w.y = -w.y;
+    return w;
+  }
+};
+
 // Entry i of the TwLds table for levels up to n_max: level n = 2^(floor(log2(i + 1)) + 1),
 // k = i + 1 - n/2, read from the pyramid.
 template <class T>
@@ -434,7 +451,8 @@ __device__ __forceinline__ void ci_unit(int u, int lognseq, int logj, int& s, in
 // so a caller can fetch per-output data before the transform. JF orders the
 // fused passes' units unit-fastest (coalesced when a sequence is contiguous
 // in global memory). The caller synchronises after an unfused last pass; a
-// fused first pass needs no synchronisation before it.
+// fused first pass needs no synchronisation before it; LDS the block wrote
+// before the call is visible to store (there is a barrier before it).
 template <class T, int DIR, int E, int LOGN, bool FIRST, bool LASTF, bool JF, class TW, class LD, class ST>
 __device__ __forceinline__ void fft_ci_fused(C2<T>* buf, int lognseq, const TW& tw, int tid, int nthr, LD load,
                                              ST store) {
@@ -453,6 +471,7 @@ __device__ __forceinline__ void fft_ci_fused(C2<T>* buf, int lognseq, const TW& 
 #pragma unroll
     for (int i = 0; i < U1; ++i) dft_reg<T, R1, DIR>(v[i]);
     if constexpr (LASTF && LAST == 0) {
+      __syncthreads();                  // a store may read LDS tables the block staged before the call
 #pragma unroll
       for (int i = 0; i < U1; ++i) {
         const int u = tid + i * nthr;

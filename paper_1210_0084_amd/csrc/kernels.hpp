@@ -151,24 +151,13 @@ __device__ __forceinline__ C2<T> load_sample_pair(const T* __restrict__ xs, cons
 // it sits in a batch).
 template <class T, int LOGN, class TW>
 __device__ __forceinline__ void fwd_pass1_body(const KArgs<T>& a, const SliceTask& tk, int cb, C2<T>* buf,
-                                               const TW& tws, const T* __restrict__ x, C2<T>* __restrict__ out,
-                                               bool plain, int tid, int nthr) {
-  constexpr int LAST = last_pass_logns(LOGN, 8), RL = 1 << (LOGN - LAST), UL = kPassE / RL, NS = 1 << LAST;
+                                               const TW& tws, const InterTw<T>& inter, const T* __restrict__ x,
+                                               C2<T>* __restrict__ out, bool plain, int tid, int nthr) {
   const int jlo = ((a.N - a.Mt) / 2) & ~1;           // first sample pair touching the support of h_0
   const int jhi = (a.N + (a.N + a.Mt) / 2 - 1) & ~1;  // last one
   const T* __restrict__ xs = x + tk.x_base;
   const SliceIn si = slice_in(tk);
-  const int c0 = cb * a.C, smask = a.C - 1;
-  // inter-step twiddles of this thread's outputs, fetched before the transform
-  C2<T> w[UL][RL];
-  const int unitsL = 1 << (a.logC + LAST);
-#pragma unroll
-  for (int i = 0; i < UL; ++i) {
-    const int u = imin(tid + i * nthr, unitsL - 1);
-    const int n1 = c0 + (u & smask), j = u >> a.logC;
-#pragma unroll
-    for (int r = 0; r < RL; ++r) w[i][r] = twiddle<T, -1>(a.tw, a.N, (n1 * (j + r * NS)) & (a.N - 1));
-  }
+  const int c0 = cb * a.C;
   auto load = [&](int s, int e) -> C2<T> {
     const int j = 2 * (c0 + s + a.N1 * e);
     const int jc = imin(imax(j, jlo), jhi);
@@ -179,11 +168,14 @@ __device__ __forceinline__ void fwd_pass1_body(const KArgs<T>& a, const SliceTas
     // rounded by itself: the same value whichever load path (and code) fed it
     return {mul_rn(x2.x, h2.x), mul_rn(x2.y, h2.y)};
   };
-  auto store = [&](int i, int r, int s, int e, C2<T> v) { out[e * a.N1 + c0 + s] = cmul(v, w[i][r]); };
+  auto store = [&](int, int, int s, int e, C2<T> v) {
+    out[e * a.N1 + c0 + s] = cmul(v, inter.template get<-1>(((c0 + s) * e) & (a.N - 1)));
+  };
   fft_ci_fused<T, -1, kPassE, LOGN, true, true, false>(buf, a.logC, tws, tid, nthr, load, store);
 }
 
-// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
+// TWL stages the FFT twiddles in LDS. LDS: values (padded) | FFT twiddles (N2)
+// | four-step tables (N1 + N2).
 template <class T, bool TWL>
 __global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kColPassWaves)))
 k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict__ x, C2<T>* __restrict__ W1) {
@@ -195,15 +187,17 @@ k_fwd_pass1(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict
   if (tk.S == 0) return;                              // unused task slot
   const int tid = threadIdx.x, nthr = blockDim.x;
   C2<T>* twl = buf + padded(a.C * a.N2);
+  const InterTw<T> inter{twl + a.N2, twl + a.N2 + a.N1, a.logN2};
+  stage_inter(twl + a.N2, twl + a.N2 + a.N1, a.tw, a.N, a.N1, a.N2, tid, nthr);
   if constexpr (TWL) stage_twiddles(twl, a.tw, a.N2, tid, nthr);
   const SliceIn si = slice_in(tk);
   const bool plain = si.even && si.start >= 0 && si.start + 2 * a.N <= imin(si.valid, si.period);
   C2<T>* out = W1 + (int64_t)task * a.ws1;
   const TwLds<T> tl{twl};
   const TwGlobal<T> tg{a.tw};
-#define SLICQ_P1(L)                                                                      \
-  if constexpr (TWL) fwd_pass1_body<T, L>(a, tk, cb, buf, tl, x, out, plain, tid, nthr);  \
-  else fwd_pass1_body<T, L>(a, tk, cb, buf, tg, x, out, plain, tid, nthr);
+#define SLICQ_P1(L)                                                                             \
+  if constexpr (TWL) fwd_pass1_body<T, L>(a, tk, cb, buf, tl, inter, x, out, plain, tid, nthr);  \
+  else fwd_pass1_body<T, L>(a, tk, cb, buf, tg, inter, x, out, plain, tid, nthr);
   SLICQ_LOGN_SWITCH(a.logN2, SLICQ_P1)
 #undef SLICQ_P1
 }
@@ -345,6 +339,27 @@ __device__ __forceinline__ void stage_twiddles(C2<T>* twl, const C2<T>* __restri
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       if (b + q * nthr < n - 1) twl[b + q * nthr] = v[q];
+  }
+}
+
+// Stages the four-step twiddle tables of InterTw: hi[q] = e^{-2 pi i q / N1}
+// (level N1 of the pyramid) and lo[r] = e^{-2 pi i r / N} for r < N2.
+template <class T>
+__device__ __forceinline__ void stage_inter(C2<T>* hi, C2<T>* lo, const C2<T>* __restrict__ tw, int N, int N1,
+                                            int N2, int tid, int nthr) {
+  for (int b = tid; b < N1 + N2; b += 8 * nthr) {
+    C2<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = imin(b + q * nthr, N1 + N2 - 1);
+      v[q] = i < N1 ? tw[N1 + i] : tw[N + i - N1];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = b + q * nthr;
+      if (i < N1) hi[i] = v[q];
+      else if (i < N1 + N2) lo[i - N1] = v[q];
+    }
   }
 }
 
@@ -687,26 +702,17 @@ __device__ __forceinline__ void herm_pack(C2<T> a, C2<T> b, C2<T> u, C2<T>& zk, 
 // LDS; the last FFT pass applies e^{+2 pi i n1 k2 / N} and stores W1.
 template <class T, int LOGN, class TW>
 __device__ __forceinline__ void inv_passA_fft(const KArgs<T>& a, int rb, int logTwoP, C2<T>* buf, const TW& tws,
-                                              C2<T>* __restrict__ out, int tid, int nthr) {
-  constexpr int LAST = last_pass_logns(LOGN, 8), RL = 1 << (LOGN - LAST), UL = kPassE / RL, NS = 1 << LAST;
-  const int unitsL = 1 << (logTwoP + LAST);
-  C2<T> tw[UL][RL];
-#pragma unroll
-  for (int i = 0; i < UL; ++i) {
-    int s, j;
-    ci_unit<true>(imin(tid + i * nthr, unitsL - 1), logTwoP, LAST, s, j);
-    const int row = pass2_row(rb, s, a.P, a.N2);
-#pragma unroll
-    for (int r = 0; r < RL; ++r) tw[i][r] = twiddle<T, 1>(a.tw, a.N, ((j + r * NS) * row) & (a.N - 1));
-  }
+                                              const InterTw<T>& inter, C2<T>* __restrict__ out, int tid, int nthr) {
   auto none = [](int, int) { return C2<T>{T(0), T(0)}; };
-  auto store = [&](int i, int r, int s, int e, C2<T> v) {
-    out[pass2_row(rb, s, a.P, a.N2) * a.N1 + e] = cmul(v, tw[i][r]);
+  auto store = [&](int, int, int s, int e, C2<T> v) {
+    const int row = pass2_row(rb, s, a.P, a.N2);
+    out[row * a.N1 + e] = cmul(v, inter.template get<1>((e * row) & (a.N - 1)));
   };
   fft_ci_fused<T, 1, kPassE, LOGN, false, true, true>(buf, logTwoP, tws, tid, nthr, none, store);
 }
 
-// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
+// TWL stages the FFT twiddles in LDS. LDS: values (padded) | FFT twiddles (N1)
+// | four-step tables (N1 + N2).
 template <class T, bool TWL>
 __global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? kRowPassWavesF32 : 4)))
 k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
@@ -719,6 +725,7 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   const int N = a.N, N1 = a.N1, N2 = a.N2;
   const int units = P * N1, total = twoP * N1;
   C2<T>* twl = buf + padded(total);
+  const InterTw<T> inter{twl + N1, twl + 2 * N1, a.logN2};
   const C2<T>* Z = W2 + (int64_t)task * a.ws2;
   constexpr int U = kPassE / 2;
   // every load first: spectrum pairs and their twiddles
@@ -731,6 +738,7 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
     w[i] = twiddle<T, 1>(a.tw, 2 * N, q.k);
   }
   const C2<T> zh = Z[N / 2], wh = twiddle<T, 1>(a.tw, 2 * N, N / 2);
+  stage_inter(twl + N1, twl + 2 * N1, a.tw, N, N1, N2, tid, nthr);
   if constexpr (TWL) stage_twiddles(twl, a.tw, N1, tid, nthr);
 #pragma unroll
   for (int i = 0; i < U; ++i) {
@@ -751,9 +759,9 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
   C2<T>* out = W1 + (int64_t)task * a.ws1;
   const TwLds<T> tl{twl};
   const TwGlobal<T> tg{a.tw};
-#define SLICQ_PA(L)                                                          \
-  if constexpr (TWL) inv_passA_fft<T, L>(a, rb, logTwoP, buf, tl, out, tid, nthr); \
-  else inv_passA_fft<T, L>(a, rb, logTwoP, buf, tg, out, tid, nthr);
+#define SLICQ_PA(L)                                                                 \
+  if constexpr (TWL) inv_passA_fft<T, L>(a, rb, logTwoP, buf, tl, inter, out, tid, nthr); \
+  else inv_passA_fft<T, L>(a, rb, logTwoP, buf, tg, inter, out, tid, nthr);
   SLICQ_LOGN_SWITCH(a.logN1, SLICQ_PA)
 #undef SLICQ_PA
 }

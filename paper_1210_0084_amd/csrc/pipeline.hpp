@@ -137,10 +137,10 @@ Geometry<T> geometry(const Plan& p) {
   const size_t cb = sizeof(C2<T>);
   g.g1 = p.N1 / p.C;
   g.b1 = threads_for((int64_t)p.C * p.N2, kPassE);
-  g.s1 = (padded(p.C * p.N2) + p.N2) * cb;          // values, twiddles up to N2
+  g.s1 = (padded(p.C * p.N2) + p.N2 + p.N1 + p.N2) * cb;   // values, FFT twiddles, four-step tables
   g.g2 = (p.N2 / 2) / p.P;
   g.b2 = threads_for((int64_t)2 * p.P * p.N1, kPassE);
-  g.s2 = (padded(2 * p.P * p.N1) + p.N1) * cb;      // values, twiddles up to N1
+  g.s2 = (padded(2 * p.P * p.N1) + p.N1 + p.N1 + p.N2) * cb;   // values, FFT twiddles, four-step tables
   g.ga = p.ana_small;
   g.ba = threads_for(std::max(p.ana_cap_small, 1), kSmallE);
   g.sa = lds_tail_offset<T>(p.ana_cap_small);
