@@ -274,9 +274,11 @@ int slicq_stream_restore(slicq_stream_server server, int32_t id, const void* buf
  * must hold all n_slices slices at once), so that a profiler can time it
  * alone. Stages: 0 slice FFT pass 1, 1 slice FFT pass 2 and real split,
  * 2 band analysis, 3 band synthesis, 4 inverse FFT pass A, 5 inverse FFT pass B
- * with overlap-add. The stage reads what the preceding call left in the
- * workspace; outputs are overwritten (stage 5 accumulates into the overlap
- * samples of y, which stage 3 zeroes). */
+ * with overlap-add (and the fix-up kernel that adds the second contribution
+ * of every output sample two slices share). The stage reads what the
+ * preceding call left in the workspace; outputs are overwritten (stage 5
+ * rewrites y in full, so it may be repeated; it overwrites the workspace
+ * region that stage 4 reads). */
 int slicq_profile_stage(slicq_plan plan, slicq_dtype dtype, int stage, int64_t n_slices, const void* x,
                         void* coef, void* y, void* work, size_t work_bytes, void* hip_stream);
 /* The same for a prepared batch: re-launches one stage over all of its

@@ -110,7 +110,6 @@ int run_analysis(slicq::Plan& p, int dt, const slicq::SliceTask* tasks, int64_t 
                  void* coef, const slicq::WorkLayout& w, char* work, hipStream_t st) {
   using namespace slicq;
   KArgs<T> a = make_args<T>(p, dt, false);
-  a.zero_ola = 0;
   const Geometry<T> g = geometry<T>(p);
   HipLaunch L{st};
   C2<T>* W1 = reinterpret_cast<C2<T>*>(work + w.w1_off);
@@ -128,20 +127,14 @@ int run_synthesis(slicq::Plan& p, int dt, bool adjoint, const slicq::SliceTask* 
                   const void* coef, void* y, const slicq::WorkLayout& w, char* work, hipStream_t st) {
   using namespace slicq;
   KArgs<T> a = make_args<T>(p, dt, adjoint);
-  const bool chunked = w.chunk < ntasks;
-  a.zero_ola = chunked ? 0 : 1;
   const Geometry<T> g = geometry<T>(p);
   HipLaunch L{st};
-  if (chunked) {
-    const int64_t per = (p.Mt - 1 + 255) / 256;
-    L.launch(k_zero_overlaps<T>, ntasks * per, 256, 0, tasks, ntasks, (int32_t)p.N, (int32_t)p.Mt,
-             static_cast<T*>(y));
-  }
   C2<T>* W1 = reinterpret_cast<C2<T>*>(work + w.w1_off);
   C2<T>* W2 = reinterpret_cast<C2<T>*>(work + w.w2_off);
   for (int64_t t0 = 0; t0 < ntasks; t0 += w.chunk) {
     const int64_t cnt = std::min<int64_t>(w.chunk, ntasks - t0);
-    launch_synthesis<T>(p, a, g, tasks + t0, cnt, static_cast<const C2<T>*>(coef), static_cast<T*>(y), W1, W2, L);
+    launch_synthesis<T>(p, a, g, tasks + t0, t0, cnt, static_cast<const C2<T>*>(coef), static_cast<T*>(y), W1, W2,
+                        L);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SLICQ_OK : hip_fail(e, adjoint ? "adjoint launch" : "synthesis launch");
@@ -729,7 +722,6 @@ static int profile_stage_impl(slicq::Plan& p, slicq_dtype dt, int stage, int64_t
     using T = decltype(tag);
     using namespace slicq;
     KArgs<T> a = make_args<T>(p, dt, false);
-    a.zero_ola = 1;
     const Geometry<T> g = geometry<T>(p);
     C2<T>* W1 = reinterpret_cast<C2<T>*>(wk + w.w1_off);
     C2<T>* W2 = reinterpret_cast<C2<T>*>(wk + w.w2_off);
@@ -744,7 +736,7 @@ static int profile_stage_impl(slicq::Plan& p, slicq_dtype dt, int stage, int64_t
         launch_band_syn(a, g, tasks, n, (const C2<T>*)coef, W2, static_cast<T*>(y), L);
         break;
       case 4: L.launch(k_inv_passA<T, true>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1); break;
-      default: L.launch(k_inv_passB<T, true>, n * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, static_cast<T*>(y)); break;
+      default: launch_inv_passB(a, g, tasks, 0, n, W1, W2, static_cast<T*>(y), L); break;
     }
   };
   if (dt == SLICQ_F32) go(float{});

@@ -15,7 +15,7 @@ struct alignas(16) SliceTask {
   int64_t y_base, y_start, y_period, y_valid;
   int64_t coef_base;
   int32_t m, S;
-  int32_t flags;      // bit 0: zero the right-hand overlap of the output first
+  int32_t flags;      // reserved (set to 1 by the task builders)
   int32_t pad_;
   int64_t pad2_;
 };
@@ -81,13 +81,24 @@ struct alignas(16) RingCopy {
 // position x of the owning work item (and, for the self-mirrored DC and
 // Nyquist bands, adds the conjugate of the one at position y, else y = -1)
 // times a weight: the dual window (synthesis) or the analysis window
-// (adjoint). The first two entries of bin j sit at fixed places, ent2_pos[j]
-// = (x0, y0, x1, y1) and ent2_w*[2j], ent2_w*[2j + 1] (weight 0 and x = 0
-// for a missing entry); any further entries are ent_off[j] .. ent_off[j+1]-1
-// of ent_pos (pairs x, y) and ent_w*.
+// (adjoint). The first two entries of bin j sit in one record, ola_syn[j] or
+// ola_adj[j] (weight 0 and x = 0 for a missing entry); any further entries
+// are ent_off[j] .. ent_off[j+1]-1 of ent_pos (pairs x, y) and ent_w*.
 struct TableLayout {
   uint64_t tw, h0, hd, g, gd, bands, ana, syn, runs;
-  uint64_t ent2_pos, ent2_wsyn, ent2_wadj, ent_off, ent_pos, ent_wsyn, ent_wadj, total;
+  uint64_t ola_syn, ola_adj, ent_off, ent_pos, ent_wsyn, ent_wadj, total;
 };
+
+// The first two overlap-add entries of a bin, read with one load: positions
+// x0 | x1 << 16 (bit 15 set when the bin has further entries), mirror
+// positions y0 | y1 << 16 (0xffff: none), weights w0, w1. Positions are below
+// kSynMaxValues, so 14 bits hold them.
+template <class T>
+struct alignas(16) OlaRec {
+  uint32_t xx, yy;
+  T w0, w1;
+};
+constexpr uint32_t kOlaMore = 0x8000u, kOlaPosMask = 0x3fffu, kOlaNone = 0xffffu;
+static_assert(kSynMaxValues <= 0x4000, "overlap-add positions must fit 14 bits");
 
 }  // namespace slicq

@@ -40,6 +40,7 @@ __device__ __forceinline__ C2<T> mul_mi(C2<T> a) {
 }
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
 // LDS index with one pad slot every 2^kPadShift complex values (bank
@@ -47,6 +48,17 @@ __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 // faster than one per 16).
 constexpr int kPadShift = 4;
 __device__ __forceinline__ int pidx(int i) { return i + (i >> kPadShift); }
+
+// Lanes per wavefront (CDNA): blocks are one-dimensional, so the lanes of a
+// wave are threads (tid & ~(kWave - 1)) .. + kWave - 1.
+constexpr int kWave = 64;
+
+// True for every lane of a wave that holds at least one index below n:
+// lets a whole idle wave branch around work it would only repeat (clamped).
+// The wave base is read from the first lane, so the test is a scalar branch.
+__device__ __forceinline__ bool wave_has(int tid, int n) {
+  return __builtin_amdgcn_readfirstlane(tid & ~(kWave - 1)) < n;
+}
 __host__ __device__ constexpr int padded(int n) { return n + (n >> kPadShift) + 1; }
 
 // e^{DIR 2 pi i k / R} for small constant R, as constants.
@@ -133,6 +145,24 @@ struct TwLds {
   const C2<T>* tw;
   __device__ __forceinline__ C2<T> get(int n, int k) const { return tw[(n >> 1) - 1 + k]; }
 };
+
+// e^{-2 pi i k / n} for n = 2^l <= 2^L from two small LDS tables: with
+// m = k 2^(L - l) = hi 2^(L/2) + lo, the product of e^{-2 pi i hi / 2^(L - L/2)}
+// (t[hi]) and e^{-2 pi i lo / 2^L} (t[2^(L - L/2) + lo]); 2^(L - L/2) + 2^(L/2)
+// entries instead of every level up to 2^L (error within one more rounding).
+template <class T>
+struct TwSplit {
+  const C2<T>* t;
+  int L;
+  __device__ __forceinline__ C2<T> get(int n, int k) const {
+    const int LL = L >> 1;
+    const int m = k << (L - (31 - __builtin_clz((unsigned)n)));
+    return cmul(t[m >> LL], t[(1 << (L - LL)) + (m & ((1 << LL) - 1))]);
+  }
+};
+
+// Entries of the TwSplit tables for transforms up to 2^L.
+__host__ __device__ constexpr int split_tw_entries(int L) { return (1 << (L - (L >> 1))) + (1 << (L >> 1)); }
 
 // Four-step twiddles e^{DIR 2 pi i m / N}, 0 <= m < N = N1 N2, as the product
 // of e^{-2 pi i (m >> log N2) / N1} (hi, N1 entries) and e^{-2 pi i (m mod N2) / N}
@@ -300,7 +330,9 @@ __device__ __forceinline__ int pidx_step(int pb, int p0, int r) {
   else return pidx(p0 + r * S);
 }
 
-template <class T, int DIR, int R, int E, int LOGN, int LOGNS, class TW>
+// SKIP: waves without a unit branch around the reads and the arithmetic (for
+// callers whose batches leave whole waves idle; it costs a few instructions).
+template <class T, int DIR, int R, int E, int LOGN, int LOGNS, class TW, bool SKIP = false>
 __device__ __forceinline__ void stockham_pass_c(C2<T>* buf, int base, int nseq, const TW& tws, int tid, int nthr) {
   constexpr int U = E / R;
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
@@ -309,25 +341,27 @@ __device__ __forceinline__ void stockham_pass_c(C2<T>* buf, int base, int nseq, 
   constexpr int SREAD = 1 << LUNITS;          // read stride of a unit's values
   const int total = nseq << LUNITS;
   C2<T> v[U][R];
+  if (!SKIP || wave_has(tid, total)) {
 #pragma unroll
-  for (int i = 0; i < U; ++i) {
-    const int u = imin(tid + i * nthr, total - 1);
-    const int s = u >> LUNITS, j = u & (SREAD - 1);
-    const int p0 = base + (s << LOGN) + j;
-    const int pb = pidx(p0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[i][r] = buf[pidx_step<SREAD>(pb, p0, r)];
-  }
-#pragma unroll
-  for (int i = 0; i < U; ++i) {
-    if constexpr (NS > 1) {
+    for (int i = 0; i < U; ++i) {
       const int u = imin(tid + i * nthr, total - 1);
-      C2<T> w[R];
-      twiddle_powers<T, DIR, R>(tws, NS * R, u & (NS - 1), w);
+      const int s = u >> LUNITS, j = u & (SREAD - 1);
+      const int p0 = base + (s << LOGN) + j;
+      const int pb = pidx(p0);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
+      for (int r = 0; r < R; ++r) v[i][r] = buf[pidx_step<SREAD>(pb, p0, r)];
     }
-    dft_reg<T, R, DIR>(v[i]);
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      if constexpr (NS > 1) {
+        const int u = imin(tid + i * nthr, total - 1);
+        C2<T> w[R];
+        twiddle_powers<T, DIR, R>(tws, NS * R, u & (NS - 1), w);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
+      }
+      dft_reg<T, R, DIR>(v[i]);
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -359,13 +393,13 @@ __host__ __device__ constexpr int last_pass_logns(int logn, int rmax) {
 
 // Passes of the CONTIG FFT from Ns = 2^LOGNS while Ns < 2^STOP (the whole
 // transform with the defaults).
-template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW, int STOP = LOGN>
+template <class T, int DIR, int E, int RMAX, int LOGN, int LOGNS, class TW, int STOP = LOGN, bool SKIP = false>
 __device__ __forceinline__ void lds_fft_c(C2<T>* buf, int base, int nseq, const TW& tw, int tid, int nthr) {
   if constexpr (LOGNS < LOGN && LOGNS < STOP) {
     constexpr int REM = LOGN - LOGNS;
     constexpr int LR = (RMAX >= 16 && REM >= 4) ? 4 : (RMAX >= 8 && REM >= 3) ? 3 : (RMAX >= 4 && REM >= 2) ? 2 : 1;
-    stockham_pass_c<T, DIR, (1 << LR), E, LOGN, LOGNS, TW>(buf, base, nseq, tw, tid, nthr);
-    lds_fft_c<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW, STOP>(buf, base, nseq, tw, tid, nthr);
+    stockham_pass_c<T, DIR, (1 << LR), E, LOGN, LOGNS, TW, SKIP>(buf, base, nseq, tw, tid, nthr);
+    lds_fft_c<T, DIR, E, RMAX, LOGN, LOGNS + LR, TW, STOP, SKIP>(buf, base, nseq, tw, tid, nthr);
   }
 }
 
@@ -560,43 +594,45 @@ __device__ __forceinline__ void lds_fft_interleaved(C2<T>* buf, int logn, int lo
 }
 
 // The passes after a first radix-8 pass done by the caller (3 <= logn <= 13).
+// Waves without a unit skip each pass (a batch may fill only part of the block).
 template <class T, int DIR, int E, class TW>
 __device__ __forceinline__ void lds_fft_contig_after8(C2<T>* buf, int base, int logn, int nseq, const TW& tw,
                                                       int tid, int nthr) {
   switch (logn) {
     case 3: break;
-    case 4: lds_fft_c<T, DIR, E, 8, 4, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 5: lds_fft_c<T, DIR, E, 8, 5, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 6: lds_fft_c<T, DIR, E, 8, 6, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 7: lds_fft_c<T, DIR, E, 8, 7, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 8: lds_fft_c<T, DIR, E, 8, 8, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 9: lds_fft_c<T, DIR, E, 8, 9, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 10: lds_fft_c<T, DIR, E, 8, 10, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 11: lds_fft_c<T, DIR, E, 8, 11, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 12: lds_fft_c<T, DIR, E, 8, 12, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
-    default: lds_fft_c<T, DIR, E, 8, 13, 3, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 4: lds_fft_c<T, DIR, E, 8, 4, 3, TW, 4, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 5: lds_fft_c<T, DIR, E, 8, 5, 3, TW, 5, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 6: lds_fft_c<T, DIR, E, 8, 6, 3, TW, 6, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 7: lds_fft_c<T, DIR, E, 8, 7, 3, TW, 7, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 8: lds_fft_c<T, DIR, E, 8, 8, 3, TW, 8, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 9: lds_fft_c<T, DIR, E, 8, 9, 3, TW, 9, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 10: lds_fft_c<T, DIR, E, 8, 10, 3, TW, 10, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 11: lds_fft_c<T, DIR, E, 8, 11, 3, TW, 11, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 12: lds_fft_c<T, DIR, E, 8, 12, 3, TW, 12, true>(buf, base, nseq, tw, tid, nthr); break;
+    default: lds_fft_c<T, DIR, E, 8, 13, 3, TW, 13, true>(buf, base, nseq, tw, tid, nthr); break;
   }
 }
 
 // Batched CONTIG FFT of nseq sequences of length 2^logn, 1 <= logn <= 13,
-// dispatched to the compile-time variant (same contract as lds_fft).
+// dispatched to the compile-time variant (same contract as lds_fft); waves
+// without a unit skip each pass.
 template <class T, int DIR, int E, int RMAX, class TW>
 __device__ __forceinline__ void lds_fft_contig(C2<T>* buf, int base, int logn, int nseq, const TW& tw, int tid,
                                                int nthr) {
   switch (logn) {
-    case 1: lds_fft_c<T, DIR, E, RMAX, 1, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 2: lds_fft_c<T, DIR, E, RMAX, 2, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 3: lds_fft_c<T, DIR, E, RMAX, 3, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 4: lds_fft_c<T, DIR, E, RMAX, 4, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 5: lds_fft_c<T, DIR, E, RMAX, 5, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 6: lds_fft_c<T, DIR, E, RMAX, 6, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 7: lds_fft_c<T, DIR, E, RMAX, 7, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 8: lds_fft_c<T, DIR, E, RMAX, 8, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 9: lds_fft_c<T, DIR, E, RMAX, 9, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 10: lds_fft_c<T, DIR, E, RMAX, 10, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 11: lds_fft_c<T, DIR, E, RMAX, 11, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    case 12: lds_fft_c<T, DIR, E, RMAX, 12, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
-    default: lds_fft_c<T, DIR, E, RMAX, 13, 0, TW>(buf, base, nseq, tw, tid, nthr); break;
+    case 1: lds_fft_c<T, DIR, E, RMAX, 1, 0, TW, 1, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 2: lds_fft_c<T, DIR, E, RMAX, 2, 0, TW, 2, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 3: lds_fft_c<T, DIR, E, RMAX, 3, 0, TW, 3, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 4: lds_fft_c<T, DIR, E, RMAX, 4, 0, TW, 4, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 5: lds_fft_c<T, DIR, E, RMAX, 5, 0, TW, 5, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 6: lds_fft_c<T, DIR, E, RMAX, 6, 0, TW, 6, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 7: lds_fft_c<T, DIR, E, RMAX, 7, 0, TW, 7, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 8: lds_fft_c<T, DIR, E, RMAX, 8, 0, TW, 8, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 9: lds_fft_c<T, DIR, E, RMAX, 9, 0, TW, 9, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 10: lds_fft_c<T, DIR, E, RMAX, 10, 0, TW, 10, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 11: lds_fft_c<T, DIR, E, RMAX, 11, 0, TW, 11, true>(buf, base, nseq, tw, tid, nthr); break;
+    case 12: lds_fft_c<T, DIR, E, RMAX, 12, 0, TW, 12, true>(buf, base, nseq, tw, tid, nthr); break;
+    default: lds_fft_c<T, DIR, E, RMAX, 13, 0, TW, 13, true>(buf, base, nseq, tw, tid, nthr); break;
   }
 }
 

@@ -67,20 +67,23 @@ struct KArgs {
   const AnaGroupDev* ana;
   const SynGroupDev* syn;
   const SynRunDev* runs;
-  const I4* ent2_pos;     // frequency overlap-add program: two fixed entries per bin
-  const T* ent2_w;        // their weights: dual windows (synthesis) or analysis windows (adjoint)
+  const OlaRec<T>* ola2;  // frequency overlap-add program: first two entries of each bin, weighted
+                          // by the dual windows (synthesis) or the analysis windows (adjoint)
   const int32_t* ent_off; // further entries of each bin
   const int2* ent_pos;
   const T* ent_w;
   int32_t N, Mt, K, N1;
   int32_t N2, logN1, min_M, pad1_;  // min_M: smallest M_k of the plan
   int32_t logN2, C, logC, P;
-  int32_t logP, zero_ola;   // zero_ola: band_syn zeroes the output overlaps
+  int32_t logP, pad2_;
   // coefficient layout: coefficient n of band k (packing offset off_k) of
   // slice m sits at S off_k + m M_k + n (band-major) or m cps + off_k + n
   // (slice-major), relative to the signal's coef_base
   int32_t slice_major, cps;
   int64_t ws1, ws2;       // complex values per slice in the two workspace regions
+  // tasks [task0, task1) of the call's task table are the ones being launched
+  // (the time overlap-add needs to know which neighbouring slices come first)
+  int64_t task0, task1;
   T scale;                // (2N)^{-1/2}
 };
 
@@ -344,6 +347,13 @@ __device__ __forceinline__ void stage_twiddles(C2<T>* twl, const C2<T>* __restri
 
 // Stages the four-step twiddle tables of InterTw: hi[q] = e^{-2 pi i q / N1}
 // (level N1 of the pyramid) and lo[r] = e^{-2 pi i r / N} for r < N2.
+// The TwSplit tables for transforms up to 2^L: hi levels first, then lo.
+template <class T>
+__device__ __forceinline__ void stage_split(C2<T>* t, const C2<T>* __restrict__ tw, int L, int tid, int nthr) {
+  const int nh = 1 << (L - (L >> 1)), nl = 1 << (L >> 1);
+  for (int i = tid; i < nh + nl; i += nthr) t[i] = i < nh ? tw[nh + i] : tw[(1 << L) + i - nh];
+}
+
 template <class T>
 __device__ __forceinline__ void stage_inter(C2<T>* hi, C2<T>* lo, const C2<T>* __restrict__ tw, int N, int N1,
                                             int N2, int tid, int nthr) {
@@ -484,7 +494,8 @@ __device__ __forceinline__ void band_ana_fft(const KArgs<T>& a, const SliceTask&
 // inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff). Bins
 // outside [0, N] read the half spectrum by conjugate symmetry.
 // Block b takes work item g0 + b mod ng of task b / ng. TWL stages the
-// twiddles of lengths up to M in LDS. LDS: values (padded) | twiddles.
+// twiddles of lengths up to M in LDS, otherwise the two TwSplit tables.
+// LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef,
@@ -498,14 +509,14 @@ k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
   const int tid = threadIdx.x, nthr = blockDim.x;
   C2<T>* twl = reinterpret_cast<C2<T>*>(smem + lds_tail_offset<T>(G.cnt << G.logM));
   if constexpr (TWL) stage_twiddles(twl, a.tw, G.M, tid, nthr);
+  else stage_split(twl, a.tw, G.logM, tid, nthr);
   const C2<T>* __restrict__ X = W2 + (int64_t)task * a.ws2;
   C2<T>* __restrict__ cs = coef + tk.coef_base;
-  const TwGlobal<T> twg{a.tw};
   const TwLds<T> tws{twl};
 #define SLICQ_ANA_CASE(L)                                                                  \
   case L:                                                                                  \
     if constexpr (TWL) band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, tws, tid, nthr);        \
-    else band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, twg, tid, nthr);                      \
+    else band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, TwSplit<T>{twl, L}, tid, nthr);       \
     break;
   switch (G.logM) {
     SLICQ_ANA_CASE(1) SLICQ_ANA_CASE(2) SLICQ_ANA_CASE(3) SLICQ_ANA_CASE(4) SLICQ_ANA_CASE(5)
@@ -513,7 +524,7 @@ k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
     SLICQ_ANA_CASE(11) SLICQ_ANA_CASE(12)
     default:
       if constexpr (TWL) band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, tws, tid, nthr);
-      else band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, twg, tid, nthr);
+      else band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, TwSplit<T>{twl, 13}, tid, nthr);
       break;
   }
 #undef SLICQ_ANA_CASE
@@ -532,7 +543,8 @@ __device__ __forceinline__ int run_coef_index(const SliceTask& tk, const SynRunD
 // in increasing k, of weight * C_k[j mod M_k] (for the self-mirrored DC and
 // Nyquist bands weight * (C[j mod M] + conj C[-j mod M]), the real part of the
 // full synthesis). Block b takes work item g0 + b mod ng of task b / ng; item
-// 0 also clears the slice's output overlap. TWL stages the twiddles in LDS.
+// TWL stages the twiddles of
+// lengths up to the item's largest M in LDS, otherwise the two TwSplit tables.
 // LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
@@ -546,23 +558,15 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
   C2<T>* twl = reinterpret_cast<C2<T>*>(smem + lds_tail_offset<T>(G.total));
+  const int Lmax = 31 - __builtin_clz((unsigned)G.maxM);
   const C2<T>* __restrict__ cs = coef + tk.coef_base;
-  if (gi == 0 && a.zero_ola && (tk.flags & 1)) {
-    // zero the right-hand overlap of this slice in the output, which the
-    // inverse pass then accumulates into from this slice and the next
-    const int j0 = a.N + (a.N - a.Mt) / 2 + 1, j1 = a.N + (a.N + a.Mt) / 2;
-    for (int j = j0 + tid; j < j1; j += nthr) {
-      int64_t idx = tk.y_start + j;
-      if (idx >= tk.y_period) idx -= tk.y_period;
-      if (idx < tk.y_valid) y[tk.y_base + idx] = T(0);
-    }
-  }
   if ((E == 8 || E == 16) && a.min_M >= 8) {
     // first radix-8 pass fused with the loads: unit u (all runs flattened,
     // u = p / 8) takes slots j + r M/8 of one band, r = 0..7
     const int units = G.total >> 3;
 #pragma unroll
     for (int i = 0; i < E / 8; ++i) {
+      const bool live = wave_has(tid + i * nthr, units);   // idle waves skip loads and arithmetic
       const int u = imin(tid + i * nthr, units - 1);
       const int p = u << 3;
       int lds_off = G.r[0].lds_off, off = G.r[0].off, M = G.r[0].M, logM = G.r[0].logM;
@@ -576,16 +580,21 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       const int sb = q >> lu, j = q & ((1 << lu) - 1);
       const int cbase = a.slice_major ? tk.m * a.cps + off + sb * M + j : tk.S * (off + sb * M) + tk.m * M + j;
       C2<T> v[8];
+      if (live) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = cs[cbase + (r << lu)];
-      if constexpr (TWL) {
-        if (i == 0) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+        for (int r = 0; r < 8; ++r) v[r] = cs[cbase + (r << lu)];
       }
-      dft_reg<T, 8, -1>(v);
-      if (tid + i * nthr < units) {
-        const int p0 = lds_off + (sb << logM) + (j << 3);
+      if (i == 0) {
+        if constexpr (TWL) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+        else stage_split(twl, a.tw, Lmax, tid, nthr);
+      }
+      if (live) {
+        dft_reg<T, 8, -1>(v);
+        if (tid + i * nthr < units) {
+          const int p0 = lds_off + (sb << logM) + (j << 3);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) buf[pidx(p0 + r)] = v[r];
+          for (int r = 0; r < 8; ++r) buf[pidx(p0 + r)] = v[r];
+        }
       }
     }
     __syncthreads();
@@ -599,7 +608,7 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       int t = tid;
       asm volatile("" : "+v"(t));
       if constexpr (TWL) lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, t, nthr);
-      else lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, t, nthr);
+      else lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwSplit<T>{twl, Lmax}, t, nthr);
     }
   } else {
     // coefficient addresses of a batch of values (no branches), then every load
@@ -629,8 +638,9 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       C2<T> v[EB];
 #pragma unroll
       for (int i = 0; i < EB; ++i) v[i] = cs[idx[i]];
-      if constexpr (TWL) {
-        if (c == 0) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+      if (c == 0) {
+        if constexpr (TWL) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
+        else stage_split(twl, a.tw, Lmax, tid, nthr);
       }
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
@@ -647,38 +657,32 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       int t = tid;
       asm volatile("" : "+v"(t));
       if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, t, nthr);
-      else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwGlobal<T>{a.tw}, t, nthr);
+      else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwSplit<T>{twl, Lmax}, t, nthr);
     }
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;
-  const C2<T>* __restrict__ w2 = reinterpret_cast<const C2<T>*>(a.ent2_w);
   constexpr int QB = 2;                         // owned bins per thread per round
   for (int j0 = G.lo + tid; j0 < G.hi; j0 += QB * nthr) {
-    I4 ps[QB];
-    C2<T> ws[QB];
-    int eo[QB], ee[QB];
+    OlaRec<T> rec[QB];
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      const int j = imin(j0 + q * nthr, G.hi - 1);
-      ps[q] = a.ent2_pos[j];
-      ws[q] = w2[j];
-      eo[q] = a.ent_off[j];
-      ee[q] = a.ent_off[j + 1];
-    }
+    for (int q = 0; q < QB; ++q) rec[q] = a.ola2[imin(j0 + q * nthr, G.hi - 1)];
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int j = j0 + q * nthr;
       if (j >= G.hi) continue;
-      C2<T> c0 = buf[pidx(ps[q].x)], c1 = buf[pidx(ps[q].z)];
-      const C2<T> m0 = buf[pidx(imax(ps[q].y, 0))], m1 = buf[pidx(imax(ps[q].w, 0))];
-      if (ps[q].y >= 0) c0 = cadd(c0, cconj(m0));
-      if (ps[q].w >= 0) c1 = cadd(c1, cconj(m1));
-      C2<T> acc = cadd(cscale(c0, ws[q].x), cscale(c1, ws[q].y));
-      for (int e = eo[q]; e < ee[q]; ++e) {        // bins covered by more than two bands
-        const int2 pe = a.ent_pos[e];
-        C2<T> c = buf[pidx(pe.x)];
-        if (pe.y >= 0) c = cadd(c, cconj(buf[pidx(pe.y)]));
-        acc = cadd(acc, cscale(c, a.ent_w[e]));
+      const uint32_t y0 = rec[q].yy & kOlaNone, y1 = rec[q].yy >> 16;
+      C2<T> c0 = buf[pidx(rec[q].xx & kOlaPosMask)], c1 = buf[pidx(rec[q].xx >> 16)];
+      const C2<T> m0 = buf[pidx(y0 == kOlaNone ? 0 : y0)], m1 = buf[pidx(y1 == kOlaNone ? 0 : y1)];
+      if (y0 != kOlaNone) c0 = cadd(c0, cconj(m0));
+      if (y1 != kOlaNone) c1 = cadd(c1, cconj(m1));
+      C2<T> acc = cadd(cscale(c0, rec[q].w0), cscale(c1, rec[q].w1));
+      if (rec[q].xx & kOlaMore) {                 // bins covered by more than two bands
+        for (int e = a.ent_off[j]; e < a.ent_off[j + 1]; ++e) {
+          const int2 pe = a.ent_pos[e];
+          C2<T> c = buf[pidx(pe.x)];
+          if (pe.y >= 0) c = cadd(c, cconj(buf[pidx(pe.y)]));
+          acc = cadd(acc, cscale(c, a.ent_w[e]));
+        }
       }
       Z[j] = acc;
     }
@@ -766,30 +770,60 @@ k_inv_passA(KArgs<T> a, const C2<T>* __restrict__ W2, C2<T>* __restrict__ W1) {
 #undef SLICQ_PA
 }
 
-// Adds v at window position j of the slice into the output: plain stores where
-// only this slice contributes, atomic adds on the M-1 samples shared with a
-// neighbour (exactly two contributions into a zeroed sample: order-free).
+// Time overlap-add (Algorithm 4) without atomics. Window position j of a
+// slice (0 <= j < 2N, output sample start + j) is its own when
+// 2|j - N| <= N - Mt and is shared with the left (j < N) or right neighbour
+// slice when N - Mt < 2|j - N| < N + Mt: the two overlaps of nov samples,
+// |j - N| = ola_d0 .. ola_d0 + nov - 1. Of the two contributions to a shared
+// sample, the one written first is stored into y; the other is stored into
+// the slice's overlap buffer (left side at 0, right side at Mt) and added by
+// k_ola_fix after the inverse pass. One rounding either way (a + b = b + a).
+__host__ __device__ constexpr int ola_d0(int N, int Mt) { return (N - Mt) / 2 + 1; }
+__host__ __device__ constexpr int ola_count(int N, int Mt) { return (N + Mt - 1) / 2 - (N - Mt) / 2; }
+
+// Which sides of task gi (slice m of S; tasks of one signal are consecutive
+// in m, neighbours circular) are written second: the left side when the left
+// neighbour was launched in an earlier batch of tasks or is in this one, the
+// right side when the right neighbour was launched in an earlier batch. With
+// a single batch: every left side, no right side. Single-slice tasks (stream
+// rings) take their neighbours from earlier and later calls.
+__device__ __forceinline__ void ola_sides(const SliceTask& tk, int64_t gi, int64_t t0, int64_t t1, bool& add_l,
+                                          bool& add_r) {
+  if (tk.S <= 1) {
+    add_l = true;
+    add_r = false;
+    return;
+  }
+  const int64_t iL = tk.m >= 1 ? gi - 1 : gi + tk.S - 1;
+  const int64_t iR = tk.m <= tk.S - 2 ? gi + 1 : gi - (tk.S - 1);
+  add_l = iL < t1;
+  add_r = iR < t0;
+}
+
+// Stores v at window position j of a slice: into the output, or into the
+// overlap buffer ov for a shared sample written second.
 template <class T>
-__device__ __forceinline__ void ola_store(T* __restrict__ ys, int ystart, int yperiod, int yvalid, int j, T v,
-                                          int N, int Mt) {
-  int dj = j - N;
-  if (dj < 0) dj = -dj;
+__device__ __forceinline__ void ola_store(T* __restrict__ ys, T* __restrict__ ov, int ystart, int yperiod,
+                                          int yvalid, int j, T v, int N, int Mt, bool add_l, bool add_r) {
+  const bool right = j > N;
+  const int dj = right ? j - N : N - j;
   if (2 * dj >= N + Mt) return;
   int idx = ystart + j;
   if (idx >= yperiod) idx -= yperiod;
   if (idx >= yvalid) return;
-  if (2 * dj <= N - Mt) ys[idx] = v;
-  else unsafeAtomicAdd(ys + idx, v);
+  if (2 * dj > N - Mt && (right ? add_r : add_l)) ov[(right ? Mt : 0) + dj - ola_d0(N, Mt)] = v;
+  else ys[idx] = v;
 }
 
 // Inverse pass B: columns n1 in [cb C, cb C + C): transform over k2 (length
 // N2 = 2^LOGN, e^+; the first FFT pass reads W1 directly), giving
 // z[n1 + N1 n2] = y[2n] + i y[2n+1]; the last pass scales, multiplies by the
-// synthesis slice window and overlap-adds into the output (Algorithm 4).
+// synthesis slice window and overlap-adds into the output (Algorithm 4) or
+// the overlap buffer ov.
 template <class T, int LOGN, class TW>
 __device__ __forceinline__ void inv_passB_body(const KArgs<T>& a, const SliceTask& tk, int cb, C2<T>* buf,
                                                const TW& tws, const C2<T>* __restrict__ in, T* __restrict__ y,
-                                               int tid, int nthr) {
+                                               T* __restrict__ ov, bool add_l, bool add_r, int tid, int nthr) {
   constexpr int LAST = last_pass_logns(LOGN, 8), RL = 1 << (LOGN - LAST), UL = kPassE / RL, NS = 1 << LAST;
   const int c0 = cb * a.C, smask = a.C - 1, unitsL = 1 << (a.logC + LAST);
   // synthesis window at this thread's outputs, fetched before the transform
@@ -806,16 +840,18 @@ __device__ __forceinline__ void inv_passB_body(const KArgs<T>& a, const SliceTas
   auto load = [&](int s, int e) -> C2<T> { return in[e * a.N1 + c0 + s]; };
   auto store = [&](int i, int r, int s, int e, C2<T> z) {
     const int j = 2 * (c0 + s + a.N1 * e);
-    ola_store(ys, ys0, yper, yval, j, z.x * a.scale * h[i][r].x, a.N, a.Mt);
-    ola_store(ys, ys0, yper, yval, j + 1, z.y * a.scale * h[i][r].y, a.N, a.Mt);
+    ola_store(ys, ov, ys0, yper, yval, j, z.x * a.scale * h[i][r].x, a.N, a.Mt, add_l, add_r);
+    ola_store(ys, ov, ys0, yper, yval, j + 1, z.y * a.scale * h[i][r].y, a.N, a.Mt, add_l, add_r);
   };
   fft_ci_fused<T, 1, kPassE, LOGN, true, true, false>(buf, a.logC, tws, tid, nthr, load, store);
 }
 
-// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles.
+// TWL stages the FFT twiddles in LDS. LDS: values (padded) | twiddles. The
+// overlap buffer of a task is its W2 region (free once pass A has read it).
 template <class T, bool TWL>
 __global__ void __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(kColPassWaves)))
-k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W1, T* __restrict__ y) {
+k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2,
+            T* __restrict__ y) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int nCB = a.N1 >> a.logC;
@@ -826,31 +862,64 @@ k_inv_passB(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __rest
   C2<T>* twl = buf + padded(a.C * a.N2);
   if constexpr (TWL) stage_twiddles(twl, a.tw, a.N2, tid, nthr);
   const C2<T>* in = W1 + (int64_t)task * a.ws1;
+  T* ov = reinterpret_cast<T*>(W2 + (int64_t)task * a.ws2);
+  bool add_l, add_r;
+  ola_sides(tk, a.task0 + task, a.task0, a.task1, add_l, add_r);
   const TwLds<T> tl{twl};
   const TwGlobal<T> tg{a.tw};
-#define SLICQ_PB(L)                                                              \
-  if constexpr (TWL) inv_passB_body<T, L>(a, tk, cb, buf, tl, in, y, tid, nthr); \
-  else inv_passB_body<T, L>(a, tk, cb, buf, tg, in, y, tid, nthr);
+#define SLICQ_PB(L)                                                                                 \
+  if constexpr (TWL) inv_passB_body<T, L>(a, tk, cb, buf, tl, in, y, ov, add_l, add_r, tid, nthr); \
+  else inv_passB_body<T, L>(a, tk, cb, buf, tg, in, y, ov, add_l, add_r, tid, nthr);
   SLICQ_LOGN_SWITCH(a.logN2, SLICQ_PB)
 #undef SLICQ_PB
 }
 
-// Zeroes the right-hand output overlap of every task (used when slices are
-// processed in several chunks, so that no chunk clears a sample that an
-// earlier chunk has already accumulated into).
+// Second contributions of the shared output samples: block b adds the
+// buffered samples r*kOlaFixRun .. of side b % 2 (left, right) of task
+// b / (2 * runs) into the output, for the sides written second (see
+// ola_sides); each thread moves kOlaFixPer samples 256 apart.
+constexpr int kOlaFixPer = 8, kOlaFixRun = 256 * kOlaFixPer;
 template <class T>
-__global__ void __launch_bounds__(256) k_zero_overlaps(const SliceTask* __restrict__ tasks, int64_t ntasks,
-                                                       int32_t N, int32_t Mt, T* __restrict__ y) {
-  const int64_t per = (Mt - 1 + 255) / 256;
-  const int64_t task = blockIdx.x / per;
-  if (task >= ntasks) return;
+__global__ void __launch_bounds__(256) k_ola_fix(KArgs<T> a, const SliceTask* __restrict__ tasks,
+                                                 const C2<T>* __restrict__ W2, T* __restrict__ y) {
+  const int nov = ola_count(a.N, a.Mt);
+  const int runs = (nov + kOlaFixRun - 1) / kOlaFixRun;
+  const int64_t task = blockIdx.x / (2 * runs);
+  const int rest = (int)(blockIdx.x - task * 2 * runs);
+  const bool right = rest & 1;
   const SliceTask tk = tasks[task];
-  if (tk.S == 0 || !(tk.flags & 1)) return;
-  const int j = N + (N - Mt) / 2 + 1 + (int)(blockIdx.x - task * per) * 256 + threadIdx.x;
-  if (j >= N + (N + Mt) / 2) return;
-  int64_t idx = tk.y_start + j;
-  if (idx >= tk.y_period) idx -= tk.y_period;
-  if (idx < tk.y_valid) y[tk.y_base + idx] = T(0);
+  if (tk.S == 0) return;
+  bool add_l, add_r;
+  ola_sides(tk, a.task0 + task, a.task0, a.task1, add_l, add_r);
+  if (!(right ? add_r : add_l)) return;
+  const T* __restrict__ ov = reinterpret_cast<const T*>(W2 + task * a.ws2) + (right ? a.Mt : 0);
+  T* __restrict__ ys = y + tk.y_base;
+  const int d0 = ola_d0(a.N, a.Mt);
+  const int q0 = (rest >> 1) * kOlaFixRun + (int)threadIdx.x;
+  int64_t idx[kOlaFixPer];
+  T v[kOlaFixPer], w[kOlaFixPer];
+#pragma unroll
+  for (int i = 0; i < kOlaFixPer; ++i) {
+    const int q = imin(q0 + 256 * i, nov - 1);
+    const int dj = d0 + q;
+    int64_t t = tk.y_start + (right ? a.N + dj : a.N - dj);
+    if (t >= tk.y_period) t -= tk.y_period;
+    idx[i] = imin64(t, tk.y_valid - 1);
+  }
+#pragma unroll
+  for (int i = 0; i < kOlaFixPer; ++i) {
+    v[i] = ov[imin(q0 + 256 * i, nov - 1)];
+    w[i] = ys[idx[i]];
+  }
+#pragma unroll
+  for (int i = 0; i < kOlaFixPer; ++i) {
+    const int q = q0 + 256 * i;
+    if (q >= nov) break;
+    const int dj = d0 + q;
+    int64_t t = tk.y_start + (right ? a.N + dj : a.N - dj);
+    if (t >= tk.y_period) t -= tk.y_period;
+    if (t < tk.y_valid) ys[t] = w[i] + v[i];
+  }
 }
 
 // Streaming ring traffic: block b moves descriptor b's samples from the packed

@@ -78,8 +78,7 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
   a.ana = reinterpret_cast<const AnaGroupDev*>(base + L.ana);
   a.syn = reinterpret_cast<const SynGroupDev*>(base + L.syn);
   a.runs = reinterpret_cast<const SynRunDev*>(base + L.runs);
-  a.ent2_pos = reinterpret_cast<const I4*>(base + L.ent2_pos);
-  a.ent2_w = reinterpret_cast<const T*>(base + (adjoint ? L.ent2_wadj : L.ent2_wsyn));
+  a.ola2 = reinterpret_cast<const OlaRec<T>*>(base + (adjoint ? L.ola_adj : L.ola_syn));
   a.ent_off = reinterpret_cast<const int32_t*>(base + L.ent_off);
   a.ent_pos = reinterpret_cast<const int2*>(base + L.ent_pos);
   a.ent_w = reinterpret_cast<const T*>(base + (adjoint ? L.ent_wadj : L.ent_wsyn));
@@ -110,10 +109,9 @@ struct Geometry {
   int g2, b2; size_t s2;      // forward pass 2 / inverse pass A
   // band analysis: small items [0, ga) with ba threads, E = kSmallE (kernel
   // bound kAnaThreads); large items [ga, ga + gab) with bab threads,
-  // E = kBigAnaE (bound kAnaBigThreads). Small items read the twiddle pyramid
-  // from global memory (cached): an LDS copy per block would cost residency,
-  // which measured slower; large items stage it in LDS where that costs no
-  // residency (tab, tsb).
+  // E = kBigAnaE (bound kAnaBigThreads). Items stage two small twiddle tables
+  // (TwSplit) in LDS; every level up to M (tab, tsb) only for large items and
+  // only where that costs no resident block per CU.
   int ga, ba; size_t sa;
   int gab, bab; size_t sab; bool tab;
   // band synthesis: small items [0, gs), bs threads, E = kSmallE (bound
@@ -135,6 +133,11 @@ template <class T>
 Geometry<T> geometry(const Plan& p) {
   Geometry<T> g{};
   const size_t cb = sizeof(C2<T>);
+  auto split_bytes = [&](int32_t maxM) {   // TwSplit tables for lengths up to maxM
+    int L = 0;
+    while ((1 << L) < maxM) ++L;
+    return (size_t)split_tw_entries(L) * cb;
+  };
   g.g1 = p.N1 / p.C;
   g.b1 = threads_for((int64_t)p.C * p.N2, kPassE);
   g.s1 = (padded(p.C * p.N2) + p.N2 + p.N1 + p.N2) * cb;   // values, FFT twiddles, four-step tables
@@ -143,24 +146,24 @@ Geometry<T> geometry(const Plan& p) {
   g.s2 = (padded(2 * p.P * p.N1) + p.N1 + p.N1 + p.N2) * cb;   // values, FFT twiddles, four-step tables
   g.ga = p.ana_small;
   g.ba = threads_for(std::max(p.ana_cap_small, 1), kSmallE);
-  g.sa = lds_tail_offset<T>(p.ana_cap_small);
+  g.sa = lds_tail_offset<T>(p.ana_cap_small) + split_bytes(p.ana_maxM_small);
   g.gab = (int)p.ana.size() - p.ana_small;
   g.bab = threads_for(std::max(p.ana_cap_big, 1), kBigAnaE);
   g.sab = lds_tail_offset<T>(p.ana_cap_big);
   int32_t big_ana_M = 0;
   for (int i = p.ana_small; i < (int)p.ana.size(); ++i) big_ana_M = std::max(big_ana_M, p.ana[i].M);
   g.tab = lds_twiddles_pay(g.sab, (size_t)big_ana_M * cb);
-  if (g.tab) g.sab += (size_t)big_ana_M * cb;
+  g.sab += g.tab ? (size_t)big_ana_M * cb : split_bytes(big_ana_M);
   g.gs = p.syn_small;
   g.bs = threads_for(std::max(p.syn_cap_small, 1), kSmallE);
-  g.ss = lds_tail_offset<T>(p.syn_cap_small);
+  g.ss = lds_tail_offset<T>(p.syn_cap_small) + split_bytes(p.syn_maxM_small);
   g.gsb = (int)p.syn.size() - p.syn_small;
   g.bsb = threads_for(std::max(p.syn_cap_big, 1), kBigSynE);
   g.ssb = lds_tail_offset<T>(p.syn_cap_big);
   int32_t big_maxM = 0;
   for (int i = p.syn_small; i < (int)p.syn.size(); ++i) big_maxM = std::max(big_maxM, p.syn[i].maxM);
   g.tsb = lds_twiddles_pay(g.ssb, (size_t)big_maxM * cb);
-  if (g.tsb) g.ssb += (size_t)big_maxM * cb;
+  g.ssb += g.tsb ? (size_t)big_maxM * cb : split_bytes(big_maxM);
   size_t lds = std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss));
   if (g.gab) lds = std::max(lds, g.sab);
   if (g.gsb) lds = std::max(lds, g.ssb);
@@ -206,13 +209,27 @@ void launch_analysis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, con
   (void)p;
 }
 
-// Synthesis (or adjoint) of tasks [t0, t0 + cnt) (Algorithm 4).
+// Inverse pass B of tasks [t0, t0 + cnt) of the call's task table (tasks
+// points at task t0), then the second contributions of the shared samples.
 template <class T, class Launch>
-void launch_synthesis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks,
+void launch_inv_passB(const KArgs<T>& a0, const Geometry<T>& g, const SliceTask* tasks, int64_t t0, int64_t cnt,
+                      C2<T>* W1, C2<T>* W2, T* y, Launch& L) {
+  KArgs<T> a = a0;
+  a.task0 = t0;
+  a.task1 = t0 + cnt;
+  L.launch(k_inv_passB<T, true>, cnt * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, W2, y);
+  const int nov = ola_count(a.N, a.Mt);
+  if (nov > 0)
+    L.launch(k_ola_fix<T>, cnt * 2 * ((nov + kOlaFixRun - 1) / kOlaFixRun), 256, 0, a, tasks, (const C2<T>*)W2, y);
+}
+
+// Synthesis (or adjoint) of tasks [t0, t0 + cnt) (Algorithm 4); tasks points at task t0.
+template <class T, class Launch>
+void launch_synthesis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t t0,
                       int64_t cnt, const C2<T>* coef, T* y, C2<T>* W1, C2<T>* W2, Launch& L) {
   launch_band_syn(a, g, tasks, cnt, coef, W2, y, L);
   L.launch(k_inv_passA<T, true>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1);
-  L.launch(k_inv_passB<T, true>, cnt * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, y);
+  launch_inv_passB(a, g, tasks, t0, cnt, W1, W2, y, L);
   (void)p;
 }
 

@@ -109,6 +109,23 @@ size_t append(std::vector<unsigned char>& blob, const T* data, size_t n) {
   return off;
 }
 
+// The per-bin records of the first two overlap-add entries (weights w: two per bin).
+template <class T>
+std::vector<OlaRec<T>> ola_records(const Plan& p, const std::vector<double>& w) {
+  const size_t nb = p.ent2_pos.size() / 4;
+  std::vector<OlaRec<T>> r(nb);
+  auto y16 = [](int32_t y) { return y < 0 ? kOlaNone : (uint32_t)y; };
+  for (size_t j = 0; j < nb; ++j) {
+    const int32_t* e = &p.ent2_pos[4 * j];
+    const bool more = p.ent_off[j + 1] > p.ent_off[j];
+    r[j].xx = (uint32_t)e[0] | ((uint32_t)e[2] << 16) | (more ? kOlaMore : 0u);
+    r[j].yy = y16(e[1]) | (y16(e[3]) << 16);
+    r[j].w0 = (T)w[2 * j];
+    r[j].w1 = (T)w[2 * j + 1];
+  }
+  return r;
+}
+
 }  // namespace
 
 int build_plan(const PlanParams& p, Plan& out, std::string& err) {
@@ -531,7 +548,6 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
   lay.ana = append(blob, p.ana.data(), p.ana.size());
   lay.syn = append(blob, p.syn.data(), p.syn.size());
   lay.runs = append(blob, p.runs.data(), p.runs.size());
-  lay.ent2_pos = append(blob, p.ent2_pos.data(), p.ent2_pos.size());
   lay.ent_off = append(blob, p.ent_off.data(), p.ent_off.size());
   // overflow entries: keep at least one element so every table has an address
   std::vector<int32_t> epos = p.ent_pos;
@@ -539,15 +555,16 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
   if (ews.empty()) { epos = {0, -1}; ews = {0.0}; ewa = {0.0}; }
   lay.ent_pos = append(blob, epos.data(), epos.size());
   if (dtype == 0) {
-    std::vector<float> w2s(p.ent2_wsyn.begin(), p.ent2_wsyn.end()), w2a(p.ent2_wadj.begin(), p.ent2_wadj.end());
     std::vector<float> ws(ews.begin(), ews.end()), wa(ewa.begin(), ewa.end());
-    lay.ent2_wsyn = append(blob, w2s.data(), w2s.size());
-    lay.ent2_wadj = append(blob, w2a.data(), w2a.size());
+    const std::vector<OlaRec<float>> rs = ola_records<float>(p, p.ent2_wsyn), ra = ola_records<float>(p, p.ent2_wadj);
+    lay.ola_syn = append(blob, rs.data(), rs.size());
+    lay.ola_adj = append(blob, ra.data(), ra.size());
     lay.ent_wsyn = append(blob, ws.data(), ws.size());
     lay.ent_wadj = append(blob, wa.data(), wa.size());
   } else {
-    lay.ent2_wsyn = append(blob, p.ent2_wsyn.data(), p.ent2_wsyn.size());
-    lay.ent2_wadj = append(blob, p.ent2_wadj.data(), p.ent2_wadj.size());
+    const std::vector<OlaRec<double>> rs = ola_records<double>(p, p.ent2_wsyn), ra = ola_records<double>(p, p.ent2_wadj);
+    lay.ola_syn = append(blob, rs.data(), rs.size());
+    lay.ola_adj = append(blob, ra.data(), ra.size());
     lay.ent_wsyn = append(blob, ews.data(), ews.size());
     lay.ent_wadj = append(blob, ewa.data(), ewa.size());
   }

@@ -280,9 +280,8 @@ class StreamServer {
       C2<T>* W1 = reinterpret_cast<C2<T>*>(work_ + wl_.w1_off);
       C2<T>* W2 = reinterpret_cast<C2<T>*>(work_ + wl_.w2_off);
       KArgs<T> a = make_args<T>(p_, dt_, false);
-      a.zero_ola = 1;
       launch_analysis<T>(p_, a, geo_, tasks_d, ntask, xring_, coef_, W1, W2, be_);
-      launch_synthesis<T>(p_, a, geo_, tasks_d, ntask, coef_, yring_, W1, W2, be_);
+      launch_synthesis<T>(p_, a, geo_, tasks_d, 0, ntask, coef_, yring_, W1, W2, be_);
     }
     // release output made final by this tick's slices
     int64_t gathered = 0;

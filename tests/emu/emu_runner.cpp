@@ -155,16 +155,9 @@ int run(const std::string& op, slicq::Plan& p, int dt, int64_t chunk_req, const 
     std::fclose(f);
   } else {
     KArgs<T> a = make_args<T>(p, dt, kind == "adj");
-    const bool chunked = w.chunk < total;
-    a.zero_ola = chunked ? 0 : 1;
-    if (chunked) {
-      const int64_t per = (p.Mt - 1 + 255) / 256;
-      L.launch(k_zero_overlaps<T>, total * per, 256, 0, (const SliceTask*)tasks, total, (int32_t)p.N,
-               (int32_t)p.Mt, x.data());
-    }
     for (int64_t t0 = 0; t0 < total; t0 += w.chunk)
-      launch_synthesis<T>(p, a, g, tasks + t0, std::min(w.chunk, total - t0), (const C2<T>*)coef.data(), x.data(),
-                          W1, W2, L);
+      launch_synthesis<T>(p, a, g, tasks + t0, t0, std::min(w.chunk, total - t0), (const C2<T>*)coef.data(),
+                          x.data(), W1, W2, L);
     FILE* f = std::fopen(outpath, "wb");
     for (int64_t i = 0; i < xlen; ++i) {
       double v = (double)x[i];

@@ -30,6 +30,10 @@ extern thread_local std::barrier<>* emu_barrier;
 
 inline void __syncthreads() { emu_barrier->arrive_and_wait(); }
 
+// The kernels read the first lane only of values that are equal on every lane
+// of a wave (a wave's base thread index), so each lane's own value is the result.
+inline int __builtin_amdgcn_readfirstlane(int x) { return x; }
+
 template <class T>
 inline T unsafeAtomicAdd(T* p, T v) {
   return std::atomic_ref<T>(*p).fetch_add(v);

@@ -43,6 +43,15 @@ def test_emu_chunked_and_batched():
     ref = pack(pl, analyze(pl, x))
     assert rel(H.analyze(kw, x, 1, chunk=3), ref) < 1e-12
     assert rel(H.synthesize(kw, ref, 500, 1, chunk=3), x) < 1e-12
+    # one slice per chunk: every shared output sample has its two slices in
+    # different launches, the first slice's left neighbour (the last slice,
+    # circularly) in a later one; two slices share both of their overlaps
+    assert rel(H.synthesize(kw, ref, 500, 1, chunk=1), x) < 1e-12
+    x2 = np.random.default_rng(6).standard_normal(64)
+    r2 = pack(pl, analyze(pl, x2))
+    assert num_slices(64, pl.two_n) == 2
+    assert rel(H.synthesize(kw, r2, 64, 1, chunk=1), x2) < 1e-12
+    assert rel(H.synthesize(kw, r2, 64, 0, chunk=1), x2) < 1e-5
     xs = [np.random.default_rng(i).standard_normal(n) for i, n in enumerate([100, 0, 64, 257])]
     cb = H.analyze_batched(kw, xs, 1)
     refb = np.concatenate([pack(pl, analyze(pl, v)) for v in xs if len(v)])

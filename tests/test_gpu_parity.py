@@ -199,6 +199,15 @@ def test_small_workspace_runs_in_chunks(sq, dev):
     c_chunk = plan.analyze(x, work=work)
     y_chunk = plan.synthesize(c_chunk, T, work=work)
     assert torch.equal(c_full, c_chunk) and torch.equal(y_full, y_chunk)
+    # one slice per pass, two slices: both shared overlaps span two launches
+    T2 = plan.N
+    x2 = torch.tensor(pink_plus_tones(T2, 48000.0, 10), dtype=torch.float32, device=dev)
+    assert plan.num_slices(T2) == 2
+    one = plan.workspace_bytes(0, 2) - (2 * plan.N + 64) * 8
+    w1 = torch.empty(one, dtype=torch.uint8, device=dev)
+    c2 = plan.analyze(x2).clone()
+    y2 = plan.synthesize(c2, T2).clone()
+    assert torch.equal(plan.synthesize(c2, T2, work=w1), y2)
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
