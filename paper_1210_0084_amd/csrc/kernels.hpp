@@ -161,20 +161,29 @@ __device__ __forceinline__ void fwd_pass1_body(const KArgs<T>& a, const SliceTas
   const T* __restrict__ xs = x + tk.x_base;
   const SliceIn si = slice_in(tk);
   const int c0 = cb * a.C;
-  auto load = [&](int s, int e) -> C2<T> {
+  // the window product is rounded by itself: the same value whichever load
+  // path fed it, so both instantiations below give bitwise equal results
+  auto load_plain = [&](int s, int e) -> C2<T> {
     const int j = 2 * (c0 + s + a.N1 * e);
     const int jc = imin(imax(j, jlo), jhi);
-    C2<T> x2;
-    if (plain) x2 = *reinterpret_cast<const C2<T>*>(xs + si.start + jc);
-    else x2 = load_sample_pair(xs, si, jc);
+    const C2<T> x2 = *reinterpret_cast<const C2<T>*>(xs + si.start + jc);
     const C2<T> h2 = *reinterpret_cast<const C2<T>*>(a.h0 + j);
-    // rounded by itself: the same value whichever load path (and code) fed it
+    return {mul_rn(x2.x, h2.x), mul_rn(x2.y, h2.y)};
+  };
+  auto load_any = [&](int s, int e) -> C2<T> {
+    const int j = 2 * (c0 + s + a.N1 * e);
+    const int jc = imin(imax(j, jlo), jhi);
+    const C2<T> x2 = load_sample_pair(xs, si, jc);
+    const C2<T> h2 = *reinterpret_cast<const C2<T>*>(a.h0 + j);
     return {mul_rn(x2.x, h2.x), mul_rn(x2.y, h2.y)};
   };
   auto store = [&](int, int, int s, int e, C2<T> v) {
     out[e * a.N1 + c0 + s] = cmul(v, inter.template get<-1>(((c0 + s) * e) & (a.N - 1)));
   };
-  fft_ci_fused<T, -1, kPassE, LOGN, true, true, false>(buf, a.logC, tws, tid, nthr, load, store);
+  // one branch per block: a per-load choice made the compiler wait for every
+  // load before issuing the next
+  if (plain) fft_ci_fused<T, -1, kPassE, LOGN, true, true, false>(buf, a.logC, tws, tid, nthr, load_plain, store);
+  else fft_ci_fused<T, -1, kPassE, LOGN, true, true, false>(buf, a.logC, tws, tid, nthr, load_any, store);
 }
 
 // TWL stages the FFT twiddles in LDS. LDS: values (padded) | FFT twiddles (N2)
@@ -332,9 +341,14 @@ k_fwd_pass2(KArgs<T> a, const C2<T>* __restrict__ W1, C2<T>* __restrict__ W2) {
 }
 
 // Stages the TwLds table for FFT lengths up to n (n - 1 entries) at twl:
-// each thread issues up to 8 loads before writing any of them.
+// one entry per thread when the block covers the table, else each thread
+// issues up to 8 loads before writing any of them.
 template <class T>
 __device__ __forceinline__ void stage_twiddles(C2<T>* twl, const C2<T>* __restrict__ tw, int n, int tid, int nthr) {
+  if (n - 1 <= nthr) {
+    if (tid < n - 1) twl[tid] = tw_stage_value(tw, tid);
+    return;
+  }
   for (int b = tid; b < n - 1; b += 8 * nthr) {
     C2<T> v[8];
 #pragma unroll
@@ -345,8 +359,6 @@ __device__ __forceinline__ void stage_twiddles(C2<T>* twl, const C2<T>* __restri
   }
 }
 
-// Stages the four-step twiddle tables of InterTw: hi[q] = e^{-2 pi i q / N1}
-// (level N1 of the pyramid) and lo[r] = e^{-2 pi i r / N} for r < N2.
 // The TwSplit tables for transforms up to 2^L: hi levels first, then lo.
 template <class T>
 __device__ __forceinline__ void stage_split(C2<T>* t, const C2<T>* __restrict__ tw, int L, int tid, int nthr) {
@@ -354,9 +366,17 @@ __device__ __forceinline__ void stage_split(C2<T>* t, const C2<T>* __restrict__ 
   for (int i = tid; i < nh + nl; i += nthr) t[i] = i < nh ? tw[nh + i] : tw[(1 << L) + i - nh];
 }
 
+// Stages the four-step twiddle tables of InterTw: hi[q] = e^{-2 pi i q / N1}
+// (level N1 of the pyramid) and lo[r] = e^{-2 pi i r / N} for r < N2 (one
+// entry per thread when the block covers both).
 template <class T>
 __device__ __forceinline__ void stage_inter(C2<T>* hi, C2<T>* lo, const C2<T>* __restrict__ tw, int N, int N1,
                                             int N2, int tid, int nthr) {
+  if (N1 + N2 <= nthr) {
+    if (tid < N1) hi[tid] = tw[N1 + tid];
+    else if (tid < N1 + N2) lo[tid - N1] = tw[N + tid - N1];
+    return;
+  }
   for (int b = tid; b < N1 + N2; b += 8 * nthr) {
     C2<T> v[8];
 #pragma unroll
