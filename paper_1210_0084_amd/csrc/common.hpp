@@ -84,8 +84,12 @@ struct alignas(16) RingCopy {
 // (adjoint). The first two entries of bin j sit in one record, ola_syn[j] or
 // ola_adj[j] (weight 0 and x = 0 for a missing entry); any further entries
 // are ent_off[j] .. ent_off[j+1]-1 of ent_pos (pairs x, y) and ent_w*.
+// Entries of the radix-8 twiddle rows of the band FFTs (passes at Ns = 8 and
+// Ns = 64, seven rows each).
+constexpr int kPow8Entries = 7 * 8 + 7 * 64;
+
 struct TableLayout {
-  uint64_t tw, h0, hd, g, gd, bands, ana, syn, runs;
+  uint64_t tw, tw8, h0, hd, g, gd, bands, ana, syn, runs;
   uint64_t ola_syn, ola_adj, ent_off, ent_pos, ent_wsyn, ent_wadj, total;
 };
 

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "common.hpp"
+
 namespace slicq {
 
 template <class T>
@@ -146,23 +148,45 @@ struct TwLds {
   __device__ __forceinline__ C2<T> get(int n, int k) const { return tw[(n >> 1) - 1 + k]; }
 };
 
-// e^{-2 pi i k / n} for n = 2^l <= 2^L from two small LDS tables: with
-// m = k 2^(L - l) = hi 2^(L/2) + lo, the product of e^{-2 pi i hi / 2^(L - L/2)}
-// (t[hi]) and e^{-2 pi i lo / 2^L} (t[2^(L - L/2) + lo]); 2^(L - L/2) + 2^(L/2)
-// entries instead of every level up to 2^L (error within one more rounding).
-template <class T>
-struct TwSplit {
+// Twiddles of the band FFTs, from small LDS tables. get(n, k) gives
+// e^{-2 pi i k / n} for n = 2^l <= 2^L as a product: with
+// m = k 2^(L - l) = hi 2^(L/2) + lo, it is e^{-2 pi i hi / 2^(L - L/2)} (t[hi])
+// times e^{-2 pi i lo / 2^L} (t[2^(L - L/2) + lo]). That needs 2^(L - L/2) +
+// 2^(L/2) entries instead of every level up to 2^L, with the error of one
+// more rounding.
+// With P8, the radix-8 passes at Ns = 8 and Ns = 64 read their seven powers
+// directly instead (pow8): row r = 1..7 of pass Ns holds
+// e^{-2 pi i r k / (8 Ns)}, for k < Ns, contiguous in k (p8: the Ns = 8 rows,
+// then the Ns = 64 rows). That saves the index arithmetic and products, and
+// costs kPow8Entries more entries to stage.
+template <class T, bool P8>
+struct TwBand {
   const C2<T>* t;
   int L;
+  const C2<T>* p8;
+  static constexpr bool kPow8 = P8;
   __device__ __forceinline__ C2<T> get(int n, int k) const {
     const int LL = L >> 1;
     const int m = k << (L - (31 - __builtin_clz((unsigned)n)));
     return cmul(t[m >> LL], t[(1 << (L - LL)) + (m & ((1 << LL) - 1))]);
   }
+  template <int DIR, int NS>
+  __device__ __forceinline__ void pow8(int k, C2<T>* w) const {
+    const C2<T>* row = p8 + (NS == 8 ? 0 : 7 * 8) + k;
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      w[r] = row[(r - 1) * NS];
+      if constexpr (DIR > 0) w[r].y = -w[r].y;
+    }
+  }
 };
 
-// Entries of the TwSplit tables for transforms up to 2^L.
+// Entries of the TwBand tables for transforms up to 2^L (the split tables,
+// then, with P8, the radix-8 rows).
 __host__ __device__ constexpr int split_tw_entries(int L) { return (1 << (L - (L >> 1))) + (1 << (L >> 1)); }
+__host__ __device__ constexpr int band_tw_entries(int L, bool p8) {
+  return split_tw_entries(L) + (p8 ? kPow8Entries : 0);
+}
 
 // Four-step twiddles e^{DIR 2 pi i m / N}, 0 <= m < N = N1 N2, as the product
 // of e^{-2 pi i (m >> log N2) / N1} (hi, N1 entries) and e^{-2 pi i (m mod N2) / N}
@@ -215,6 +239,23 @@ __device__ __forceinline__ void twiddle_powers(const TW& src, int n, int k, C2<T
 #pragma unroll
     for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
   }
+}
+
+// Twiddles w^1 .. w^(R-1) of a pass at Ns = NS (w = e^{DIR 2 pi i k / (NS R)}):
+// the direct radix-8 rows where the source has them, else twiddle_powers.
+template <class TW, class = void>
+struct HasPow8 {
+  static constexpr bool value = false;
+};
+template <class TW>
+struct HasPow8<TW, decltype((void)TW::kPow8)> {
+  static constexpr bool value = TW::kPow8;
+};
+
+template <class T, int DIR, int R, int NS, class TW>
+__device__ __forceinline__ void pass_twiddles(const TW& src, int k, C2<T>* w) {
+  if constexpr (R == 8 && (NS == 8 || NS == 64) && HasPow8<TW>::value) src.template pow8<DIR, NS>(k, w);
+  else twiddle_powers<T, DIR, R>(src, NS * R, k, w);
 }
 
 // Batch layouts of `nseq` sequences of length n in LDS (padded indices):
@@ -356,7 +397,7 @@ __device__ __forceinline__ void stockham_pass_c(C2<T>* buf, int base, int nseq, 
       if constexpr (NS > 1) {
         const int u = imin(tid + i * nthr, total - 1);
         C2<T> w[R];
-        twiddle_powers<T, DIR, R>(tws, NS * R, u & (NS - 1), w);
+        pass_twiddles<T, DIR, R, NS>(tws, u & (NS - 1), w);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
       }

@@ -60,6 +60,7 @@ constexpr int64_t kMaxSignalElems = 0x7fffffffLL;
 template <class T>
 struct KArgs {
   const C2<T>* tw;        // twiddle pyramid
+  const C2<T>* tw8;       // radix-8 twiddle rows of the band FFTs (TwBand)
   const T* h0;            // analysis slice window (2N)
   const T* hsyn;          // synthesis slice window: h~_0 (synthesis) or h_0 (adjoint)
   const T* g;             // analysis band windows
@@ -359,11 +360,19 @@ __device__ __forceinline__ void stage_twiddles(C2<T>* twl, const C2<T>* __restri
   }
 }
 
-// The TwSplit tables for transforms up to 2^L: hi levels first, then lo.
-template <class T>
-__device__ __forceinline__ void stage_split(C2<T>* t, const C2<T>* __restrict__ tw, int L, int tid, int nthr) {
-  const int nh = 1 << (L - (L >> 1)), nl = 1 << (L >> 1);
-  for (int i = tid; i < nh + nl; i += nthr) t[i] = i < nh ? tw[nh + i] : tw[(1 << L) + i - nh];
+// The TwBand tables for transforms up to 2^L: split hi levels, split lo
+// levels, then (P8) the radix-8 rows.
+template <bool P8, class T>
+__device__ __forceinline__ void stage_band(C2<T>* t, const C2<T>* __restrict__ tw, const C2<T>* __restrict__ tw8,
+                                           int L, int tid, int nthr) {
+  const int nh = 1 << (L - (L >> 1)), nl = 1 << (L >> 1), ns = nh + nl;
+  for (int i = tid; i < band_tw_entries(L, P8); i += nthr)
+    t[i] = i < nh ? tw[nh + i] : i < ns ? tw[(1 << L) + i - nh] : tw8[i - ns];
+}
+
+template <bool P8, class T>
+__device__ __forceinline__ TwBand<T, P8> band_tw(const C2<T>* t, int L) {
+  return TwBand<T, P8>{t, L, t + split_tw_entries(L)};
 }
 
 // Stages the four-step twiddle tables of InterTw: hi[q] = e^{-2 pi i q / N1}
@@ -491,7 +500,7 @@ __device__ __forceinline__ void band_ana_fft(const KArgs<T>& a, const SliceTask&
     for (int i = 0; i < UL; ++i) {
       const int u = imin(tid + i * nthr, unitsL - 1);
       C2<T> w[RL];
-      twiddle_powers<T, 1, RL>(tws, NS * RL, u & (NS - 1), w);
+      pass_twiddles<T, 1, RL, NS>(tws, u & (NS - 1), w);
 #pragma unroll
       for (int r = 1; r < RL; ++r) q[i][r] = cmul(q[i][r], w[r]);
       dft_reg<T, RL, 1>(q[i]);
@@ -514,7 +523,7 @@ __device__ __forceinline__ void band_ana_fft(const KArgs<T>& a, const SliceTask&
 // inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff). Bins
 // outside [0, N] read the half spectrum by conjugate symmetry.
 // Block b takes work item g0 + b mod ng of task b / ng. TWL stages the
-// twiddles of lengths up to M in LDS, otherwise the two TwSplit tables.
+// twiddles of lengths up to M in LDS, otherwise the TwBand tables.
 // LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
@@ -529,14 +538,14 @@ k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
   const int tid = threadIdx.x, nthr = blockDim.x;
   C2<T>* twl = reinterpret_cast<C2<T>*>(smem + lds_tail_offset<T>(G.cnt << G.logM));
   if constexpr (TWL) stage_twiddles(twl, a.tw, G.M, tid, nthr);
-  else stage_split(twl, a.tw, G.logM, tid, nthr);
+  else stage_band<false>(twl, a.tw, a.tw8, G.logM, tid, nthr);   // the radix-8 rows cost more than they save here
   const C2<T>* __restrict__ X = W2 + (int64_t)task * a.ws2;
   C2<T>* __restrict__ cs = coef + tk.coef_base;
   const TwLds<T> tws{twl};
 #define SLICQ_ANA_CASE(L)                                                                  \
   case L:                                                                                  \
     if constexpr (TWL) band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, tws, tid, nthr);        \
-    else band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, TwSplit<T>{twl, L}, tid, nthr);       \
+    else band_ana_fft<T, E, L>(a, tk, G, X, cs, buf, band_tw<false>(twl, L), tid, nthr);   \
     break;
   switch (G.logM) {
     SLICQ_ANA_CASE(1) SLICQ_ANA_CASE(2) SLICQ_ANA_CASE(3) SLICQ_ANA_CASE(4) SLICQ_ANA_CASE(5)
@@ -544,7 +553,7 @@ k_band_ana(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
     SLICQ_ANA_CASE(11) SLICQ_ANA_CASE(12)
     default:
       if constexpr (TWL) band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, tws, tid, nthr);
-      else band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, TwSplit<T>{twl, 13}, tid, nthr);
+      else band_ana_fft<T, E, 13>(a, tk, G, X, cs, buf, band_tw<false>(twl, 13), tid, nthr);
       break;
   }
 #undef SLICQ_ANA_CASE
@@ -564,7 +573,7 @@ __device__ __forceinline__ int run_coef_index(const SliceTask& tk, const SynRunD
 // Nyquist bands weight * (C[j mod M] + conj C[-j mod M]), the real part of the
 // full synthesis). Block b takes work item g0 + b mod ng of task b / ng; item
 // TWL stages the twiddles of
-// lengths up to the item's largest M in LDS, otherwise the two TwSplit tables.
+// lengths up to the item's largest M in LDS, otherwise the TwBand tables.
 // LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
@@ -606,7 +615,7 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       }
       if (i == 0) {
         if constexpr (TWL) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
-        else stage_split(twl, a.tw, Lmax, tid, nthr);
+        else stage_band<true>(twl, a.tw, a.tw8, Lmax, tid, nthr);
       }
       if (live) {
         dft_reg<T, 8, -1>(v);
@@ -628,7 +637,7 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       int t = tid;
       asm volatile("" : "+v"(t));
       if constexpr (TWL) lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, t, nthr);
-      else lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, TwSplit<T>{twl, Lmax}, t, nthr);
+      else lds_fft_contig_after8<T, -1, E>(buf, R.lds_off, R.logM, R.cnt, band_tw<true>(twl, Lmax), t, nthr);
     }
   } else {
     // coefficient addresses of a batch of values (no branches), then every load
@@ -660,7 +669,7 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       for (int i = 0; i < EB; ++i) v[i] = cs[idx[i]];
       if (c == 0) {
         if constexpr (TWL) stage_twiddles(twl, a.tw, G.maxM, tid, nthr);
-        else stage_split(twl, a.tw, Lmax, tid, nthr);
+        else stage_band<true>(twl, a.tw, a.tw8, Lmax, tid, nthr);
       }
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
@@ -677,7 +686,7 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       int t = tid;
       asm volatile("" : "+v"(t));
       if constexpr (TWL) lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwLds<T>{twl}, t, nthr);
-      else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, TwSplit<T>{twl, Lmax}, t, nthr);
+      else lds_fft_contig<T, -1, E, 8>(buf, R.lds_off, R.logM, R.cnt, band_tw<true>(twl, Lmax), t, nthr);
     }
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;
@@ -692,9 +701,9 @@ k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restr
       if (j >= G.hi) continue;
       const uint32_t y0 = rec[q].yy & kOlaNone, y1 = rec[q].yy >> 16;
       C2<T> c0 = buf[pidx(rec[q].xx & kOlaPosMask)], c1 = buf[pidx(rec[q].xx >> 16)];
-      const C2<T> m0 = buf[pidx(y0 == kOlaNone ? 0 : y0)], m1 = buf[pidx(y1 == kOlaNone ? 0 : y1)];
-      if (y0 != kOlaNone) c0 = cadd(c0, cconj(m0));
-      if (y1 != kOlaNone) c1 = cadd(c1, cconj(m1));
+      // mirror entries only in the bins of the DC and Nyquist bands
+      if (y0 != kOlaNone) c0 = cadd(c0, cconj(buf[pidx(y0)]));
+      if (y1 != kOlaNone) c1 = cadd(c1, cconj(buf[pidx(y1)]));
       C2<T> acc = cadd(cscale(c0, rec[q].w0), cscale(c1, rec[q].w1));
       if (rec[q].xx & kOlaMore) {                 // bins covered by more than two bands
         for (int e = a.ent_off[j]; e < a.ent_off[j + 1]; ++e) {

@@ -79,6 +79,7 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
   a.syn = reinterpret_cast<const SynGroupDev*>(base + L.syn);
   a.runs = reinterpret_cast<const SynRunDev*>(base + L.runs);
   a.ola2 = reinterpret_cast<const OlaRec<T>*>(base + (adjoint ? L.ola_adj : L.ola_syn));
+  a.tw8 = reinterpret_cast<const C2<T>*>(base + L.tw8);
   a.ent_off = reinterpret_cast<const int32_t*>(base + L.ent_off);
   a.ent_pos = reinterpret_cast<const int2*>(base + L.ent_pos);
   a.ent_w = reinterpret_cast<const T*>(base + (adjoint ? L.ent_wadj : L.ent_wsyn));
@@ -109,8 +110,8 @@ struct Geometry {
   int g2, b2; size_t s2;      // forward pass 2 / inverse pass A
   // band analysis: small items [0, ga) with ba threads, E = kSmallE (kernel
   // bound kAnaThreads); large items [ga, ga + gab) with bab threads,
-  // E = kBigAnaE (bound kAnaBigThreads). Items stage two small twiddle tables
-  // (TwSplit) in LDS; every level up to M (tab, tsb) only for large items and
+  // E = kBigAnaE (bound kAnaBigThreads). Items stage small twiddle tables
+  // (TwBand) in LDS; every level up to M (tab, tsb) only for large items and
   // only where that costs no resident block per CU.
   int ga, ba; size_t sa;
   int gab, bab; size_t sab; bool tab;
@@ -133,10 +134,10 @@ template <class T>
 Geometry<T> geometry(const Plan& p) {
   Geometry<T> g{};
   const size_t cb = sizeof(C2<T>);
-  auto split_bytes = [&](int32_t maxM) {   // TwSplit tables for lengths up to maxM
+  auto split_bytes = [&](int32_t maxM, bool p8) {   // TwBand tables for lengths up to maxM
     int L = 0;
     while ((1 << L) < maxM) ++L;
-    return (size_t)split_tw_entries(L) * cb;
+    return (size_t)band_tw_entries(L, p8) * cb;
   };
   g.g1 = p.N1 / p.C;
   g.b1 = threads_for((int64_t)p.C * p.N2, kPassE);
@@ -146,24 +147,24 @@ Geometry<T> geometry(const Plan& p) {
   g.s2 = (padded(2 * p.P * p.N1) + p.N1 + p.N1 + p.N2) * cb;   // values, FFT twiddles, four-step tables
   g.ga = p.ana_small;
   g.ba = threads_for(std::max(p.ana_cap_small, 1), kSmallE);
-  g.sa = lds_tail_offset<T>(p.ana_cap_small) + split_bytes(p.ana_maxM_small);
+  g.sa = lds_tail_offset<T>(p.ana_cap_small) + split_bytes(p.ana_maxM_small, false);
   g.gab = (int)p.ana.size() - p.ana_small;
   g.bab = threads_for(std::max(p.ana_cap_big, 1), kBigAnaE);
   g.sab = lds_tail_offset<T>(p.ana_cap_big);
   int32_t big_ana_M = 0;
   for (int i = p.ana_small; i < (int)p.ana.size(); ++i) big_ana_M = std::max(big_ana_M, p.ana[i].M);
   g.tab = lds_twiddles_pay(g.sab, (size_t)big_ana_M * cb);
-  g.sab += g.tab ? (size_t)big_ana_M * cb : split_bytes(big_ana_M);
+  g.sab += g.tab ? (size_t)big_ana_M * cb : split_bytes(big_ana_M, false);
   g.gs = p.syn_small;
   g.bs = threads_for(std::max(p.syn_cap_small, 1), kSmallE);
-  g.ss = lds_tail_offset<T>(p.syn_cap_small) + split_bytes(p.syn_maxM_small);
+  g.ss = lds_tail_offset<T>(p.syn_cap_small) + split_bytes(p.syn_maxM_small, true);
   g.gsb = (int)p.syn.size() - p.syn_small;
   g.bsb = threads_for(std::max(p.syn_cap_big, 1), kBigSynE);
   g.ssb = lds_tail_offset<T>(p.syn_cap_big);
   int32_t big_maxM = 0;
   for (int i = p.syn_small; i < (int)p.syn.size(); ++i) big_maxM = std::max(big_maxM, p.syn[i].maxM);
   g.tsb = lds_twiddles_pay(g.ssb, (size_t)big_maxM * cb);
-  g.ssb += g.tsb ? (size_t)big_maxM * cb : split_bytes(big_maxM);
+  g.ssb += g.tsb ? (size_t)big_maxM * cb : split_bytes(big_maxM, true);
   size_t lds = std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss));
   if (g.gab) lds = std::max(lds, g.sab);
   if (g.gsb) lds = std::max(lds, g.ssb);

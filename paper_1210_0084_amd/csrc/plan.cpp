@@ -512,6 +512,16 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
       tw[2 * (n + k) + 1] = s;
     }
   }
+  // radix-8 rows of the band FFTs: row r of pass Ns holds e^{-2 pi i r k / (8 Ns)}
+  // (entry r k of pyramid level 8 Ns), k < Ns
+  std::vector<double> tw8;
+  for (int64_t ns : {8, 64})
+    for (int64_t r = 1; r < 8; ++r)
+      for (int64_t k = 0; k < ns; ++k) {
+        const int64_t e = 8 * ns + r * k;
+        tw8.push_back(8 * ns <= two_n ? tw[2 * e] : 1.0);
+        tw8.push_back(8 * ns <= two_n ? tw[2 * e + 1] : 0.0);
+      }
   std::vector<BandDev> bd;
   for (const BandInfo& b : p.bands) {
     BandDev d{};
@@ -533,12 +543,15 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
     };
     std::vector<float> twf = cvt(tw), h0 = cvt(p.h0), hd = cvt(p.hd), g = cvt(p.g), gd = cvt(p.gd);
     lay.tw = append(blob, twf.data(), twf.size());
+    const std::vector<float> tw8f = cvt(tw8);
+    lay.tw8 = append(blob, tw8f.data(), tw8f.size());
     lay.h0 = append(blob, h0.data(), h0.size());
     lay.hd = append(blob, hd.data(), hd.size());
     lay.g = append(blob, g.data(), g.size());
     lay.gd = append(blob, gd.data(), gd.size());
   } else {
     lay.tw = append(blob, tw.data(), tw.size());
+    lay.tw8 = append(blob, tw8.data(), tw8.size());
     lay.h0 = append(blob, p.h0.data(), p.h0.size());
     lay.hd = append(blob, p.hd.data(), p.hd.size());
     lay.g = append(blob, p.g.data(), p.g.size());
