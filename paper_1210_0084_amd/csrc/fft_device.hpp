@@ -367,8 +367,16 @@ __device__ __forceinline__ void lds_fft(C2<T>* buf, int base, int logn, int nseq
 // the pad run the pad count grows by S >> kPadShift per step.
 template <int S>
 __device__ __forceinline__ int pidx_step(int pb, int p0, int r) {
-  if constexpr (S % (1 << kPadShift) == 0) return pb + r * (S + (S >> kPadShift));
-  else return pidx(p0 + r * S);
+  if constexpr (S % (1 << kPadShift) == 0) {
+    return pb + r * (S + (S >> kPadShift));
+  } else if constexpr (S == (1 << kPadShift) / 2) {
+    // half a pad run: the pad count grows by (r + c) / 2 with c the bit of p0
+    // below the run length, so even r sit at constant offsets from pb and odd
+    // r at constant offsets from pb + c
+    return pb + r * S + (r >> 1) + ((r & 1) ? ((p0 >> (kPadShift - 1)) & 1) : 0);
+  } else {
+    return pidx(p0 + r * S);
+  }
 }
 
 // SKIP: waves without a unit branch around the reads and the arithmetic (for
@@ -392,12 +400,26 @@ __device__ __forceinline__ void stockham_pass_c(C2<T>* buf, int base, int nseq, 
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = buf[pidx_step<SREAD>(pb, p0, r)];
     }
+    // a thread's units lie nthr apart: with nthr a multiple of NS they share
+    // the twiddle index, so the powers are computed once (lanes past the end
+    // are clamped and never written back)
+    const bool share = U > 1 && (nthr & (NS - 1)) == 0;
+    C2<T> w0[R];
 #pragma unroll
     for (int i = 0; i < U; ++i) {
       if constexpr (NS > 1) {
-        const int u = imin(tid + i * nthr, total - 1);
         C2<T> w[R];
-        pass_twiddles<T, DIR, R, NS>(tws, u & (NS - 1), w);
+        if (i > 0 && share) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) w[r] = w0[r];
+        } else {
+          const int u = imin(tid + i * nthr, total - 1);
+          pass_twiddles<T, DIR, R, NS>(tws, u & (NS - 1), w);
+          if (i == 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) w0[r] = w[r];
+          }
+        }
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
       }
