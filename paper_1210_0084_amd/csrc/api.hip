@@ -64,6 +64,13 @@ struct HipLaunch {
     if (shmem > 65536) allow_lds(reinterpret_cast<const void*>(kernel), shmem);
     hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3((unsigned)block), shmem, st, args...);
   }
+  // gx x gy blocks (gy <= 65535)
+  template <class K, class... A>
+  void launch_xy(K kernel, int64_t gx, int gy, int block, size_t shmem, A... args) {
+    if (gx <= 0 || gy <= 0) return;
+    if (shmem > 65536) allow_lds(reinterpret_cast<const void*>(kernel), shmem);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)gx, (unsigned)gy), dim3((unsigned)block), shmem, st, args...);
+  }
 };
 
 int check_geometry(const slicq::Plan& p, int dt);
@@ -220,6 +227,11 @@ struct HipBackend {
   void launch(K kernel, int64_t grid, int block, size_t shmem, A... args) {
     HipLaunch L{st};
     L.launch(kernel, grid, block, shmem, args...);
+  }
+  template <class K, class... A>
+  void launch_xy(K kernel, int64_t gx, int gy, int block, size_t shmem, A... args) {
+    HipLaunch L{st};
+    L.launch_xy(kernel, gx, gy, block, shmem, args...);
   }
   bool sync() { return hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess; }
 };

@@ -522,7 +522,8 @@ __device__ __forceinline__ void band_ana_fft(const KArgs<T>& a, const SliceTask&
 // holds X[j] g_k[j] for the bin j of J_k with j = r (mod M_k), or 0; the
 // inverse DFT of length M_k gives c^m_{n,k} (equation CQ_coeff). Bins
 // outside [0, N] read the half spectrum by conjugate symmetry.
-// Block b takes work item g0 + b mod ng of task b / ng. TWL stages the
+// Block b takes work item g0 + b mod ng of task b / ng (the items of one
+// slice run together: their spectrum reads overlap). TWL stages the
 // twiddles of lengths up to M in LDS, otherwise the TwBand tables.
 // LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
@@ -571,17 +572,17 @@ __device__ __forceinline__ int run_coef_index(const SliceTask& tk, const SynRunD
 // owned bin runs its overlap-add program: the sum over the bands covering it,
 // in increasing k, of weight * C_k[j mod M_k] (for the self-mirrored DC and
 // Nyquist bands weight * (C[j mod M] + conj C[-j mod M]), the real part of the
-// full synthesis). Block b takes work item g0 + b mod ng of task b / ng; item
-// TWL stages the twiddles of
-// lengths up to the item's largest M in LDS, otherwise the TwBand tables.
-// LDS: values (padded) | twiddles.
+// full synthesis). Block (x, y) takes work item g0 + y of task x (one item of
+// consecutive slices runs together: they read the same overlap-add records
+// and twiddles). TWL stages the twiddles of lengths up to the item's largest
+// M in LDS, otherwise the TwBand tables. LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ coef, C2<T>* __restrict__ W2,
            T* __restrict__ y, int g0, int ng) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  const int task = blockIdx.x / ng, gi = g0 + (int)blockIdx.x - task * ng;
+  const int task = blockIdx.x, gi = g0 + (int)blockIdx.y;
   const SynGroupDev G = a.syn[gi];
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;

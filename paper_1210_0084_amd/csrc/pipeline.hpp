@@ -174,7 +174,7 @@ Geometry<T> geometry(const Plan& p) {
          (g.gab == 0 || (g.bab <= kAnaBigThreads && p.ana_cap_big <= kBigAnaE * g.bab)) &&
          g.bs <= kSynThreads && p.syn_cap_small <= kSmallE * g.bs &&
          (g.gsb == 0 || (g.bsb <= kSynBigThreads && p.syn_cap_big <= kBigSynE * g.bsb)) &&
-         lds <= kMaxLdsBytes;
+         g.gs + g.gsb <= 65535 && lds <= kMaxLdsBytes;   // synthesis items per slice: grid y
   return g;
 }
 
@@ -182,10 +182,16 @@ Geometry<T> geometry(const Plan& p) {
 template <class T, class Launch>
 void launch_band_ana(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
                      const C2<T>* W2, C2<T>* coef, Launch& L) {
-  if (g.ga) L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, false>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0, g.ga);
+  if (g.ga)
+    L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, false>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0,
+             g.ga);
   if (g.gab) {
-    if (g.tab) L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, true>, cnt * g.gab, g.bab, g.sab, a, tasks, W2, coef, g.ga, g.gab);
-    else L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, false>, cnt * g.gab, g.bab, g.sab, a, tasks, W2, coef, g.ga, g.gab);
+    if (g.tab)
+      L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, true>, cnt * g.gab, g.bab, g.sab, a, tasks, W2,
+               coef, g.ga, g.gab);
+    else
+      L.launch(k_band_ana<T, kBigAnaE, kAnaBigThreads, kSmallWaves, false>, cnt * g.gab, g.bab, g.sab, a, tasks, W2,
+               coef, g.ga, g.gab);
   }
 }
 
@@ -193,10 +199,16 @@ void launch_band_ana(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* t
 template <class T, class Launch>
 void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
                      const C2<T>* coef, C2<T>* W2, T* y, Launch& L) {
-  if (g.gs) L.launch(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, cnt * g.gs, g.bs, g.ss, a, tasks, coef, W2, y, 0, g.gs);
+  if (g.gs)
+    L.launch_xy(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, cnt, g.gs, g.bs, g.ss, a, tasks, coef, W2,
+                y, 0, g.gs);
   if (g.gsb) {
-    if (g.tsb) L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, true>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
-    else L.launch(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt * g.gsb, g.bsb, g.ssb, a, tasks, coef, W2, y, g.gs, g.gsb);
+    if (g.tsb)
+      L.launch_xy(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, true>, cnt, g.gsb, g.bsb, g.ssb, a, tasks, coef,
+                  W2, y, g.gs, g.gsb);
+    else
+      L.launch_xy(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt, g.gsb, g.bsb, g.ssb, a, tasks, coef,
+                  W2, y, g.gs, g.gsb);
   }
 }
 

@@ -32,12 +32,16 @@ namespace {
 struct EmuLaunch {
   template <class K, class... A>
   void launch(K kernel, int64_t grid, int block, size_t shmem, A... args) {
-    if (grid <= 0) return;
+    launch_xy(kernel, grid, 1, block, shmem, args...);
+  }
+  template <class K, class... A>
+  void launch_xy(K kernel, int64_t gx, int gy, int block, size_t shmem, A... args) {
+    if (gx <= 0 || gy <= 0) return;
     if (shmem > slicq::EMU_LDS || block <= 0 || block > 1024) {
       std::fprintf(stderr, "bad launch: block %d shmem %zu\n", block, shmem);
       std::exit(3);
     }
-    for (int64_t b = 0; b < grid; ++b) {
+    for (int64_t b = 0; b < gx * gy; ++b) {
       std::memset(slicq::smem, 0xff, slicq::EMU_LDS);
       std::barrier<> bar(block);
       std::vector<std::thread> th;
@@ -45,7 +49,7 @@ struct EmuLaunch {
       for (int t = 0; t < block; ++t) {
         th.emplace_back([&, t] {
           threadIdx = dim3((unsigned)t);
-          blockIdx = dim3((unsigned)b);
+          blockIdx = dim3((unsigned)(b % gx), (unsigned)(b / gx));
           blockDim = dim3((unsigned)block);
           emu_barrier = &bar;
           kernel(args...);
