@@ -64,12 +64,13 @@ struct HipLaunch {
     if (shmem > 65536) allow_lds(reinterpret_cast<const void*>(kernel), shmem);
     hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3((unsigned)block), shmem, st, args...);
   }
-  // gx x gy blocks (gy <= 65535)
+  // gx x gy x gz blocks (gy, gz <= 65535)
   template <class K, class... A>
-  void launch_xy(K kernel, int64_t gx, int gy, int block, size_t shmem, A... args) {
-    if (gx <= 0 || gy <= 0) return;
+  void launch_xyz(K kernel, int64_t gx, int gy, int gz, int block, size_t shmem, A... args) {
+    if (gx <= 0 || gy <= 0 || gz <= 0) return;
     if (shmem > 65536) allow_lds(reinterpret_cast<const void*>(kernel), shmem);
-    hipLaunchKernelGGL(kernel, dim3((unsigned)gx, (unsigned)gy), dim3((unsigned)block), shmem, st, args...);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3((unsigned)block), shmem, st,
+                       args...);
   }
 };
 
@@ -229,9 +230,9 @@ struct HipBackend {
     L.launch(kernel, grid, block, shmem, args...);
   }
   template <class K, class... A>
-  void launch_xy(K kernel, int64_t gx, int gy, int block, size_t shmem, A... args) {
+  void launch_xyz(K kernel, int64_t gx, int gy, int gz, int block, size_t shmem, A... args) {
     HipLaunch L{st};
-    L.launch_xy(kernel, gx, gy, block, shmem, args...);
+    L.launch_xyz(kernel, gx, gy, gz, block, shmem, args...);
   }
   bool sync() { return hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess; }
 };

@@ -572,17 +572,19 @@ __device__ __forceinline__ int run_coef_index(const SliceTask& tk, const SynRunD
 // owned bin runs its overlap-add program: the sum over the bands covering it,
 // in increasing k, of weight * C_k[j mod M_k] (for the self-mirrored DC and
 // Nyquist bands weight * (C[j mod M] + conj C[-j mod M]), the real part of the
-// full synthesis). Block (x, y) takes work item g0 + y of task x (one item of
-// consecutive slices runs together: they read the same overlap-add records
-// and twiddles). TWL stages the twiddles of lengths up to the item's largest
+// full synthesis). Block (x, y, z) takes work item g0 + y of task
+// z gridDim.x + x: one item of a tile of consecutive slices runs together
+// (they read the same overlap-add records and twiddles; tiles keep the band
+// an item shares with its neighbour in cache until the neighbour reads it). TWL stages the twiddles of lengths up to the item's largest
 // M in LDS, otherwise the TwBand tables. LDS: values (padded) | twiddles.
 template <class T, int E, int NT, int WPE, bool TWL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_band_syn(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __restrict__ coef, C2<T>* __restrict__ W2,
-           T* __restrict__ y, int g0, int ng) {
+           T* __restrict__ y, int g0, int ntask) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  const int task = blockIdx.x, gi = g0 + (int)blockIdx.y;
+  const int task = (int)(blockIdx.z * gridDim.x + blockIdx.x), gi = g0 + (int)blockIdx.y;
+  if (task >= ntask) return;                   // padding of the last tile
   const SynGroupDev G = a.syn[gi];
   const SliceTask tk = tasks[task];
   if (tk.S == 0) return;

@@ -195,20 +195,27 @@ void launch_band_ana(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* t
   }
 }
 
-// Band synthesis (dual or adjoint) of cnt tasks: one launch per work-item class.
+// Band synthesis (dual or adjoint) of cnt tasks: one launch per work-item
+// class, on a grid of (slices of a tile, items, tiles); balanced tiles of at
+// most kSynTile slices (more when 65535 tiles do not cover cnt).
+constexpr int64_t kSynTile = 128;
+
 template <class T, class Launch>
 void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
                      const C2<T>* coef, C2<T>* W2, T* y, Launch& L) {
+  const int64_t tiles = std::min<int64_t>((cnt + kSynTile - 1) / kSynTile, 65535);
+  const int64_t tx = tiles ? (cnt + tiles - 1) / tiles : 0;
+  const int n = (int)cnt;
   if (g.gs)
-    L.launch_xy(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, cnt, g.gs, g.bs, g.ss, a, tasks, coef, W2,
-                y, 0, g.gs);
+    L.launch_xyz(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, tx, g.gs, (int)tiles, g.bs, g.ss, a,
+                 tasks, coef, W2, y, 0, n);
   if (g.gsb) {
     if (g.tsb)
-      L.launch_xy(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, true>, cnt, g.gsb, g.bsb, g.ssb, a, tasks, coef,
-                  W2, y, g.gs, g.gsb);
+      L.launch_xyz(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, true>, tx, g.gsb, (int)tiles, g.bsb, g.ssb, a,
+                   tasks, coef, W2, y, g.gs, n);
     else
-      L.launch_xy(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, cnt, g.gsb, g.bsb, g.ssb, a, tasks, coef,
-                  W2, y, g.gs, g.gsb);
+      L.launch_xyz(k_band_syn<T, kBigSynE, kSynBigThreads, kSmallWaves, false>, tx, g.gsb, (int)tiles, g.bsb, g.ssb, a,
+                   tasks, coef, W2, y, g.gs, n);
   }
 }
 

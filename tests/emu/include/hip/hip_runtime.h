@@ -25,7 +25,7 @@ struct dim3 {
   dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
 
-extern thread_local dim3 threadIdx, blockIdx, blockDim;
+extern thread_local dim3 threadIdx, blockIdx, blockDim, gridDim;
 extern thread_local std::barrier<>* emu_barrier;
 
 inline void __syncthreads() { emu_barrier->arrive_and_wait(); }

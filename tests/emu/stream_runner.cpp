@@ -20,7 +20,7 @@
 
 #include "stream_server.hpp"
 
-thread_local dim3 threadIdx, blockIdx, blockDim;
+thread_local dim3 threadIdx, blockIdx, blockDim, gridDim;
 thread_local std::barrier<>* emu_barrier = nullptr;
 
 namespace slicq {
@@ -39,21 +39,22 @@ struct EmuBackend {
   void d2h(void* h, const void* d, size_t n) { std::memcpy(h, d, n); }
   template <class K, class... A>
   void launch(K kernel, int64_t grid, int block, size_t shmem, A... args) {
-    launch_xy(kernel, grid, 1, block, shmem, args...);
+    launch_xyz(kernel, grid, 1, 1, block, shmem, args...);
   }
   template <class K, class... A>
-  void launch_xy(K kernel, int64_t gx, int gy, int block, size_t shmem, A... args) {
-    if (gx <= 0 || gy <= 0) return;
+  void launch_xyz(K kernel, int64_t gx, int gy, int gz, int block, size_t shmem, A... args) {
+    if (gx <= 0 || gy <= 0 || gz <= 0) return;
     if (shmem > slicq::EMU_LDS || block <= 0 || block > 1024) std::exit(3);
-    for (int64_t b = 0; b < gx * gy; ++b) {
+    for (int64_t b = 0; b < gx * gy * gz; ++b) {
       std::memset(slicq::smem, 0xff, slicq::EMU_LDS);
       std::barrier<> bar(block);
       std::vector<std::thread> th;
       for (int t = 0; t < block; ++t) {
         th.emplace_back([&, t] {
           threadIdx = dim3((unsigned)t);
-          blockIdx = dim3((unsigned)(b % gx), (unsigned)(b / gx));
+          blockIdx = dim3((unsigned)(b % gx), (unsigned)(b / gx % gy), (unsigned)(b / (gx * gy)));
           blockDim = dim3((unsigned)block);
+          gridDim = dim3((unsigned)gx, (unsigned)gy, (unsigned)gz);
           emu_barrier = &bar;
           kernel(args...);
         });
