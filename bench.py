@@ -6,10 +6,17 @@ seeded pink noise plus harmonic tones), 48 bins per octave from 32.7 Hz to
 the analysis of both channels followed by their synthesis (one batched launch
 sequence each); inputs are resident in HBM before the timed region.
 
-Prints one JSON line: Msamples/s of audio (padding excluded), the roofline of
-the dominant kernel (algorithmic bytes per launch / HIP-event launch time
-against the 8 TB/s HBM peak), per-stage timings, and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+Prints one JSON line: Msamples/s of audio (padding excluded); the roofline
+of the dominant kernel, whose achieved rate counts only its share of the
+path's algorithmic bytes (the signal read once, the coefficients written once
+and read once, the output written once; every intermediate it moves is
+overhead and appears in `traffic`), against the 8 TB/s HBM peak and against a
+device copy timed in the same run; per-stage timings; sub-records for the
+batched (ragged batch in one HIP graph), differentiable (loss forward +
+adjoint backward) and streaming (p50/p99 slice latency) forms; and the FP64
+CPU oracle timed on the host: the 2^16-sample FP64 workload in CPU seconds,
+and a 10 s excerpt of the benchmark signal single-process and with a process
+pool over slices (median of 5 after a warm-up, core count and CPU model).
 """
 from __future__ import annotations
 
@@ -31,8 +38,9 @@ STAGES = ["fwd_pass1", "fwd_pass2", "band_ana", "band_syn", "inv_passA", "inv_pa
 
 
 def stage_bytes(plan, n_slices: int, b: int) -> dict:
-    """Algorithmic HBM bytes per launch of each kernel: what its interface must
-    read and write once (b = bytes per real value)."""
+    """Bytes each kernel's interface reads and writes once per launch (b =
+    bytes per real value): algorithmic bytes plus the intermediates the
+    pipeline passes between kernels."""
     N, M, cps = plan.N, plan.transition, plan.coefs_per_slice
     cb = 2 * b
     win = N + M - 1                         # non-zero samples of one slice window
@@ -45,6 +53,37 @@ def stage_bytes(plan, n_slices: int, b: int) -> dict:
         "inv_passB": cb * N + b * win,
     }
     return {k: v * n_slices for k, v in per.items()}
+
+
+def algorithmic_share(plan, n_slices: int, samples: int, b: int) -> dict:
+    """Each kernel's share of the path's algorithmic bytes: the signal read
+    once (slice pass 1), the coefficients written once (band analysis) and
+    read once (band synthesis), the output written once (inverse pass B with
+    its overlap fix-up). Intermediates (column FFTs, half spectra) count
+    nothing."""
+    c = 2 * b * n_slices * plan.coefs_per_slice
+    return {"fwd_pass1": b * samples, "fwd_pass2": 0, "band_ana": c, "band_syn": c, "inv_passA": 0,
+            "inv_passB": b * samples}
+
+
+def copy_rate(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Device-to-device copy of nbytes (read + write counted), GB/s: the
+    practical HBM ceiling measured in the same run."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def kernel_sources_hash() -> str:
@@ -92,28 +131,84 @@ def _stage_report(plan, n_slices, x, coef, y, reps, layout=None):
     return {k: {"ms": round(ms[k], 4), "GBs": round(sb[k] / (ms[k] * 1e-3) / 1e9, 1)} for k in STAGES}
 
 
-def cpu_baseline(prm, xs, seconds_target=15.0):
-    """The FP64 oracle (unchanged) on the first slices of the left channel."""
-    from oracle import OraclePlan, analyze, synthesize
-    opl = OraclePlan(prm["fs"], prm["fmin"], prm["fmax"], prm["bins_per_octave"], prm["slice_len"],
-                     prm["transition"])
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_POOL_STATE = {}
+
+
+def _pool_init(opl, x):
+    _POOL_STATE["opl"], _POOL_STATE["x"] = opl, x
+
+
+def _pool_slices(rng):
+    from oracle import analyze_slices, synthesize_slices
+    opl, x = _POOL_STATE["opl"], _POOL_STATE["x"]
+    c = analyze_slices(opl, x, rng[0], rng[1])
+    return synthesize_slices(opl, c, len(x), rng[0], rng[1])
+
+
+def _median_time(fn, runs=5):
+    fn()                                    # warm-up
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def cpu_baseline(xs):
+    """The FP64 oracle (unchanged) on the host cores: the 2^16-sample FP64
+    workload (analysis then synthesis, CPU seconds), and a 10 s excerpt of
+    the benchmark's left channel single-process and with a pool of processes
+    over its slices. Median of 5 runs after one warm-up each."""
+    import multiprocessing as mp
+    from oracle import OraclePlan, analyze, synthesize, num_slices
+    from workloads import make_c1
+    p1 = _preset("c1")
+    opl1 = OraclePlan(**p1)
+    x1 = make_c1()
+    t_c1 = _median_time(lambda: synthesize(opl1, analyze(opl1, x1), len(x1)))
+    prm = _preset("c2")
+    opl = OraclePlan(**prm)
     T = int(10 * prm["fs"])                 # a 10 s excerpt
     x = xs[0][:T].astype(np.float64)
-    t0 = time.perf_counter()
-    c = analyze(opl, x)
-    y = synthesize(opl, c, T)
-    dt = time.perf_counter() - t0
-    reps = 1
-    while dt * reps < seconds_target and reps < 8:
-        t0 = time.perf_counter()
-        c = analyze(opl, x)
-        y = synthesize(opl, c, T)
-        dt = min(dt, time.perf_counter() - t0)
-        reps += 1
-    err = float(np.abs(y - x).max())
-    return {"value": T / dt / 1e6, "unit": "Msamples/s", "cores": 1, "kind": "oracle",
-            "sample": f"analysis+synthesis of 10 s ({T} samples) of the left channel, FP64 numpy, "
-                      f"best of {reps}; reconstruction max error {err:.1e}"}
+    t_one = _median_time(lambda: synthesize(opl, analyze(opl, x), T))
+    err = float(np.abs(synthesize(opl, analyze(opl, x), T) - x).max())
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    procs = max(1, min(16, avail))          # the host's share for one GPU
+    S = num_slices(T, opl.two_n)
+    cuts = np.linspace(0, S, min(procs, S) + 1).astype(int)
+    ranges = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(len(ranges), initializer=_pool_init, initargs=(opl, x)) as pool:
+        def pooled():
+            return sum(pool.map(_pool_slices, ranges))[:T]
+        t_pool = _median_time(pooled)
+        perr = float(np.abs(pooled() - x).max())
+    rate = lambda n, t: n / t / 1e6
+    return {"value": round(rate(T, t_pool), 3), "unit": "Msamples/s", "cores": len(ranges), "kind": "oracle",
+            "sample": f"FP64 numpy oracle, analysis+synthesis of a 10 s excerpt ({T} samples, {S} slices) of the "
+                      f"benchmark's left channel, slices split over a pool of {len(ranges)} processes; median of 5 "
+                      f"after a warm-up; reconstruction max error {max(err, perr):.1e}",
+            "single_process": {"value": round(rate(T, t_one), 3), "unit": "Msamples/s", "cores": 1,
+                               "seconds": round(t_one, 4)},
+            "fp64_2p16_workload": {"seconds": round(t_c1, 4), "Msamples_per_s": round(rate(len(x1), t_c1), 3),
+                                   "cores": 1, "sample": "2^16 samples, B=12, 110-11025 Hz, 2N=8192, M=1024, "
+                                                         "analysis then synthesis"},
+            "nproc": os.cpu_count(), "cpu_affinity": avail, "cpu_model": _cpu_model()}
 
 
 def _events():
@@ -142,24 +237,31 @@ def _preset(name):
                 transition=p.transition)
 
 
-def bench_batched(args):
+def _frac(nbytes, ms, copy_gbs=None):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if copy_gbs:
+        out["frac_of_copy"] = round(gbs / copy_gbs, 4)
+    return out
+
+
+def bench_batched(args, copy_gbs=None):
     """Ragged batch of 256 signals (5-30 s): one graph launch of the batched
     calls, the same calls eagerly, and a loop of single-signal calls."""
     import torch
     import paper_1210_0084_amd as sq
-    from paper_1210_0084_amd.tuning import BatchGraph
-    from workloads import batch_lengths, pink_plus_tones
+    from paper_1210_0084_amd.tuning import BatchGraph, autotune
+    from workloads import make_c3_cut
     dev = torch.device("cuda:0")
     prm = _preset("c3")
-    # lengths as the ragged-batch generator draws them; content cut from one
-    # 60 s pink-plus-tones recording at random offsets (the time of the
-    # transform does not depend on the samples, generating 256 distinct
-    # recordings would take minutes of host time)
-    lens = [int(t) for t in batch_lengths(args.c3_signals, 44100.0, 4)]
-    base = pink_plus_tones(int(60 * 44100), 44100.0, 4_000_012).astype(np.float32)
-    g = np.random.default_rng(4)
-    offs0 = [int(g.integers(0, len(base) - t + 1)) for t in lens]
-    plan = sq.Plan(**prm)
+    lens, offs0, base = make_c3_cut(args.c3_signals)
+    base = base.astype(np.float32)
+    tuned = None
+    opts = {}
+    if args.c3_tune:
+        tuned = autotune(prm, lens, "f32", cache=args.tune_cache, reps=3)
+        opts = dict(tuned["options"])
+    plan = sq.Plan(**prm, **opts)
     lay = plan.batch_layout(lens)
     x = torch.tensor(np.concatenate([base[o:o + t] for o, t in zip(offs0, lens)]), device=dev)
     coef = torch.empty(lay.coef_len, dtype=torch.complex64, device=dev)
@@ -188,17 +290,18 @@ def bench_batched(args):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"ragged batch of {len(lens)} signals of 5-30 s (44.1 kHz), B=24, "
                                    "41.2-22050 Hz, 2N=32768, M=4096; analysis+synthesis in one HIP graph",
-                       "samples": samples, "slices": lay.total_slices},
-            "path": {"GBs": round(path_bytes / (ms_graph * 1e-3) / 1e9, 1),
-                     "frac": round(path_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "reconstruction_max_abs_err": err},
+                       "samples": samples, "slices": lay.total_slices, "options": opts or "defaults"},
+            "path": dict(_frac(path_bytes, ms_graph, copy_gbs), algorithmic_bytes=path_bytes,
+                         reconstruction_max_abs_err=err),
             "stages": stages,
+            "tuning": ({"chosen": tuned["options"], "ms": round(tuned["ms"], 4), "candidates": len(tuned["all"])}
+                       if tuned else None),
             "compare": {"graph_ms": round(ms_graph, 3), "eager_batched_ms": round(ms_eager, 3),
                         "per_signal_loop_ms": round(ms_loop, 3), "graph_Msps": rate(ms_graph),
                         "eager_Msps": rate(ms_eager), "loop_Msps": rate(ms_loop)}}
 
 
-def bench_differentiable(args):
+def bench_differentiable(args, copy_gbs=None):
     """Batch of 32 x 6 s: loss of the log-magnitude coefficients against a
     second batch, forward through SliCQFunction and backward through the
     adjoint kernel, beside the plain analysis + synthesis of the same batch."""
@@ -227,11 +330,16 @@ def bench_differentiable(args):
     yy = torch.empty_like(xf)
     ms_plain = _time(lambda: (plan.analyze_batched(xf, out=coef, layout=lay),
                               plan.synthesize_batched(coef, out=yy, layout=lay)), args.steps, args.warmup)
+    ms_ana = _time(lambda: plan.analyze_batched(xf, out=coef, layout=lay), args.steps, args.warmup)
     ms_adj = _time(lambda: plan.synthesize_batched(coef, out=yy, layout=lay, adjoint=True), args.steps, args.warmup)
     plan.analyze_batched(xf, out=coef, layout=lay)
     plan.synthesize_batched(coef, out=yy, layout=lay)
     stages = _stage_report(plan, lay.total_slices, xf, coef, yy, args.stage_reps, lay)
     samples = B * T
+    cbytes = 8 * lay.total_slices * plan.coefs_per_slice
+    # forward (x read, c written) + backward through the adjoint (grad c read,
+    # grad x written): the same algorithmic bytes as analysis + synthesis
+    path_bytes = 2 * 4 * samples + 2 * cbytes
     rate = lambda ms: round(samples / (ms * 1e-3) / 1e6, 1)
     return {"metric": METRIC, "value": rate(ms_fb), "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(ms_fb, 4), "higher_is_better": True, "scaling": "weak",
@@ -239,9 +347,15 @@ def bench_differentiable(args):
             "config": {"workload": f"{B} x 6 s (264600 samples) at 44.1 kHz, B=36, 65.4-16000 Hz, 2N=16384, "
                                    "M=2048; log-magnitude loss forward + adjoint backward", "slices": lay.total_slices},
             "stages": stages,
+            "hbm": {"forward_backward": _frac(path_bytes, ms_fb, copy_gbs),
+                    "plain_analysis_synthesis": _frac(path_bytes, ms_plain, copy_gbs),
+                    "analysis_only": _frac(4 * samples + cbytes, ms_ana, copy_gbs),
+                    "adjoint_only": _frac(cbytes + 4 * samples, ms_adj, copy_gbs),
+                    "algorithmic_bytes": path_bytes},
             "compare": {"forward_backward_ms": round(ms_fb, 3), "plain_analysis_synthesis_ms": round(ms_plain, 3),
-                        "adjoint_only_ms": round(ms_adj, 3), "forward_backward_Msps": rate(ms_fb),
-                        "plain_Msps": rate(ms_plain)}}
+                        "analysis_only_ms": round(ms_ana, 3), "adjoint_only_ms": round(ms_adj, 3),
+                        "loss_ops_ms": round(ms_fb - ms_ana - ms_adj, 3),
+                        "forward_backward_Msps": rate(ms_fb), "plain_Msps": rate(ms_plain)}}
 
 
 def bench_stream(args):
@@ -262,7 +376,6 @@ def bench_stream(args):
     srv = sq.StreamServer(plan, "f32", max_streams=n_streams + 64, max_batch=2 * n_streams)
     rng = np.random.default_rng(5)
     stop = threading.Event()
-    lock = threading.Lock()
 
     def ticker():
         while not stop.is_set():
@@ -337,7 +450,18 @@ def bench_stream(args):
             "unpaced": {"Msamples_per_s": round(un["samples_in"] / t_un / 1e6, 2), "slices_per_s":
                         round(un["slices"] / t_un, 1), "streams": len(ids), "rounds": rounds,
                         "latency_p50_ms": round(un["latency_p50_s"] * 1e3, 3),
-                        "latency_p99_ms": round(un["latency_p99_s"] * 1e3, 3)}}
+                        "latency_p99_ms": round(un["latency_p99_s"] * 1e3, 3)},
+            "device_bytes": {"per_stream": un["bytes_per_stream"], "fixed": un["fixed_bytes"]}}
+
+
+def _form_summary(rec):
+    """The key figures of a form's record, for the default line."""
+    keep = {k: rec[k] for k in ("value", "unit", "ms_per_step") if k in rec}
+    keep["workload"] = rec["config"]["workload"]
+    for k in ("path", "hbm", "compare", "latency_ms", "unpaced", "tuning"):
+        if rec.get(k) is not None:
+            keep[k] = rec[k]
+    return keep
 
 
 def main():
@@ -346,6 +470,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched, differentiable and streaming sub-records of the default line")
     ap.add_argument("--graph", action="store_true", help="replay the step's launches as one HIP graph (same speed on c2)")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -354,6 +480,8 @@ def main():
                     help="c2 (default): 60 s stereo; c3: ragged batch in a HIP graph; c4: differentiable; "
                          "c5: streaming service")
     ap.add_argument("--c3-signals", type=int, default=256)
+    ap.add_argument("--c3-tune", action="store_true", help="autotune the ragged batch's work items first")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--c4-batch", type=int, default=32)
     ap.add_argument("--c5-streams", type=int, default=512)
     ap.add_argument("--c5-seconds", type=float, default=10.0)
@@ -368,15 +496,18 @@ def main():
         print(json.dumps(fn(args)), flush=True)
         return
 
+    from workloads import PRESETS, make_c2
+    xs = make_c2()
+    # the oracle's process pool forks before anything touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(xs)
+
     import torch
     import paper_1210_0084_amd as sq
-    from workloads import PRESETS, make_c2
 
     p = PRESETS["c2"]
     prm = dict(fs=p.fs, fmin=p.fmin, fmax=p.fmax, bins_per_octave=p.bins_per_octave, slice_len=p.slice_len,
                transition=p.transition)
     dev = torch.device("cuda:0")
-    xs = make_c2()
     T = xs.shape[1]
     plan = sq.Plan(**prm)
     lay = plan.batch_layout([T, T])
@@ -413,12 +544,17 @@ def main():
 
     # per-kernel timing of the pipeline the last step launched (HIP events on the same stream)
     S = lay.total_slices
+    if args.graph:
+        eager()                             # the stage hooks read the plan's own workspace
+        torch.cuda.synchronize()
     stage_ms = time_stages(plan, S, x, coef, y, args.stage_reps, lay)
     sbytes = stage_bytes(plan, S, 4)
-    stages = {k: {"ms": round(stage_ms[k], 4), "GBs": round(sbytes[k] / (stage_ms[k] * 1e-3) / 1e9, 1)}
-              for k in STAGES}
+    share = algorithmic_share(plan, S, samples, 4)
+    copy_gbs = copy_rate()
+    stages = {k: {"ms": round(stage_ms[k], 4), "interface_GBs": round(sbytes[k] / (stage_ms[k] * 1e-3) / 1e9, 1),
+                  "algorithmic_GBs": round(share[k] / (stage_ms[k] * 1e-3) / 1e9, 1)} for k in STAGES}
     dom = max(STAGES, key=lambda k: stage_ms[k])
-    achieved = sbytes[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    achieved = share[dom] / (stage_ms[dom] * 1e-3) / 1e9
     path_bytes = 2 * 4 * samples + 2 * 8 * S * plan.coefs_per_slice
     rec = {
         "metric": METRIC,
@@ -437,11 +573,14 @@ def main():
                                "2N=65536, M=8192; analysis+synthesis" + (" (one HIP graph)" if args.graph else ""),
                    "signals": 2, "samples_per_signal": T, "slices": S, "coefs_per_slice": plan.coefs_per_slice},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom), "algorithmic_bytes": sbytes[dom]},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+                     "algorithmic_bytes": share[dom], "interface_bytes": sbytes[dom],
+                     "kernel_ms": round(stage_ms[dom], 4), "copy_GBs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
         "path": {"algorithmic_bytes_per_step": path_bytes,
                  "GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1),
                  "frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "frac_of_copy": round(path_bytes / (ms * 1e-3) / 1e9 / copy_gbs, 4),
                  "host_wall_ms_per_step": round(t_host * 1e3 / args.steps, 4),
                  "reconstruction_max_abs_err": err},
         "stages": stages,
@@ -454,8 +593,21 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = 4 * n
-    if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(prm, xs)
+        del src, dst
+    del x, coef, y
+    torch.cuda.empty_cache()
+    if not args.no_forms:
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup, sub.stage_reps = 10, 3, 5
+        sub.c5_seconds = min(args.c5_seconds, 6.0)
+        forms = {}
+        for name, fn in (("batched", bench_batched), ("differentiable", bench_differentiable)):
+            forms[name] = _form_summary(fn(sub, copy_gbs))
+            torch.cuda.empty_cache()
+        forms["streaming"] = _form_summary(bench_stream(sub))
+        rec["forms"] = forms
+    if cpu is not None:
+        rec["cpu_baseline"] = cpu
     print(json.dumps(rec), flush=True)
 
 

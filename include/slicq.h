@@ -160,10 +160,13 @@ int slicq_adjoint(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t 
 /* Ragged batches. Signal b holds samples x_off[b] .. x_off[b+1]-1 of the
  * packed x (x_off: nsig + 1 int64 in device memory, x_len = packed length)
  * and its coefficients start at coef_off[b] (nsig int64, device memory) with
- * the single-signal layout. total_slices must equal sum_b S_b; signals whose
- * ranges fall outside the buffers are skipped. Every slice of every signal is
- * processed by the same launches (one per kernel). Per-signal results are
- * identical to the single-signal calls. */
+ * the single-signal layout. total_slices must equal sum_b S_b. The offsets
+ * live in device memory, so these calls cannot check them on the host and
+ * never synchronise: a signal whose samples or coefficients fall outside
+ * x_len / coef_len (or beyond total_slices) is skipped and the task builder
+ * flags it in the workspace; slicq_batched_status reads that flag back.
+ * Every slice of every signal is processed by the same launches (one per
+ * kernel). Per-signal results are identical to the single-signal calls. */
 int slicq_analyze_batched(slicq_plan plan, slicq_dtype dtype, const void* x, int64_t x_len,
                           const int64_t* x_off, int32_t nsig, int64_t total_slices, void* coef,
                           int64_t coef_len, const int64_t* coef_off, void* work, size_t work_bytes,
@@ -176,16 +179,26 @@ int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dtype, const void* coef, 
                           const int64_t* coef_off, void* y, int64_t y_len, const int64_t* y_off,
                           int32_t nsig, int64_t total_slices, void* work, size_t work_bytes,
                           void* hip_stream);
+/* Validity of the last batched call that used `work` (same plan, dtype and
+ * total_slices): waits for hip_stream, then *bad = 1 if that call skipped a
+ * signal whose ranges fell outside its buffers (and returns SLICQ_ESIZE),
+ * else *bad = 0 and SLICQ_OK; *slices (may be NULL) receives the slice count
+ * the task builder found. Synchronises the stream: call it when the caller
+ * chooses, never inside graph capture. */
+int slicq_batched_status(slicq_plan plan, slicq_dtype dtype, int64_t total_slices, const void* work,
+                         size_t work_bytes, int32_t* bad, int64_t* slices, void* hip_stream);
 
 /* Prepared batches: the slice task table of a ragged batch built once and
  * reused by any number of transforms of batches with the same offsets (the
  * batched calls above rebuild it on every call). slicq_batch_tasks_bytes
  * gives the size of the caller-owned device buffer `tasks`.
- * slicq_batch_create enqueues the build on hip_stream (offsets as for the
+ * slicq_batch_create builds the table on hip_stream (offsets as for the
  * batched calls; x_len and coef_len bound the signal and coefficient ranges
- * the tasks may address) and returns a host handle that keeps the plan, the
- * tasks pointer and these bounds; the offsets may be freed once the build has
- * run. slicq_*_batch then run the transform with the prepared tasks: buffers
+ * the tasks may address), waits for it once and checks it: a signal whose
+ * samples or coefficients fall outside those bounds, or a slice count other
+ * than total_slices, fails the call with SLICQ_ESIZE (no handle). On success
+ * it returns a host handle that keeps the plan, the tasks pointer and these
+ * bounds; the offsets may be freed. slicq_*_batch then run the transform with the prepared tasks: buffers
  * must be at least x_len / coef_len long (SLICQ_ESIZE otherwise) and the
  * tasks buffer must stay alive and unmodified. A workspace smaller than
  * slicq_workspace_size(total_slices) is processed in chunks. The handle is
@@ -215,7 +228,12 @@ int slicq_adjoint_batch(slicq_batch batch, slicq_dtype dtype, const void* coef, 
  * threads proceed meanwhile and join the next tick. Per-stream state (input
  * and output rings of 4N samples) lives in device memory allocated once at
  * creation; admission is limited by max_streams and hbm_budget_bytes
- * (0 = no budget). Samples passed to push/poll are host memory of the
+ * (0 = no budget): every device buffer the server allocates, fixed
+ * (workspace and coefficients for max_batch slices) or per stream (two rings
+ * and the staging share), is counted against the budget. Each tick serves
+ * the ready slices of the streams round robin, starting after the last
+ * stream the previous tick reached when max_batch cut it short, so no stream
+ * waits more than a bounded number of ticks under overload. Samples passed to push/poll are host memory of the
  * server's dtype. A device error fences the server (SLICQ_EHIP on every later
  * call). */
 typedef struct slicq_stream_server_s* slicq_stream_server;
@@ -229,7 +247,8 @@ typedef struct {
   int32_t slots;             /* streams the budget admits */
   int32_t pad_;
   int64_t ring_len;          /* samples per ring (4N) */
-  int64_t bytes_per_stream;  /* device bytes per admitted stream */
+  int64_t bytes_per_stream;  /* device bytes per admitted stream (two rings, staging, copy records) */
+  int64_t fixed_bytes;       /* device bytes independent of the stream count (workspace, coefficients) */
 } slicq_stream_stats;
 
 int slicq_stream_server_create(slicq_plan plan, slicq_dtype dtype, int32_t max_streams, int32_t max_batch,

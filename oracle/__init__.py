@@ -25,5 +25,6 @@ docstring; all functions here are pinned by tests under ``tests/`` marked
 """
 from .plan import OraclePlan, BandTable, plan_from_tables, q_factor  # noqa: F401
 from .transform import (analyze, synthesize, adjoint, analyze_full, synthesize_full,  # noqa: F401
-                        num_slices, padded_length, analyze_stream, synthesize_stream, pack, unpack)
+                        num_slices, padded_length, analyze_stream, synthesize_stream, pack, unpack,
+                        analyze_slices, synthesize_slices)
 from . import brute  # noqa: F401

@@ -65,21 +65,29 @@ def analyze_full(plan, f) -> List[np.ndarray]:
     return _analyze(plan, f, plan.all_bands)
 
 
-def _analyze(plan, f, bands):
+def _analyze(plan, f, bands, m0: int = 0, m1=None):
     two_n, N = plan.two_n, plan.N
     T = f.shape[0]
     L = padded_length(T, two_n)
     S = 2 * L // two_n
+    m1 = S if m1 is None else min(int(m1), S)
     fp = np.zeros(L, dtype=f.dtype)
     fp[:T] = f
-    out = [np.zeros((S, b.M), dtype=np.complex128) for b in bands]
+    out = [np.zeros((max(m1 - m0, 0), b.M), dtype=np.complex128) for b in bands]
     scale = 1.0 / math.sqrt(two_n)
-    for m in range(S):
+    for m in range(m0, m1):
         xm = fp[_slice_index(m, N, L)] * plan.h0
         X = np.fft.fft(xm) * scale
         for kk, b in enumerate(bands):
-            out[kk][m] = _band_ifft(X, b, two_n)
+            out[kk][m - m0] = _band_ifft(X, b, two_n)
     return out
+
+
+def analyze_slices(plan, f, m0: int, m1: int) -> List[np.ndarray]:
+    """Slices m0 .. m1-1 of ``analyze(plan, f)`` (Algorithm 3's loop over m
+    restricted to a range; slices are independent given the signal), so that
+    a pool of processes can share the slices of one signal."""
+    return _analyze(plan, np.asarray(f, dtype=np.float64), plan.bands, m0, m1)
 
 
 def _slice_synthesis(plan, coefs_m, bands, window) -> np.ndarray:
@@ -109,14 +117,23 @@ def synthesize(plan, c, T: int) -> np.ndarray:
     bands take the conjugate coefficients and the result is the real part of
     the full synthesis.
     """
+    two_n = plan.two_n
+    L = padded_length(T, two_n)
+    return synthesize_slices(plan, c, T, 0, 2 * L // two_n)[:T]
+
+
+def synthesize_slices(plan, c, T: int, m0: int, m1: int) -> np.ndarray:
+    """The contribution of slices m0 .. m1-1 to the overlap-add of Algorithm 4,
+    over all L samples of the padded signal (``c`` holds those slices only,
+    as arrays (m1 - m0, M_k)). Summing the contributions of a partition of
+    the slices gives ``synthesize`` (before truncation to T)."""
     two_n, N = plan.two_n, plan.N
     L = padded_length(T, two_n)
-    S = 2 * L // two_n
     out = np.zeros(L)
-    for m in range(S):
-        y = _slice_synthesis(plan, _mirror_coefs(plan, c, m), plan.all_bands, "dual")
+    for m in range(m0, m1):
+        y = _slice_synthesis(plan, _mirror_coefs(plan, c, m - m0), plan.all_bands, "dual")
         np.add.at(out, _slice_index(m, N, L), y.real * plan.hd)
-    return out[:T]
+    return out
 
 
 def synthesize_full(plan, c, T: int) -> np.ndarray:

@@ -42,7 +42,8 @@ class _StreamStats(ctypes.Structure):
                 ("closed", ctypes.c_int64), ("gap_samples", ctypes.c_int64), ("latency_p50_s", ctypes.c_double),
                 ("latency_p99_s", ctypes.c_double), ("latency_max_s", ctypes.c_double),
                 ("latency_count", ctypes.c_int64), ("busy_s", ctypes.c_double), ("slots", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("ring_len", ctypes.c_int64), ("bytes_per_stream", ctypes.c_int64)]
+                ("pad_", ctypes.c_int32), ("ring_len", ctypes.c_int64), ("bytes_per_stream", ctypes.c_int64),
+                ("fixed_bytes", ctypes.c_int64)]
 
 
 class _Opts(ctypes.Structure):
@@ -91,6 +92,8 @@ def load_library():
         "slicq_synthesize_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_adjoint_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_profile_stage": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, I64, P, P, P, P, SZ, P]),
+        "slicq_batched_status": (ctypes.c_int, [P, ctypes.c_int, I64, P, SZ, ctypes.POINTER(I32),
+                                                ctypes.POINTER(I64), P]),
         "slicq_batch_tasks_bytes": (SZ, [I64]),
         "slicq_profile_stage_batch": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
         "slicq_batch_create": (ctypes.c_int, [P, P, P, I32, I64, I64, I64, P, SZ, P, ctypes.POINTER(P)]),
@@ -450,6 +453,17 @@ class Plan:
                   lay.total_slices, ctypes.c_void_p(w.data_ptr()), wb, ctypes.c_void_p(_stream_ptr(coef.device))))
         self._note_tasks(dt, coef.device, lay.total_slices, work)
         return out
+
+    def batched_status(self, dt: int, n_slices: int, device, work=None) -> int:
+        """Slice count the last batched call's task builder found in the
+        workspace; raises SlicqError if that call skipped a signal whose
+        ranges fell outside its buffers. Waits for the current stream."""
+        w, wb = self._workspace(dt, n_slices, device, work)
+        bad, n = ctypes.c_int32(), ctypes.c_int64()
+        _check(self._lib.slicq_batched_status(self._h, dt, int(n_slices), ctypes.c_void_p(w.data_ptr()), wb,
+                                              ctypes.byref(bad), ctypes.byref(n),
+                                              ctypes.c_void_p(_stream_ptr(device))))
+        return n.value
 
     def profile_stage(self, stage: int, n_slices: int, x, coef, y, work=None, layout: Optional[BatchLayout] = None):
         """Enqueues one kernel of the preceding call's pipeline (measurement hook). Pass the

@@ -414,6 +414,7 @@ int slicq_stream_stats_get(slicq_stream_server s, slicq_stream_stats* out) {
     out->slots = srv.slots();
     out->ring_len = srv.ring();
     out->bytes_per_stream = (int64_t)srv.per_stream_bytes();
+    out->fixed_bytes = (int64_t)srv.fixed_bytes();
     return SLICQ_OK;
   });
 }
@@ -657,6 +658,25 @@ int slicq_adjoint_batched(slicq_plan plan, slicq_dtype dt, const void* coef, int
                               work_bytes, stream);
 }
 
+int slicq_batched_status(slicq_plan plan, slicq_dtype dt, int64_t total, const void* work, size_t work_bytes,
+                         int32_t* bad, int64_t* slices, void* stream) {
+  if (!plan || !work || !bad) return fail(SLICQ_EINVAL, "null argument");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "bad dtype");
+  if (total <= 0) return fail(SLICQ_EINVAL, "total_slices must be > 0");
+  slicq::WorkLayout w;
+  int rc = layout_or_fail(plan->p, dt, total, work_bytes, w);
+  if (rc) return rc;
+  int32_t hs[2] = {0, 0};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(hs, static_cast<const char*>(work) + w.status_off, sizeof hs, hipMemcpyDeviceToHost,
+                                st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "status read");
+  *bad = hs[0] != 0 ? 1 : 0;
+  if (slices) *slices = hs[1];
+  return *bad ? fail(SLICQ_ESIZE, "the last batched call skipped a signal outside its buffers") : SLICQ_OK;
+}
+
 size_t slicq_batch_tasks_bytes(int64_t total_slices) {
   return total_slices < 0 ? 0 : slicq::tasks_bytes(total_slices) + 256;   // tasks, then two status words
 }
@@ -674,9 +694,23 @@ int slicq_batch_create(slicq_plan plan, const int64_t* x_off, const int64_t* coe
   slicq::Plan& p = plan->p;
   auto* t = static_cast<slicq::SliceTask*>(tasks);
   auto* status = reinterpret_cast<int32_t*>(static_cast<char*>(tasks) + slicq::tasks_bytes(total));
-  batched_tasks(p, x_off, nsig, total, x_len, coef_off, coef_len, t, status, static_cast<hipStream_t>(stream));
-  const hipError_t e = hipGetLastError();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  batched_tasks(p, x_off, nsig, total, x_len, coef_off, coef_len, t, status, st);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "task table launch");
+  // one wait per prepared batch: a table with skipped signals is refused here
+  int32_t hs[2] = {0, 0};
+  e = hipMemcpyAsync(hs, status, sizeof hs, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "task table check");
+  if (hs[0] != 0)
+    return fail(SLICQ_ESIZE, "a signal's samples or coefficients fall outside x_len / coef_len, or the slices "
+                             "exceed total_slices");
+  if ((int64_t)hs[1] != total) {
+    char b[160];
+    std::snprintf(b, sizeof b, "the offsets describe %d slices, not total_slices = %lld", hs[1], (long long)total);
+    return fail(SLICQ_ESIZE, b);
+  }
   *out = new (std::nothrow) slicq_batch_s{plan, t, total, x_len, coef_len};
   return *out ? SLICQ_OK : fail(SLICQ_ENOMEM, "out of host memory");
 }

@@ -96,11 +96,16 @@ class StreamServer {
     N_ = p_.N;
     R_ = 4 * p_.N;
     cps_ = p_.coefs_per_slice;
-    per_stream_ = 2 * (size_t)R_ * sizeof(T);
-    int cap = max_streams;
-    if (budget_bytes > 0) cap = (int)std::min<int64_t>(cap, (int64_t)(budget_bytes / per_stream_));
-    slots_ = std::max(cap, 0);
     max_batch_ = std::max(max_batch, 1);
+    // device bytes: per slot two rings, its share of the staging buffer and
+    // two copy records; fixed: the workspace and coefficients of max_batch
+    // slices and the spare copy records
+    per_stream_ = 3 * (size_t)R_ * sizeof(T) + 2 * sizeof(RingCopy);
+    fixed_ = workspace_bytes(p_, dt_, max_batch_) + (size_t)max_batch_ * cps_ * sizeof(C2<T>) + 2 * sizeof(RingCopy);
+    int64_t cap = max_streams;
+    if (budget_bytes > 0)
+      cap = budget_bytes > fixed_ ? std::min<int64_t>(cap, (int64_t)((budget_bytes - fixed_) / per_stream_)) : 0;
+    slots_ = (int)std::max<int64_t>(cap, 0);
     streams_.resize(slots_);
   }
 
@@ -113,7 +118,7 @@ class StreamServer {
       return false;
     }
     const size_t ring_bytes = (size_t)slots_ * R_ * sizeof(T);
-    work_bytes_ = workspace_bytes(p_, dt_, max_batch_);
+    work_bytes_ = workspace_bytes(p_, dt_, max_batch_);   // counted in fixed_
     staging_cap_ = (int64_t)slots_ * R_;
     xring_ = (T*)be_.dmalloc(ring_bytes);
     yring_ = (T*)be_.dmalloc(ring_bytes);
@@ -150,6 +155,7 @@ class StreamServer {
   int64_t ring() const { return R_; }
   int64_t coefs_per_slice() const { return cps_; }
   size_t per_stream_bytes() const { return per_stream_; }
+  size_t fixed_bytes() const { return fixed_; }
 
   // Admission: returns a slot id >= 0, or -1 if every slot is taken.
   int open() {
@@ -230,9 +236,20 @@ class StreamServer {
           s.on_device += n;
         }
       }
-      for (int id = 0; id < slots_ && ntask < max_batch_; ++id) {
+      // round robin: start with the stream the previous tick's batch could not
+      // take (a stream holds at most R/N ready slices, so every stream is
+      // served within a bounded number of ticks)
+      const int start = rr_;
+      bool full = false;
+      for (int i = 0; i < slots_ && !full; ++i) {
+        const int id = (start + i) % slots_;
         Stream& s = streams_[id];
-        while (s.active && ntask < max_batch_ && s.on_device >= s.next_slice * N_ + (N_ + p_.Mt) / 2) {
+        while (s.active && s.on_device >= s.next_slice * N_ + (N_ + p_.Mt) / 2) {
+          if (ntask == max_batch_) {       // full: this stream is served first next tick
+            rr_ = id;
+            full = true;
+            break;
+          }
           const int64_t m = s.next_slice++;
           SliceTask tk{};
           tk.x_base = (int64_t)id * R_;
@@ -478,8 +495,8 @@ class StreamServer {
   int dt_;
   Backend& be_;
   int64_t N_ = 0, R_ = 0, cps_ = 0, staging_cap_ = 0;
-  size_t per_stream_ = 0, work_bytes_ = 0;
-  int slots_ = 0, max_batch_ = 0;
+  size_t per_stream_ = 0, fixed_ = 0, work_bytes_ = 0;
+  int slots_ = 0, max_batch_ = 0, rr_ = 0;
   std::vector<Stream> streams_;
   std::vector<int> to_clear_;
   std::vector<double> lat_;

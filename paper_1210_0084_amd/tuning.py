@@ -101,7 +101,10 @@ class BatchGraph:
         self.plan, self.x, self.coef, self.y, self.layout = plan, x, coef, y, layout
         dt = 0 if x.dtype == torch.float32 else 1
         plan._ensure_tables(dt, x.device)
-        plan._workspace(dt, layout.total_slices, x.device)
+        # the graph records this workspace's address: it is owned here, so no
+        # later call on the plan (which may replace the plan's own workspace)
+        # can free it while the graph may still be replayed
+        self.work = torch.empty(plan.workspace_bytes(dt, layout.total_slices), dtype=torch.uint8, device=x.device)
         layout.device(x.device)
         # warm up outside the capture (first-use attribute settings, allocations)
         self._run(adjoint)
@@ -116,8 +119,8 @@ class BatchGraph:
         torch.cuda.synchronize(x.device)
 
     def _run(self, adjoint):
-        self.plan.analyze_batched(self.x, out=self.coef, layout=self.layout)
-        self.plan.synthesize_batched(self.coef, out=self.y, layout=self.layout, adjoint=adjoint)
+        self.plan.analyze_batched(self.x, out=self.coef, layout=self.layout, work=self.work)
+        self.plan.synthesize_batched(self.coef, out=self.y, layout=self.layout, adjoint=adjoint, work=self.work)
 
     def replay(self):
         self.graph.replay()

@@ -64,7 +64,7 @@ def stream(plan: dict, signals, hop: int, dtype: int = 1, mode: int = 0, max_str
     for i in sel:
         ys.append(out[pos:pos + lens[i]])
         pos += lens[i]
-    return ys, out[pos:pos + 4]
+    return ys, out[pos:pos + 5]
 
 
 def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,

@@ -102,7 +102,7 @@ int run(slicq::Plan& plan, int dt, int max_streams, int max_batch, size_t budget
   std::vector<std::vector<T>> y(ns);
   std::vector<int64_t> fed(ns, 0);
   std::vector<unsigned char> snap;
-  int64_t snap_fed = -1;
+  int64_t snap_fed = -1, min_out8 = -1;
   bool more = true;
   for (int round = 0; more; ++round) {
     more = false;
@@ -126,6 +126,20 @@ int run(slicq::Plan& plan, int dt, int max_streams, int max_batch, size_t budget
     if (round == 3 && id[sel[0]] >= 0) {
       if (!srv.snapshot(id[sel[0]], snap)) return 13;
       snap_fed = fed[sel[0]];
+    }
+    if (round == 8) {                       // progress of the least served stream so far
+      min_out8 = (int64_t)1 << 62;
+      for (int i : sel) min_out8 = std::min<int64_t>(min_out8, (int64_t)y[i].size());
+    }
+  }
+  // drain: slices still queued when max_batch was below the arrival rate
+  for (int64_t n = 1; n > 0;) {
+    n = srv.tick();
+    if (n < 0) return 12;
+    for (int i : sel) {
+      std::vector<T> buf(1 << 16);
+      int64_t got;
+      while ((got = srv.poll(id[i], buf.data(), (int64_t)buf.size())) > 0) y[i].insert(y[i].end(), buf.begin(), buf.begin() + got);
     }
   }
   // replay stream sel[0] from its snapshot in a fresh slot and compare the rest
@@ -170,7 +184,7 @@ int run(slicq::Plan& plan, int dt, int max_streams, int max_batch, size_t budget
     }
   }
   const StreamStats st = srv.stats();
-  double stv[4] = {(double)st.admitted, (double)st.rejected, (double)st.slices, (double)st.ticks};
+  double stv[5] = {(double)st.admitted, (double)st.rejected, (double)st.slices, (double)st.ticks, (double)min_out8};
   std::fwrite(stv, sizeof stv, 1, f);
   std::fclose(f);
   return 0;

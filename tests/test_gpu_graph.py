@@ -40,6 +40,35 @@ def test_graph_replays_equal_eager(dev):
         assert (gy - x).abs().max().item() < 1e-4
 
 
+def test_graph_survives_larger_eager_calls(dev):
+    # the graph owns its workspace: an eager call on the same plan that needs a
+    # larger workspace (and replaces the plan's own) leaves replays unchanged
+    import torch
+    import paper_1210_0084_amd as sq
+    from paper_1210_0084_amd.tuning import BatchGraph
+    plan = sq.Plan(**c3_kw())
+    lens = [60000, 90001]
+    lay = plan.batch_layout(lens)
+    x = torch.tensor(np.concatenate([pink_plus_tones(n, 44100.0, 80 + i) for i, n in enumerate(lens)]),
+                     dtype=torch.float32, device=dev)
+    coef = torch.empty(lay.coef_len, dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    graph = BatchGraph(plan, x, coef, y, lay)
+    graph.replay()
+    torch.cuda.synchronize()
+    c0, y0 = coef.clone(), y.clone()
+    big = torch.tensor(pink_plus_tones(2_000_000, 44100.0, 99), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        cb = plan.analyze(big)                      # grows the plan's workspace
+        yb = plan.synthesize(cb, big.numel())
+        coef.zero_()
+        y.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(coef, c0) and torch.equal(y, y0)
+        assert (yb - big).abs().max().item() < 1e-4
+
+
 def test_autotuner_picks_a_valid_option(dev, tmp_path):
     import paper_1210_0084_amd as sq
     from paper_1210_0084_amd.tuning import autotune

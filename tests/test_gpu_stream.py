@@ -96,9 +96,27 @@ def test_alone_equals_in_the_mix_bitwise(sq, plan):
 
 
 def test_admission_by_memory_budget(sq, plan):
-    per = 2 * 4 * plan.N * 4            # two rings of 4N float32 samples
-    srv = sq.StreamServer(plan, "f32", max_streams=16, max_batch=8, hbm_budget_bytes=3 * per)
+    # every device buffer counts against the budget: per stream two rings of
+    # 4N float32 samples plus its 4N-sample share of the staging buffer (and
+    # two 16-byte copy records); fixed: the workspace and coefficients of
+    # max_batch slices
+    import torch
+    probe = sq.StreamServer(plan, "f32", max_streams=1, max_batch=8)
+    st0 = probe.stats()
+    per, fixed = st0["bytes_per_stream"], st0["fixed_bytes"]
+    assert per == 3 * 4 * plan.N * 4 + 32
+    assert fixed >= plan.workspace_bytes(0, 8) + 8 * plan.coefs_per_slice * 8
+    del probe
+    torch.cuda.synchronize()
+    before = torch.cuda.mem_get_info()[0]
+    budget = fixed + 3 * per + per // 2
+    srv = sq.StreamServer(plan, "f32", max_streams=16, max_batch=8, hbm_budget_bytes=budget)
     assert srv.stats()["slots"] == 3
+    used = before - torch.cuda.mem_get_info()[0]
+    # the driver rounds allocations up to its page size: allow 2 MiB per buffer
+    assert used <= budget + 8 * (2 << 20), (used, budget)
+    with pytest.raises(sq.SlicqBusy):
+        sq.StreamServer(plan, "f32", max_streams=16, max_batch=8, hbm_budget_bytes=fixed + per - 1)
     ids = [srv.open() for _ in range(3)]
     with pytest.raises(sq.SlicqBusy):
         srv.open()
@@ -195,3 +213,59 @@ def test_push_many_and_poll_many_match_single_calls(sq, plan):
         assert np.array_equal(y, ref[ids1[i]])
     with pytest.raises(sq.SlicqError):
         many.push_many([ids[0], 99], [np.zeros(4), np.zeros(4)])   # 99 is not open: nothing is appended
+
+
+def test_churn_alone_equals_in_a_large_mix_bitwise(sq, plan):
+    # 64 streams, with streams closing and new ones opening mid-run: a
+    # stream's output and coefficients are bit-identical alone and in the mix
+    rng = np.random.default_rng(11)
+    mix = sq.StreamServer(plan, "f32", max_streams=80, max_batch=256)
+    n0 = 64
+    lens = [int(rng.integers(30000, 60000)) for _ in range(n0 + 8)]
+    sigs = [pink_plus_tones(n, 48000.0, 5_001_000 + i) for i, n in enumerate(lens)]
+    flush = plan.N + plan.transition
+    ids = {i: mix.open() for i in range(n0)}
+    fed = {i: 0 for i in ids}
+    outs = {i: [] for i in ids}
+    watch = 3                                   # compared alone below
+    caps_mix = {}
+    late = list(range(n0, n0 + 8))
+    closed = set()
+    rnd = 0
+    while any(fed[i] < lens[i] + flush for i in ids if i not in closed):
+        rnd += 1
+        if rnd == 4:                            # churn: close 8 streams, open 8 new ones
+            for i in range(10, 18):
+                mix.close(ids[i])
+                closed.add(i)
+            for i in late:
+                ids[i] = mix.open()
+                fed[i] = 0
+                outs[i] = []
+        for i, sid in ids.items():
+            if i in closed or fed[i] >= lens[i] + flush:
+                continue
+            h = np.zeros(HOP)
+            lo, hi = fed[i], min(fed[i] + HOP, lens[i])
+            if hi > lo:
+                h[:hi - lo] = sigs[i][lo:hi]
+            mix.push(sid, h)
+            fed[i] += HOP
+        mix.tick()
+        m, c = mix.last_coefs(ids[watch])
+        if m >= 0:
+            caps_mix[m] = c
+        for i, sid in ids.items():
+            if i not in closed:
+                outs[i].append(mix.poll(sid))
+    for i in [watch, n0 + 2]:                   # one stream from the start, one opened mid-run
+        alone = sq.StreamServer(plan, "f32", max_streams=2, max_batch=16)
+        a = alone.open()
+        out_a, caps_a = feed(alone, [a], [sigs[i]], coefs_of=a if i == watch else None)
+        y = np.concatenate(outs[i])[:lens[i]]
+        assert np.array_equal(out_a[a], y), i
+        if i == watch:
+            assert caps_a.keys() == caps_mix.keys()
+            for m in caps_a:
+                assert np.array_equal(caps_a[m], caps_mix[m])
+    assert rel(np.concatenate(outs[n0 + 5])[:lens[n0 + 5]], sigs[n0 + 5]) <= 1e-5

@@ -176,3 +176,59 @@ def test_transposition_fact_golden():
 def test_invalid_parameters(bad):
     with pytest.raises(ValueError):
         OraclePlan(**bad)
+
+
+DERIVED = json.load(open(os.path.join(GOLDEN, "derived_constants.json")))
+
+
+@pytest.mark.parametrize("name", list(PRESETS))
+def test_derived_constants(name):
+    # constants an independent pre-build computation of the same readings gave
+    # (K below Nyquist, minimal filter length 16 bins, power-of-two M_k)
+    import collections
+    d = DERIVED[name]
+    pl = preset_plan(name)
+    assert math.isclose(pl.Q, d["Q"], abs_tol=5e-5)
+    assert (pl.K0, pl.K, pl.nbands) == (d["K0"], d["K"], d["nbands"])
+    assert int(np.sum(pl.xi / pl.Q < pl.min_win * pl.fs / pl.two_n)) == d["widened"]
+    assert sum(b.length for b in pl.bands) == d["sum_J"]
+    assert pl.coefs_per_slice == d["sum_M"]
+    hist = collections.Counter(str(int(b.M)) for b in pl.bands)
+    assert dict(hist) == d["M_hist"]
+    assert (pl.bands[0].M, pl.bands[0].length) == (d["M_dc"], d["J_dc"])
+    assert (pl.bands[-1].M, pl.bands[-1].length) == (d["M_nyq"], d["J_nyq"])
+    assert abs(pl.D.min() - d["D_min"]) <= 0.01 and abs(pl.D.max() - d["D_max"]) <= 0.01
+    assert abs(pl.xi[-1] - d["xi_K"]) <= 0.05
+
+
+@pytest.mark.parametrize("name", list(PRESETS))
+def test_minimal_filter_length(name):
+    # Section 5.3: filters shorter than about 16 samples change the
+    # coefficients visibly, so every constant-Q band is at least min_win bins
+    # wide. Checked on the band tables themselves, not on the bandwidth
+    # formula: the support of a Hann band is the open interval of width
+    # Omega_k around xi_k, so it spans at least min_win - 1 whole bins, is
+    # centred on xi_k, and is never wider than the bound requires.
+    pl = preset_plan(name)
+    binw = pl.fs / pl.two_n
+    for b in pl.bands[1:pl.K + 1]:
+        assert b.length >= pl.min_win - 1, (b.k, b.length)
+        centre = (b.start + b.start + b.length - 1) / 2 * binw
+        assert abs(centre - b.xi) <= binw, (b.k, centre, b.xi)
+        cq_bins = b.xi / pl.Q / binw                 # constant-Q width in bins (Table 1)
+        need = max(cq_bins, pl.min_win)
+        # integer points strictly inside an open interval of width `need`
+        assert need - 1 - 1e-9 <= b.length <= need + 1 + 1e-9, (b.k, b.length, need)
+    # without the bound the narrowest bands of the long-slice presets hold
+    # fewer bins than the bound asks for (the widening is doing work)
+    raw = preset_plan("c2", min_win=0.0)
+    assert min(b.length for b in raw.bands[1:raw.K + 1]) < 8
+    with pytest.raises(ValueError):
+        preset_plan("c5", min_win=0.0)            # some bands would hold no bin at all
+
+
+def test_minimal_filter_length_matches_paper_threshold():
+    # the default bound is the length the paper calls largely equivalent
+    facts = json.load(open(os.path.join(GOLDEN, "paper_facts.json")))["minimal_filter_length"]
+    pl = preset_plan("c1")
+    assert pl.min_win == facts["equivalent_above"]

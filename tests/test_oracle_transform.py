@@ -189,3 +189,41 @@ def test_stream_form_equals_circular_without_wrap():
     y = synthesize_stream(pl, b, L)
     np.testing.assert_allclose(y[:T], f, atol=1e-13)
     assert np.abs(y[T:]).max() < 1e-13
+
+
+def test_pack_unpack_roundtrip():
+    # band-major packing (band k, slice m, index n at S off_k + m M_k + n) and
+    # its inverse; element positions checked one by one
+    from oracle import OraclePlan, pack, unpack
+    pl = OraclePlan(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0)
+    S = 5
+    g = np.random.default_rng(3)
+    c = [g.standard_normal((S, b.M)) + 1j * g.standard_normal((S, b.M)) for b in pl.bands]
+    flat = pack(pl, c)
+    assert flat.shape == (S * pl.coefs_per_slice,)
+    off = pl.offsets
+    for k, b in enumerate(pl.bands):
+        for m in (0, S - 1):
+            for n in (0, b.M - 1):
+                assert flat[S * off[k] + m * b.M + n] == c[k][m, n]
+    back = unpack(pl, flat, S)
+    assert all(np.array_equal(a, b) for a, b in zip(back, c))
+
+
+def test_slice_ranges_partition_the_transform():
+    # analysis restricted to slice ranges gives the rows of the full analysis;
+    # synthesis contributions of a partition of the slices sum to the full
+    # synthesis (the overlap-add is linear), and reconstruct the signal
+    from oracle import OraclePlan, analyze, synthesize, analyze_slices, synthesize_slices
+    pl = OraclePlan(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0)
+    T = 700
+    x = np.random.default_rng(8).standard_normal(T)
+    full = analyze(pl, x)
+    S = full[0].shape[0]
+    cuts = [0, 3, 4, 9, S]
+    parts = [analyze_slices(pl, x, a, b) for a, b in zip(cuts[:-1], cuts[1:])]
+    for k in range(pl.nbands):
+        assert np.array_equal(np.concatenate([p[k] for p in parts]), full[k])
+    y = sum(synthesize_slices(pl, p, T, a, b) for p, a, b in zip(parts, cuts[:-1], cuts[1:]))[:T]
+    np.testing.assert_allclose(y, synthesize(pl, full, T), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(y, x, rtol=0, atol=1e-12)

@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Preset", "PRESETS", "rng", "noise_plus_sines", "pink_noise",
     "harmonic_tones", "pink_plus_tones", "batch_lengths", "make_c1", "make_c2",
-    "make_c3", "make_c4", "make_c5_stream",
+    "make_c3", "make_c3_cut", "make_c4", "make_c5_stream",
 ]
 
 
@@ -136,6 +136,18 @@ def make_c3(n_signals: int = 256, seed: int = 4, lo_s: float = 5.0, hi_s: float 
     """Ragged batch: list of float64 signals, lengths uniform in [5 s, 30 s]."""
     lens = batch_lengths(n_signals, 44100.0, seed, lo_s, hi_s)
     return [pink_plus_tones(int(T), 44100.0, seed * 1_000_003 + i) for i, T in enumerate(lens)]
+
+
+def make_c3_cut(n_signals: int = 256, seed: int = 4):
+    """The ragged batch's lengths (as ``make_c3`` draws them) with content cut
+    at seeded offsets from one 60 s pink-plus-tones recording: (lengths,
+    offsets, recording). Rendering 256 distinct recordings takes minutes of
+    host time, and the transform's cost does not depend on the content."""
+    lens = [int(t) for t in batch_lengths(n_signals, 44100.0, seed)]
+    base = pink_plus_tones(int(60 * 44100), 44100.0, 4_000_012)
+    g = rng(seed)
+    offs = [int(g.integers(0, len(base) - t + 1)) for t in lens]
+    return lens, offs, base
 
 
 def make_c4(batch: int = 32, T: int = 264600, target: bool = False) -> np.ndarray:
