@@ -76,6 +76,10 @@ typedef struct {
                                into its bins may exceed it, up to 16384 */
   int32_t pass_cap;         /* tuning: complex values per slice-FFT work item (power of two), default 4096 */
   int32_t coef_layout;      /* SLICQ_BAND_MAJOR (0) or SLICQ_SLICE_MAJOR (1), see below */
+  int32_t unfused;          /* 0 (default): where a slice's half spectrum and its largest band
+                               transform fit one workgroup's LDS, each slice's analysis (and
+                               synthesis) runs in one workgroup with no intermediate in HBM;
+                               1: always the multi-kernel pipeline (the same results to rounding) */
 } slicq_plan_opts;
 
 enum { SLICQ_BAND_MAJOR = 0, SLICQ_SLICE_MAJOR = 1 };
@@ -91,6 +95,7 @@ typedef struct {
   int32_t n_ana_items;      /* analysis work items per slice */
   int32_t n_syn_items;      /* synthesis work items per slice */
   int32_t coef_layout;      /* SLICQ_BAND_MAJOR or SLICQ_SLICE_MAJOR */
+  int32_t fused;            /* bit d set: dtype d (SLICQ_F32 = 0, SLICQ_F64 = 1) runs one workgroup per slice */
 } slicq_plan_info;
 
 /* Design a plan from the paper's parameters (Section 3, Table 1; Section
@@ -144,6 +149,25 @@ int slicq_workspace_size(slicq_plan plan, slicq_dtype dtype, int64_t n_slices, s
  * zero padded to L = 2N ceil(T/2N) and sliced circularly. */
 int slicq_analyze(slicq_plan plan, slicq_dtype dtype, const void* x, int64_t T, void* coef,
                   int64_t coef_count, void* work, size_t work_bytes, void* hip_stream);
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * analysis as slicq_analyze (bitwise the same coefficients), with the
+ * workspace taken from a fixed device array inside the library instead of a
+ * caller buffer: slicq_static_scratch_bytes() bytes (32 MiB) per device,
+ * held until the process ends. x and coef are the caller's device buffers as
+ * for slicq_analyze. The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine (its first call on a device looks up the
+ * array's address once). Signals whose S = slicq_num_slices(T) slices need a
+ * task table plus one slice's workspace beyond the array fail with
+ * SLICQ_ESIZE; otherwise the slices run in as many chunks as the array
+ * holds. Every call on one device shares that device's array: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller. Nothing in the array needs clearing between
+ * calls (each call writes what it reads). */
+size_t slicq_static_scratch_bytes(void);
+int slicq_analyze_static(slicq_plan plan, slicq_dtype dtype, const void* x, int64_t T, void* coef,
+                         int64_t coef_count, void* hip_stream);
 
 /* Synthesis (Algorithm 4 with Algorithm 2 per slice, canonical duals) from
  * coef (S = slicq_num_slices(T) slices, band-major) into y: T real samples.
@@ -297,7 +321,10 @@ int slicq_stream_restore(slicq_stream_server server, int32_t id, const void* buf
  * of every output sample two slices share). The stage reads what the
  * preceding call left in the workspace; outputs are overwritten (stage 5
  * rewrites y in full, so it may be repeated; it overwrites the workspace
- * region that stage 4 reads). */
+ * region that stage 4 reads). For a dtype that runs one workgroup per slice
+ * (slicq_plan_info.fused), stage 0 is the whole analysis, stage 3 the whole
+ * synthesis before the overlap fix-up, stage 5 the fix-up, and stages 1, 2
+ * and 4 enqueue nothing. */
 int slicq_profile_stage(slicq_plan plan, slicq_dtype dtype, int stage, int64_t n_slices, const void* x,
                         void* coef, void* y, void* work, size_t work_bytes, void* hip_stream);
 /* The same for a prepared batch: re-launches one stage over all of its

@@ -51,14 +51,15 @@ class _Opts(ctypes.Structure):
                 ("bins_per_octave", ctypes.c_int32), ("slice_len", ctypes.c_int64),
                 ("transition_len", ctypes.c_int64), ("min_win", ctypes.c_double),
                 ("dual_slice", ctypes.c_int32), ("group_cap", ctypes.c_int32),
-                ("lds_cap", ctypes.c_int32), ("pass_cap", ctypes.c_int32), ("coef_layout", ctypes.c_int32)]
+                ("lds_cap", ctypes.c_int32), ("pass_cap", ctypes.c_int32), ("coef_layout", ctypes.c_int32),
+                ("unfused", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("nbands", ctypes.c_int32), ("slice_len", ctypes.c_int64),
                 ("transition_len", ctypes.c_int64), ("coefs_per_slice", ctypes.c_int64),
                 ("Q", ctypes.c_double), ("max_M", ctypes.c_int32), ("n_ana_items", ctypes.c_int32),
-                ("n_syn_items", ctypes.c_int32), ("coef_layout", ctypes.c_int32)]
+                ("n_syn_items", ctypes.c_int32), ("coef_layout", ctypes.c_int32), ("fused", ctypes.c_int32)]
 
 
 def library_path() -> str:
@@ -86,6 +87,8 @@ def load_library():
         "slicq_num_slices": (I64, [P, I64]),
         "slicq_workspace_size": (ctypes.c_int, [P, ctypes.c_int, I64, ctypes.POINTER(SZ)]),
         "slicq_analyze": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_analyze_static": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P]),
+        "slicq_static_scratch_bytes": (SZ, []),
         "slicq_synthesize": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
         "slicq_adjoint": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
         "slicq_analyze_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I32, I64, P, I64, P, P, SZ, P]),
@@ -228,11 +231,12 @@ class Plan:
 
     def __init__(self, fs: float, fmin: float, fmax: float, bins_per_octave: int, slice_len: int,
                  transition: int, min_win: float = 16.0, dual_slice: str = "canonical",
-                 group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: str = "band"):
+                 group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: str = "band",
+                 fused: bool = True):
         lib = load_library()
         o = _Opts(float(fs), float(fmin), float(fmax), int(bins_per_octave), int(slice_len), int(transition),
                   float(min_win), {"canonical": 0, "indicator": 1}[dual_slice], int(group_cap), int(lds_cap),
-                  int(pass_cap), {"band": 0, "slice": 1}[layout])
+                  int(pass_cap), {"band": 0, "slice": 1}[layout], 0 if fused else 1)
         h = ctypes.c_void_p()
         _check(lib.nsgt_plan_ex(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -250,6 +254,7 @@ class Plan:
         self.n_ana_items = info.n_ana_items
         self.n_syn_items = info.n_syn_items
         self.layout = "slice" if info.coef_layout == 1 else "band"
+        self.fused_dtypes = {d for d, bit in ((F32, 1), (F64, 2)) if info.fused & bit}
         self.fs, self.fmin, self.fmax, self.bins_per_octave = float(fs), float(fmin), float(fmax), int(bins_per_octave)
         nb = self.nbands
         self.M = np.zeros(nb, dtype=np.int32)
@@ -353,6 +358,24 @@ class Plan:
                                        ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(w.data_ptr()),
                                        wb, ctypes.c_void_p(_stream_ptr(x.device))))
         self._note_tasks(dt, x.device, S, work)
+        return out
+
+    def analyze_static(self, x, out):
+        """``analyze`` into the caller's ``out`` with the library's fixed device
+        scratch instead of a workspace: the call allocates nothing (for graph
+        capture and serving loops). Calls on one device must not overlap."""
+        _require_cuda(x, "x")
+        _require_cuda(out, "out")
+        if x.dim() != 1:
+            raise SlicqError("x must be 1-D")
+        dt = _dtype_code(x)
+        if _dtype_code(out) != dt or not out.is_complex():
+            raise SlicqError("out must be the complex dtype matching x")
+        if (dt, str(x.device)) not in self._tables:
+            raise SlicqError("upload the plan's tables first (one analyze call, or _ensure_tables)")
+        _check(self._lib.slicq_analyze_static(self._h, dt, ctypes.c_void_p(x.data_ptr()), x.numel(),
+                                              ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                              ctypes.c_void_p(_stream_ptr(x.device))))
         return out
 
     def _note_tasks(self, dt, device, n, work):

@@ -14,6 +14,13 @@
 #include "pipeline.hpp"
 #include "stream_server.hpp"
 
+// Scratch of slicq_analyze_static: the slice task table and the two slice
+// workspace regions, in a file-scope device array (each device that runs the
+// library holds its own copy until the process ends). Host code uses the
+// address hipGetSymbolAddress returns on each device, never this name.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 struct slicq_plan_s {
   slicq::Plan p;
   std::vector<unsigned char> blob[2];   // packed tables, kept alive for async uploads
@@ -263,6 +270,31 @@ int with_server(slicq_stream_server s, F&& fn) {
 
 }  // namespace
 
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SLICQ_EINVAL, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SLICQ_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int slicq_stream_server_create(slicq_plan plan, slicq_dtype dt, int32_t max_streams, int32_t max_batch,
@@ -478,6 +510,7 @@ int nsgt_plan_ex(const slicq_plan_opts* o, slicq_plan* out) {
   if (o->lds_cap) pp.lds_cap = o->lds_cap;
   if (o->pass_cap) pp.pass_cap = o->pass_cap;
   pp.coef_layout = o->coef_layout;
+  pp.fused = o->unfused ? 0 : 1;
   slicq_plan h = new (std::nothrow) slicq_plan_s;
   if (!h) return fail(SLICQ_ENOMEM, "out of host memory");
   std::string err;
@@ -526,6 +559,7 @@ int nsgt_plan_info(slicq_plan plan, slicq_plan_info* info) {
   info->n_ana_items = (int32_t)p.ana.size();
   info->n_syn_items = (int32_t)p.syn.size();
   info->coef_layout = p.prm.coef_layout;
+  info->fused = (p.fused[0].ok ? 1 : 0) | (p.fused[1].ok ? 2 : 0);
   return SLICQ_OK;
 }
 
@@ -607,6 +641,38 @@ int slicq_analyze(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, voi
   slicq::WorkLayout w;
   if ((rc = layout_or_fail(p, dt, S, work_bytes, w))) return rc;
   char* wk = static_cast<char*>(work);
+  auto* tasks = reinterpret_cast<slicq::SliceTask*>(wk + w.tasks_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  plain_tasks(p, T, S, tasks, st);
+  return dt == SLICQ_F32 ? run_analysis<float>(p, dt, tasks, S, x, coef, w, wk, st)
+                         : run_analysis<double>(p, dt, tasks, S, x, coef, w, wk, st);
+}
+
+
+size_t slicq_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int slicq_analyze_static(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, void* coef, int64_t coef_count,
+                         void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (T < 0) return fail(SLICQ_EINVAL, "T must be >= 0");
+  const int64_t S = slices_of(p, T);
+  if (S == 0) return SLICQ_OK;
+  if ((rc = check_signal_size(p, T))) return rc;
+  if (!x || !coef) return fail(SLICQ_EINVAL, "null buffer");
+  if (coef_count < S * p.coefs_per_slice) return fail(SLICQ_ESIZE, "coef_count < S * coefs_per_slice");
+  // the task table of all S slices and the scratch of at least one slice must fit
+  slicq::WorkLayout w;
+  if (!slicq::work_layout(p, dt, S, kStaticScratchBytes, w)) {
+    char b[200];
+    std::snprintf(b, sizeof b, "the static scratch (%zu bytes) cannot hold the tasks of %lld slices and one slice's "
+                  "workspace; use slicq_analyze with a caller workspace", kStaticScratchBytes, (long long)S);
+    return fail(SLICQ_ESIZE, b);
+  }
+  void* base = nullptr;
+  if ((rc = static_scratch(&base))) return rc;
+  char* wk = static_cast<char*>(base);
   auto* tasks = reinterpret_cast<slicq::SliceTask*>(wk + w.tasks_off);
   hipStream_t st = static_cast<hipStream_t>(stream);
   plain_tasks(p, T, S, tasks, st);
@@ -773,6 +839,16 @@ static int profile_stage_impl(slicq::Plan& p, slicq_dtype dt, int stage, int64_t
     C2<T>* W1 = reinterpret_cast<C2<T>*>(wk + w.w1_off);
     C2<T>* W2 = reinterpret_cast<C2<T>*>(wk + w.w2_off);
     const int64_t n = n_slices;
+    if (a.fused) {
+      // one workgroup per slice: stage 0 runs the fused analysis, 3 the fused
+      // synthesis (whole slices), 5 the overlap fix-up; the others are empty
+      a.task0 = 0;
+      a.task1 = n;
+      if (stage == 0) launch_ana_fused(p, a, tasks, n, static_cast<const T*>(x), static_cast<C2<T>*>(coef), L);
+      else if (stage == 3) launch_syn_fused(p, a, tasks, n, (const C2<T>*)coef, W2, static_cast<T*>(y), L);
+      else if (stage == 5) launch_ola_fix(a, tasks, n, (const C2<T>*)W2, static_cast<T*>(y), L);
+      return;
+    }
     switch (stage) {
       case 0: L.launch(k_fwd_pass1<T, true>, n * g.g1, g.b1, g.s1, a, tasks, static_cast<const T*>(x), W1); break;
       case 1: L.launch(k_fwd_pass2<T, true>, n * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2); break;

@@ -4,6 +4,17 @@
 
 namespace slicq {
 
+// LDS arrays of the kernels hold one pad slot every 2^kPadShift complex
+// values (bank spreading for the strided Stockham stores; one pad per 8
+// values measured no faster than one per 16): padded(n) slots hold n values.
+constexpr int kPadShift = 4;
+constexpr int padded(int n) { return n + (n >> kPadShift) + 1; }
+
+// Entries of the split twiddle tables for transforms up to 2^L (two levels
+// of the pyramid, 2^(L - L/2) and 2^L: every e^{-2 pi i k / 2^l}, l <= L, is
+// a product of one entry of each).
+constexpr int split_tw_entries(int L) { return (1 << (L - (L >> 1))) + (1 << (L >> 1)); }
+
 // One slice to process: where its 2N input samples come from, where its
 // coefficients go and where its overlap-added output goes. Sample j of the
 // slice (j < 2N, window position t = j - N) reads x[x_base + idx] with
@@ -90,8 +101,38 @@ constexpr int kPow8Entries = 7 * 8 + 7 * 64;
 
 struct TableLayout {
   uint64_t tw, tw8, h0, hd, g, gd, bands, ana, syn, runs;
-  uint64_t ola_syn, ola_adj, ent_off, ent_pos, ent_wsyn, ent_wadj, total;
+  uint64_t ola_syn, ola_adj, ent_off, ent_pos, ent_wsyn, ent_wadj;
+  uint64_t fana, fsyn, fola_syn, fola_adj, fent_off, fent_pos, fent_wsyn, fent_wadj;
+  uint64_t total;
 };
+
+// Fused per-slice work item, for plans whose half spectrum fits in one
+// workgroup's LDS: one block runs the whole analysis (or synthesis) of a
+// slice, its LDS holding an index space [0, cap) whose indices 0..N hold the
+// half spectrum. Item: bands k0 .. k0 + cnt - 1 (equal M_k) transformed at
+// indices lds .. lds + cnt M - 1, either past the spectrum (lds = N + 1) or
+// over spectrum bins no later item reads (analysis, in increasing k) or
+// writes before it (synthesis, in decreasing k). Synthesis items add their
+// bands into bins [olo, ohi] through records rec0 .. rec0 + ohi - olo.
+struct alignas(16) FusedItemDev {
+  int32_t k0, cnt, M, logM;
+  int32_t lds, olo, ohi, rec0;
+};
+
+// Frequency overlap-add record of one bin of a fused synthesis item: LDS
+// indices x0 | x1 << 16 of the first two entries (bit 15: further entries
+// follow in the overflow table; bit 31: this item is the first to write the
+// bin, which it sets instead of adding to), mirror indices y0 | y1 << 16
+// (0xffff: none) and the two weights.
+template <class T>
+struct alignas(16) FOlaRec {
+  uint32_t xx, yy;
+  T w0, w1;
+};
+constexpr uint32_t kFMore = 0x8000u, kFInit = 0x80000000u, kFPos = 0x7fffu;
+constexpr int kFusedThreads = 1024;     // block of the fused kernels
+constexpr int kFusedE = 8;              // values per thread of a fused item's band FFT
+constexpr int kFusedMaxItem = kFusedThreads * kFusedE;
 
 // The first two overlap-add entries of a bin, read with one load: positions
 // x0 | x1 << 16 (bit 15 set when the bin has further entries), mirror

@@ -45,10 +45,8 @@ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 __device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
-// LDS index with one pad slot every 2^kPadShift complex values (bank
-// spreading for the strided Stockham stores; one pad per 8 values measured no
-// faster than one per 16).
-constexpr int kPadShift = 4;
+// LDS index with one pad slot every 2^kPadShift complex values (kPadShift
+// and padded() in common.hpp).
 __device__ __forceinline__ int pidx(int i) { return i + (i >> kPadShift); }
 
 // Lanes per wavefront (CDNA): blocks are one-dimensional, so the lanes of a
@@ -61,7 +59,6 @@ constexpr int kWave = 64;
 __device__ __forceinline__ bool wave_has(int tid, int n) {
   return __builtin_amdgcn_readfirstlane(tid & ~(kWave - 1)) < n;
 }
-__host__ __device__ constexpr int padded(int n) { return n + (n >> kPadShift) + 1; }
 
 // e^{DIR 2 pi i k / R} for small constant R, as constants.
 template <class T, int R, int DIR>
@@ -183,7 +180,6 @@ struct TwBand {
 
 // Entries of the TwBand tables for transforms up to 2^L (the split tables,
 // then, with P8, the radix-8 rows).
-__host__ __device__ constexpr int split_tw_entries(int L) { return (1 << (L - (L >> 1))) + (1 << (L >> 1)); }
 __host__ __device__ constexpr int band_tw_entries(int L, bool p8) {
   return split_tw_entries(L) + (p8 ? kPow8Entries : 0);
 }

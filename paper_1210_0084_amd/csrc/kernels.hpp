@@ -86,6 +86,16 @@ struct KArgs {
   // (the time overlap-add needs to know which neighbouring slices come first)
   int64_t task0, task1;
   T scale;                // (2N)^{-1/2}
+  // fused per-slice schedule (valid when fused != 0): items, overlap-add
+  // records of the synthesis items (dual or, for the adjoint, analysis weights)
+  const FusedItemDev* fana;
+  const FusedItemDev* fsyn;
+  const FOlaRec<T>* fola;
+  const int32_t* fent_off;
+  const int2* fent_pos;
+  const T* fent_w;
+  int32_t fused, nfana, nfsyn, flogM;
+  int32_t fcap, pad3_;
 };
 
 // Byte offset, 16-byte aligned, just past `values` padded complex values in LDS.

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "fused.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -101,6 +102,18 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
   a.scale = (T)(1.0 / std::sqrt((double)p.two_n));
   a.slice_major = p.prm.coef_layout;
   a.cps = (int32_t)p.coefs_per_slice;
+  const FusedPlan& f = p.fused[dtype];
+  a.fused = f.ok ? 1 : 0;
+  a.fana = reinterpret_cast<const FusedItemDev*>(base + L.fana);
+  a.fsyn = reinterpret_cast<const FusedItemDev*>(base + L.fsyn);
+  a.fola = reinterpret_cast<const FOlaRec<T>*>(base + (adjoint ? L.fola_adj : L.fola_syn));
+  a.fent_off = reinterpret_cast<const int32_t*>(base + L.fent_off);
+  a.fent_pos = reinterpret_cast<const int2*>(base + L.fent_pos);
+  a.fent_w = reinterpret_cast<const T*>(base + (adjoint ? L.fent_wadj : L.fent_wsyn));
+  a.nfana = (int32_t)f.ana.size();
+  a.nfsyn = (int32_t)f.syn.size();
+  a.flogM = f.logM;
+  a.fcap = f.cap;
   return a;
 }
 
@@ -219,38 +232,84 @@ void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* t
   }
 }
 
+// One workgroup per slice (fused.hpp): analysis of cnt tasks.
+template <class T, class Launch>
+void launch_ana_fused(const Plan& p, const KArgs<T>& a, const SliceTask* tasks, int64_t cnt, const T* x, C2<T>* coef,
+                      Launch& L) {
+  const FusedPlan& f = p.fused[sizeof(T) == 8 ? 1 : 0];
+  switch (ilog2i(p.N)) {
+    case 5: L.launch(k_ana_fused<T, 5>, cnt, f.nthr, f.lds_bytes, a, tasks, x, coef); break;
+    case 6: L.launch(k_ana_fused<T, 6>, cnt, f.nthr, f.lds_bytes, a, tasks, x, coef); break;
+    case 12: L.launch(k_ana_fused<T, 12>, cnt, f.nthr, f.lds_bytes, a, tasks, x, coef); break;
+    case 13: L.launch(k_ana_fused<T, 13>, cnt, f.nthr, f.lds_bytes, a, tasks, x, coef); break;
+    default: L.launch(k_ana_fused<T, 14>, cnt, f.nthr, f.lds_bytes, a, tasks, x, coef); break;
+  }
+}
+
+// One workgroup per slice: synthesis (or adjoint) of cnt tasks, before the overlap fix-up.
+template <class T, class Launch>
+void launch_syn_fused(const Plan& p, const KArgs<T>& a, const SliceTask* tasks, int64_t cnt, const C2<T>* coef,
+                      C2<T>* W2, T* y, Launch& L) {
+  const FusedPlan& f = p.fused[sizeof(T) == 8 ? 1 : 0];
+  switch (ilog2i(p.N)) {
+    case 5: L.launch(k_syn_fused<T, 5>, cnt, f.nthr, f.lds_bytes, a, tasks, coef, W2, y); break;
+    case 6: L.launch(k_syn_fused<T, 6>, cnt, f.nthr, f.lds_bytes, a, tasks, coef, W2, y); break;
+    case 12: L.launch(k_syn_fused<T, 12>, cnt, f.nthr, f.lds_bytes, a, tasks, coef, W2, y); break;
+    case 13: L.launch(k_syn_fused<T, 13>, cnt, f.nthr, f.lds_bytes, a, tasks, coef, W2, y); break;
+    default: L.launch(k_syn_fused<T, 14>, cnt, f.nthr, f.lds_bytes, a, tasks, coef, W2, y); break;
+  }
+}
+
 // Analysis of tasks [t0, t0 + cnt) (Algorithm 3): slice FFT, band transforms.
 template <class T, class Launch>
 void launch_analysis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks,
                      int64_t cnt, const T* x, C2<T>* coef, C2<T>* W1, C2<T>* W2, Launch& L) {
+  if (a.fused) {
+    launch_ana_fused(p, a, tasks, cnt, x, coef, L);
+    return;
+  }
   L.launch(k_fwd_pass1<T, true>, cnt * g.g1, g.b1, g.s1, a, tasks, x, W1);
   L.launch(k_fwd_pass2<T, true>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W1, W2);
   launch_band_ana(a, g, tasks, cnt, (const C2<T>*)W2, coef, L);
-  (void)p;
 }
 
 // Inverse pass B of tasks [t0, t0 + cnt) of the call's task table (tasks
 // points at task t0), then the second contributions of the shared samples.
+template <class T, class Launch>
+void launch_ola_fix(const KArgs<T>& a, const SliceTask* tasks, int64_t cnt, const C2<T>* W2, T* y, Launch& L) {
+  const int nov = ola_count(a.N, a.Mt);
+  if (nov > 0) L.launch(k_ola_fix<T>, cnt * 2 * ((nov + kOlaFixRun - 1) / kOlaFixRun), 256, 0, a, tasks, W2, y);
+}
+
 template <class T, class Launch>
 void launch_inv_passB(const KArgs<T>& a0, const Geometry<T>& g, const SliceTask* tasks, int64_t t0, int64_t cnt,
                       C2<T>* W1, C2<T>* W2, T* y, Launch& L) {
   KArgs<T> a = a0;
   a.task0 = t0;
   a.task1 = t0 + cnt;
+  if (a.fused) {
+    launch_ola_fix(a, tasks, cnt, (const C2<T>*)W2, y, L);     // the fused synthesis wrote the overlap buffers
+    return;
+  }
   L.launch(k_inv_passB<T, true>, cnt * g.g1, g.b1, g.s1, a, tasks, (const C2<T>*)W1, W2, y);
-  const int nov = ola_count(a.N, a.Mt);
-  if (nov > 0)
-    L.launch(k_ola_fix<T>, cnt * 2 * ((nov + kOlaFixRun - 1) / kOlaFixRun), 256, 0, a, tasks, (const C2<T>*)W2, y);
+  launch_ola_fix(a, tasks, cnt, (const C2<T>*)W2, y, L);
 }
 
 // Synthesis (or adjoint) of tasks [t0, t0 + cnt) (Algorithm 4); tasks points at task t0.
 template <class T, class Launch>
-void launch_synthesis(const Plan& p, const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t t0,
+void launch_synthesis(const Plan& p, const KArgs<T>& a0, const Geometry<T>& g, const SliceTask* tasks, int64_t t0,
                       int64_t cnt, const C2<T>* coef, T* y, C2<T>* W1, C2<T>* W2, Launch& L) {
-  launch_band_syn(a, g, tasks, cnt, coef, W2, y, L);
-  L.launch(k_inv_passA<T, true>, cnt * g.g2, g.b2, g.s2, a, (const C2<T>*)W2, W1);
-  launch_inv_passB(a, g, tasks, t0, cnt, W1, W2, y, L);
-  (void)p;
+  if (a0.fused) {
+    KArgs<T> a = a0;
+    a.task0 = t0;
+    a.task1 = t0 + cnt;
+    launch_syn_fused(p, a, tasks, cnt, coef, W2, y, L);
+    launch_ola_fix(a, tasks, cnt, (const C2<T>*)W2, y, L);
+    return;
+  }
+  launch_band_syn(a0, g, tasks, cnt, coef, W2, y, L);
+  L.launch(k_inv_passA<T, true>, cnt * g.g2, g.b2, g.s2, a0, (const C2<T>*)W2, W1);
+  launch_inv_passB(a0, g, tasks, t0, cnt, W1, W2, y, L);
 }
 
 }  // namespace slicq

@@ -21,6 +21,7 @@ namespace slicq {
 
 namespace {
 
+constexpr size_t kMaxLdsBytesPlan = 160 * 1024;   // LDS of one gfx950 workgroup
 
 int64_t next_pow2(int64_t n) {
   int64_t p = 1;
@@ -124,6 +125,128 @@ std::vector<OlaRec<T>> ola_records(const Plan& p, const std::vector<double>& w) 
     r[j].w1 = (T)w[2 * j + 1];
   }
   return r;
+}
+
+// Fused per-slice schedule for one dtype (cb bytes per complex value): the
+// half spectrum X[0..N] at LDS indices 0..N, band items in increasing k
+// (analysis) and decreasing k (synthesis), each placed at index 0 when it
+// fits below every bin its item and the items after it touch (the spectrum
+// bins there are dead in analysis and not yet written in synthesis), else
+// past the spectrum. ok stays false when the spectrum and the largest item do
+// not fit one workgroup's LDS.
+void build_fused(const Plan& p, int dtype, FusedPlan& f) {
+  f = FusedPlan();
+  const int64_t N = p.N;
+  const int logN = ilog2(N);
+  if (!p.prm.fused || N < 32 || N > 16384) return;
+  if (!(logN == 5 || logN == 6 || (logN >= 12 && logN <= 14))) return;   // compiled slice lengths
+  const size_t cb = dtype ? 16 : 8;
+  const int nb = (int)p.bands.size();
+  f.logM = ilog2(p.max_M);
+  const size_t tw_bytes = (size_t)(split_tw_entries(logN) + split_tw_entries(std::max(f.logM, 1))) * cb;
+  if (tw_bytes + 64 >= kMaxLdsBytesPlan) return;
+  // largest index space whose padded array fits beside the twiddle tables
+  int64_t cap = (int64_t)((kMaxLdsBytesPlan - tw_bytes - 64) / cb);
+  while (cap > 0 && (size_t)padded((int)cap) * cb + tw_bytes + 64 > kMaxLdsBytesPlan) --cap;
+  if (cap < N + 1) return;
+  const int64_t tail = cap - (N + 1);
+  // lowest half-spectrum bin read (analysis) or written (synthesis) by bands >= k
+  std::vector<int64_t> sufmin(nb + 1, N + 1);
+  for (int k = nb - 1; k >= 0; --k) sufmin[k] = std::min<int64_t>(sufmin[k + 1], p.bands[k].hlo);
+  int64_t used = N + 1;
+  auto room = [&](int64_t bottom) { return std::min<int64_t>(kFusedMaxItem, std::max(bottom, tail)); };
+  // analysis: increasing k
+  for (int k = 0; k < nb;) {
+    const int32_t M = p.bands[k].M;
+    const int64_t r = room(sufmin[k]);
+    if (M > r) return;
+    int cnt = 1;
+    while (k + cnt < nb && p.bands[k + cnt].M == M && (int64_t)(cnt + 1) * M <= r && cnt < kMaxGroupBands) ++cnt;
+    FusedItemDev it{};
+    it.k0 = k;
+    it.cnt = cnt;
+    it.M = M;
+    it.logM = p.bands[k].logM;
+    it.lds = (int64_t)cnt * M <= sufmin[k] ? 0 : (int32_t)(N + 1);
+    used = std::max<int64_t>(used, it.lds + (int64_t)cnt * M);
+    f.ana.push_back(it);
+    k += cnt;
+  }
+  // synthesis: decreasing k; the bound of an item is set by its lowest band
+  std::vector<char> written(N + 1, 0);
+  f.ent_off.clear();
+  for (int k = nb - 1; k >= 0;) {
+    const int32_t M = p.bands[k].M;
+    if (M > room(sufmin[k])) return;
+    int cnt = 1;
+    while (k - cnt >= 0 && p.bands[k - cnt].M == M && (int64_t)(cnt + 1) * M <= room(sufmin[k - cnt]) &&
+           cnt < kMaxGroupBands)
+      ++cnt;
+    const int kl = k - cnt + 1;
+    FusedItemDev it{};
+    it.k0 = kl;
+    it.cnt = cnt;
+    it.M = M;
+    it.logM = p.bands[kl].logM;
+    it.lds = (int64_t)cnt * M <= sufmin[kl] ? 0 : (int32_t)(N + 1);
+    used = std::max<int64_t>(used, it.lds + (int64_t)cnt * M);
+    int32_t olo = (int32_t)N, ohi = 0;
+    for (int b = kl; b <= k; ++b) {
+      olo = std::min(olo, p.bands[b].hlo);
+      ohi = std::max(ohi, p.bands[b].hhi);
+    }
+    it.olo = olo;
+    it.ohi = ohi;
+    it.rec0 = (int32_t)f.rec_xx.size();
+    for (int64_t j = olo; j <= ohi; ++j) {
+      struct E { int32_t x, y; double ws, wa; };
+      std::vector<E> ent;
+      for (int b = kl; b <= k; ++b) {            // increasing k: a fixed summation order
+        const BandInfo& bi = p.bands[b];
+        if (j < bi.hlo || j > bi.hhi) continue;
+        const int64_t pos = it.lds + (int64_t)(b - kl) * M;
+        const bool selfmirror = (b == 0 || b == p.K + 1);
+        const int64_t t = j - bi.start;
+        E e;
+        e.x = (int32_t)(pos + (j & (M - 1)));
+        e.y = selfmirror ? (int32_t)(pos + ((-j) & (M - 1))) : -1;
+        e.ws = (selfmirror ? 0.5 : 1.0) * p.gd[bi.goff + t];
+        e.wa = 0.5 * p.g[bi.goff + t];
+        ent.push_back(e);
+      }
+      const bool init = !written[j];
+      written[j] = 1;
+      const int32_t x0 = ent.empty() ? (int32_t)it.lds : ent[0].x;
+      const int32_t x1 = ent.size() > 1 ? ent[1].x : x0;
+      auto y16 = [](int32_t y) { return y < 0 ? 0xffffu : (uint32_t)y; };
+      f.rec_xx.push_back((uint32_t)x0 | ((uint32_t)x1 << 16) | (ent.size() > 2 ? kFMore : 0u) | (init ? kFInit : 0u));
+      f.rec_yy.push_back(y16(ent.empty() ? -1 : ent[0].y) | (y16(ent.size() > 1 ? ent[1].y : -1) << 16));
+      f.rec_ws.push_back(ent.empty() ? 0.0 : ent[0].ws);
+      f.rec_ws.push_back(ent.size() > 1 ? ent[1].ws : 0.0);
+      f.rec_wa.push_back(ent.empty() ? 0.0 : ent[0].wa);
+      f.rec_wa.push_back(ent.size() > 1 ? ent[1].wa : 0.0);
+      f.ent_off.push_back((int32_t)f.ent_ws.size());
+      for (size_t q = 2; q < ent.size(); ++q) {
+        f.ent_pos.push_back(ent[q].x);
+        f.ent_pos.push_back(ent[q].y);
+        f.ent_ws.push_back(ent[q].ws);
+        f.ent_wa.push_back(ent[q].wa);
+      }
+    }
+    f.syn.push_back(it);
+    k = kl - 1;
+  }
+  f.ent_off.push_back((int32_t)f.ent_ws.size());
+  for (int64_t j = 0; j <= N; ++j)
+    if (!written[j]) return;                  // every bin must be set by some item
+  if (used > kFPos) return;                   // LDS indices must fit the records' 15 bits
+  f.cap = (int32_t)used;
+  int64_t need = N / (logN >= 14 ? 16 : 8);    // slice FFT: 16 values per thread at 2^14 points, else 8
+  for (const FusedItemDev& it : f.ana) need = std::max<int64_t>(need, ((int64_t)it.cnt * it.M + kFusedE - 1) / kFusedE);
+  for (const FusedItemDev& it : f.syn) need = std::max<int64_t>(need, ((int64_t)it.cnt * it.M + kFusedE - 1) / kFusedE);
+  f.nthr = (int32_t)std::min<int64_t>(kFusedThreads, std::max<int64_t>(64, (need + 63) / 64 * 64));
+  f.lds_bytes = ((size_t)padded(f.cap) * cb + 15) / 16 * 16 + tw_bytes;
+  f.ok = f.lds_bytes <= kMaxLdsBytesPlan;
 }
 
 }  // namespace
@@ -491,6 +614,8 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     }
   }
   out.ent_off[N + 1] = (int32_t)out.ent_wsyn.size();
+  build_fused(out, 0, out.fused[0]);
+  build_fused(out, 1, out.fused[1]);
   return 0;
 }
 
@@ -580,6 +705,42 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
     lay.ola_adj = append(blob, ra.data(), ra.size());
     lay.ent_wsyn = append(blob, ews.data(), ews.size());
     lay.ent_wadj = append(blob, ewa.data(), ewa.size());
+  }
+  // fused per-slice schedule of this dtype (tables with at least one element each)
+  {
+    const FusedPlan& f = p.fused[dtype];
+    std::vector<FusedItemDev> fa = f.ana, fs = f.syn;
+    if (fa.empty()) fa.resize(1);
+    if (fs.empty()) fs.resize(1);
+    lay.fana = append(blob, fa.data(), fa.size());
+    lay.fsyn = append(blob, fs.data(), fs.size());
+    std::vector<int32_t> eo = f.ent_off, ep = f.ent_pos;
+    std::vector<double> ws = f.ent_ws, wa = f.ent_wa;
+    if (eo.empty()) eo = {0};
+    if (ws.empty()) { ep = {0, -1}; ws = {0.0}; wa = {0.0}; }
+    lay.fent_off = append(blob, eo.data(), eo.size());
+    lay.fent_pos = append(blob, ep.data(), ep.size());
+    const size_t nrec = std::max<size_t>(f.rec_xx.size(), 1);
+    auto recs = [&](const std::vector<double>& w, auto tag) {
+      using T = decltype(tag);
+      std::vector<FOlaRec<T>> r(nrec);
+      for (size_t i = 0; i < f.rec_xx.size(); ++i) r[i] = {f.rec_xx[i], f.rec_yy[i], (T)w[2 * i], (T)w[2 * i + 1]};
+      return r;
+    };
+    if (dtype == 0) {
+      const std::vector<FOlaRec<float>> rs = recs(f.rec_ws, 0.0f), ra = recs(f.rec_wa, 0.0f);
+      lay.fola_syn = append(blob, rs.data(), rs.size());
+      lay.fola_adj = append(blob, ra.data(), ra.size());
+      std::vector<float> wsf(ws.begin(), ws.end()), waf(wa.begin(), wa.end());
+      lay.fent_wsyn = append(blob, wsf.data(), wsf.size());
+      lay.fent_wadj = append(blob, waf.data(), waf.size());
+    } else {
+      const std::vector<FOlaRec<double>> rs = recs(f.rec_ws, 0.0), ra = recs(f.rec_wa, 0.0);
+      lay.fola_syn = append(blob, rs.data(), rs.size());
+      lay.fola_adj = append(blob, ra.data(), ra.size());
+      lay.fent_wsyn = append(blob, ws.data(), ws.size());
+      lay.fent_wadj = append(blob, wa.data(), wa.size());
+    }
   }
   blob.resize((blob.size() + 255) & ~size_t(255));
   lay.total = blob.size();

@@ -21,6 +21,23 @@ struct PlanParams {
   int32_t lds_cap = 4096;       // target complex values per synthesis work item
   int32_t pass_cap = 4096;      // complex values per four-step FFT work item
   int32_t coef_layout = 0;      // 0: band-major, 1: slice-major
+  int32_t fused = 1;            // 1: one workgroup per slice where the half spectrum fits in LDS, 0: never
+};
+
+// The fused per-slice schedule of one dtype (see FusedItemDev).
+struct FusedPlan {
+  bool ok = false;
+  int32_t cap = 0;              // LDS indices used (spectrum, scratch)
+  int32_t nthr = 0;             // threads per block
+  int32_t logM = 0;             // log2 of the largest M_k (band twiddle tables)
+  size_t lds_bytes = 0;         // dynamic LDS per block
+  std::vector<FusedItemDev> ana, syn;
+  // overlap-add records of the synthesis items (positions and both weight sets)
+  std::vector<uint32_t> rec_xx, rec_yy;
+  std::vector<double> rec_ws, rec_wa;   // two per record
+  std::vector<int32_t> ent_off;         // per record, then the end
+  std::vector<int32_t> ent_pos;         // pairs (x, y)
+  std::vector<double> ent_ws, ent_wa;
 };
 
 struct BandInfo {
@@ -69,6 +86,7 @@ struct Plan {
   int32_t ana_maxM_small = 0, syn_maxM_small = 0;   // largest M_k in the small items
   int32_t N1 = 0, N2 = 0, logN1 = 0, logN2 = 0;
   int32_t C = 0, P = 0;                 // columns per pass-1 item, row pairs per pass-2 item
+  FusedPlan fused[2];                   // per dtype (0: f32, 1: f64)
 
   // device tables, per dtype (0: f32, 1: f64); owned by the caller
   std::mutex mu;

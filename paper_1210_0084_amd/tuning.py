@@ -1,9 +1,12 @@
 """Work-item autotuner and HIP-graph capture for batched sliCQ calls.
 
-The plan's tuning options choose how the kernels cut the work: the number of
-coefficients per analysis work item (``group_cap``), the target complex values
-per synthesis work item (``lds_cap``), the values per slice-FFT work
-item (``pass_cap``) and the coefficient layout. ``autotune`` times every
+The plan's tuning options choose how the kernels cut the work: whether each
+slice runs in one workgroup (``fused``: half spectrum and band transforms in
+LDS, where they fit) or through the multi-kernel pipeline, and for the
+pipeline the number of coefficients per analysis work item (``group_cap``),
+the target complex values per synthesis work item (``lds_cap``) and the values
+per slice-FFT work item (``pass_cap``), which set the block sizes and the
+radix schedules of the band and slice transforms. ``autotune`` times every
 candidate on the caller's batch shape with HIP events (content does not
 change the time of the transform) and returns the fastest, cached on disk
 per (plan parameters, dtype, batch shape, device).
@@ -15,8 +18,8 @@ import json
 import os
 from typing import Dict, Optional, Sequence
 
-CANDIDATES = [
-    dict(group_cap=g, pass_cap=p, lds_cap=l, layout="band")
+CANDIDATES = [dict(fused=True, layout="band")] + [
+    dict(fused=False, group_cap=g, pass_cap=p, lds_cap=l, layout="band")
     for g in (1024, 2048, 4096)
     for p in (2048, 4096)
     for l in (2048, 4096, 8192)
@@ -59,6 +62,8 @@ def autotune(params: dict, lengths: Sequence[int], dtype: str = "f32", cache: Op
             plan = Plan(**params, **cand)
         except SlicqError:
             continue
+        if cand.get("fused") and (0 if dtype == "f32" else 1) not in plan.fused_dtypes:
+            continue                          # the slice does not fit one workgroup: same as a pipeline candidate
         lay = plan.batch_layout(lengths)
         coef = torch.empty(max(lay.coef_len, 1), dtype=ctype, device=dev)
         for _ in range(2):

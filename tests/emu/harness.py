@@ -19,8 +19,8 @@ CSRC = os.path.join(ROOT, "paper_1210_0084_amd", "csrc")
 BUILD = os.path.join(HERE, "_build")
 EXE = os.path.join(BUILD, "emu_runner")
 SOURCES = [os.path.join(HERE, "emu_runner.cpp"), os.path.join(CSRC, "plan.cpp")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "plan.hpp", "common.hpp",
-                                            "stream_server.hpp")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "fft_device.hpp", "fused.hpp", "pipeline.hpp", "plan.hpp",
+                                            "common.hpp", "stream_server.hpp")]
 STREAM_EXE = os.path.join(BUILD, "stream_runner")
 
 
@@ -68,8 +68,9 @@ def stream(plan: dict, signals, hop: int, dtype: int = 1, mode: int = 0, max_str
 
 
 def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,
-        group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: int = 0) -> np.ndarray:
-    """Runs one emulated transform; returns the raw float64 output."""
+        group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: int = 0, fused: int = 0) -> np.ndarray:
+    """fused = 1 asks for the one-workgroup-per-slice kernels (the runner fails
+    if they do not fit the plan), 0 for the multi-kernel pipeline."""
     exe = build()
     with tempfile.TemporaryDirectory() as td:
         fin = os.path.join(td, "in.bin")
@@ -78,9 +79,9 @@ def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,
         args = [exe, op, str(dtype), repr(float(plan["fs"])), repr(float(plan["fmin"])), repr(float(plan["fmax"])),
                 str(plan["bins_per_octave"]), str(plan["slice_len"]), str(plan["transition"]),
                 repr(float(plan.get("min_win", 16.0))), str(plan.get("dual", 0)), str(group_cap), str(lds_cap),
-                str(pass_cap), str(chunk), str(layout), fin, fout]
+                str(pass_cap), str(chunk), str(layout), str(int(fused)), fin, fout]
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
-        r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=600)
+        r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=900)
         if r.returncode != 0:
             raise RuntimeError(f"emu_runner failed ({r.returncode}): {r.stderr[-3000:]}")
         return np.fromfile(fout, dtype=np.float64)

@@ -21,55 +21,72 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("dtype", [1, 0])
-@pytest.mark.parametrize("kw,T", [(TINY, 1), (TINY, 100), (TINY2, 300), (SIXTEEN, 37)])
-def test_emu_roundtrip_and_adjoint(kw, T, dtype):
+@pytest.mark.parametrize("kw,T,fused", [(TINY, 1, 0), (TINY, 100, 0), (TINY2, 300, 0), (SIXTEEN, 37, 0),
+                                        (TINY, 1, 1), (TINY, 100, 1), (TINY2, 300, 1)])
+def test_emu_roundtrip_and_adjoint(kw, T, fused, dtype):
+    # fused = 1: one workgroup per slice (half spectrum and band transforms in LDS)
     pl = OraclePlan(**kw)
     x = np.random.default_rng(T).standard_normal(T)
     c_ref = analyze(pl, x)
     ref = pack(pl, c_ref)
-    assert rel(H.analyze(kw, x, dtype), ref) <= TOL[dtype]
-    assert rel(H.synthesize(kw, ref, T, dtype), x) <= TOL[dtype]
+    assert rel(H.analyze(kw, x, dtype, fused=fused), ref) <= TOL[dtype]
+    assert rel(H.synthesize(kw, ref, T, dtype, fused=fused), x) <= TOL[dtype]
     g = np.random.default_rng(T + 1)
     cr = g.standard_normal(len(ref)) + 1j * g.standard_normal(len(ref))
     S = num_slices(T, pl.two_n)
-    assert rel(H.synthesize(kw, cr, T, dtype, adjoint=True), adjoint(pl, unpack(pl, cr, S), T)) <= TOL[dtype]
-    assert rel(H.synthesize(kw, cr, T, dtype), synthesize(pl, unpack(pl, cr, S), T)) <= TOL[dtype]
+    assert rel(H.synthesize(kw, cr, T, dtype, adjoint=True, fused=fused),
+               adjoint(pl, unpack(pl, cr, S), T)) <= TOL[dtype]
+    assert rel(H.synthesize(kw, cr, T, dtype, fused=fused), synthesize(pl, unpack(pl, cr, S), T)) <= TOL[dtype]
 
 
-def test_emu_chunked_and_batched():
+class _Path:
+    """The harness calls with the kernel path chosen (fused = 1: one workgroup per slice)."""
+
+    def __init__(self, fused):
+        self.analyze = lambda *a, **k: H.analyze(*a, fused=fused, **k)
+        self.synthesize = lambda *a, **k: H.synthesize(*a, fused=fused, **k)
+        self.analyze_batched = lambda *a, **k: H.analyze_batched(*a, fused=fused, **k)
+        self.synthesize_batched = lambda *a, **k: H.synthesize_batched(*a, fused=fused, **k)
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_emu_chunked_and_batched(fused):
     kw = TINY
+    E = _Path(fused)
     pl = OraclePlan(**kw)
     x = np.random.default_rng(5).standard_normal(500)
     ref = pack(pl, analyze(pl, x))
-    assert rel(H.analyze(kw, x, 1, chunk=3), ref) < 1e-12
-    assert rel(H.synthesize(kw, ref, 500, 1, chunk=3), x) < 1e-12
+    assert rel(E.analyze(kw, x, 1, chunk=3), ref) < 1e-12
+    assert rel(E.synthesize(kw, ref, 500, 1, chunk=3), x) < 1e-12
     # one slice per chunk: every shared output sample has its two slices in
     # different launches, the first slice's left neighbour (the last slice,
     # circularly) in a later one; two slices share both of their overlaps
-    assert rel(H.synthesize(kw, ref, 500, 1, chunk=1), x) < 1e-12
+    assert rel(E.synthesize(kw, ref, 500, 1, chunk=1), x) < 1e-12
     x2 = np.random.default_rng(6).standard_normal(64)
     r2 = pack(pl, analyze(pl, x2))
     assert num_slices(64, pl.two_n) == 2
-    assert rel(H.synthesize(kw, r2, 64, 1, chunk=1), x2) < 1e-12
-    assert rel(H.synthesize(kw, r2, 64, 0, chunk=1), x2) < 1e-5
+    assert rel(E.synthesize(kw, r2, 64, 1, chunk=1), x2) < 1e-12
+    assert rel(E.synthesize(kw, r2, 64, 0, chunk=1), x2) < 1e-5
     xs = [np.random.default_rng(i).standard_normal(n) for i, n in enumerate([100, 0, 64, 257])]
-    cb = H.analyze_batched(kw, xs, 1)
+    cb = E.analyze_batched(kw, xs, 1)
     refb = np.concatenate([pack(pl, analyze(pl, v)) for v in xs if len(v)])
     assert rel(cb, refb) < 1e-12
-    yb = H.synthesize_batched(kw, refb, [len(v) for v in xs], 1)
+    yb = E.synthesize_batched(kw, refb, [len(v) for v in xs], 1)
     assert rel(yb, np.concatenate(xs)) < 1e-12
 
 
+@pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("kw", [C4, C5], ids=["c4", "c5"])
-def test_emu_preset_shapes(kw):
+def test_emu_preset_shapes(kw, fused):
     # one pair of slices at full slice length: large band groups (M_k = 8192 in c4),
-    # many overlapping narrow bands (c5), both thread-count variants of the band kernels
+    # many overlapping narrow bands (c5), both thread-count variants of the band
+    # kernels; fused = 1: one workgroup per slice, its spectrum and scratch in LDS
     pl = OraclePlan(**kw)
     T = 9000
     x = np.random.default_rng(3).standard_normal(T)
     ref = pack(pl, analyze(pl, x))
-    assert rel(H.analyze(kw, x, 0), ref) <= 1e-5
-    assert rel(H.synthesize(kw, ref, T, 0), x) <= 1e-5
+    assert rel(H.analyze(kw, x, 0, fused=fused), ref) <= 1e-5
+    assert rel(H.synthesize(kw, ref, T, 0, fused=fused), x) <= 1e-5
 
 
 def test_emu_slice_major_layout():

@@ -71,7 +71,8 @@ _plans = {}
 def gpu_plan(sq, kw):
     key = tuple(sorted(kw.items()))
     if key not in _plans:
-        _plans[key] = (sq.Plan(**kw), OraclePlan(**kw))
+        okw = {k: v for k, v in kw.items() if k != "fused"}
+        _plans[key] = (sq.Plan(**kw), OraclePlan(**okw))
     return _plans[key]
 
 
@@ -114,11 +115,37 @@ def test_c1_full(sq, dev, dt):
     check_roundtrip(sq, dev, preset("c1"), make_c1(), dt)
 
 
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "pipeline"])
 @pytest.mark.parametrize("name,T", [("c3", 100000), ("c4", 264600), ("c5", 60000), ("c2", 150000)])
-def test_preset_shapes_f32(sq, dev, name, T):
+def test_preset_shapes_f32(sq, dev, name, T, fused):
+    # fused: one workgroup per slice where the half spectrum fits in LDS (2N <=
+    # 32768 in FP32); pipeline: the multi-kernel path (the only one for c2)
     p = PRESETS[name]
     x = pink_plus_tones(T, p.fs, 77) if name != "c4" else noise_plus_sines(T, p.fs, 5)
-    check_roundtrip(sq, dev, preset(name), x, "f32", check_adjoint=(name == "c4"))
+    kw = dict(preset(name), fused=fused)
+    plan, _ = gpu_plan(sq, kw)
+    assert (0 in plan.fused_dtypes) == (fused and name != "c2")
+    check_roundtrip(sq, dev, kw, x, "f32", check_adjoint=(name in ("c4", "c5")))
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_fused_and_pipeline_agree(sq, dev, dt):
+    # the two kernel paths compute the same transform (to rounding): 2N = 8192
+    # fits one workgroup in both FP32 and FP64
+    import torch
+    kw = preset("c1")
+    fused = sq.Plan(**kw)
+    pipe = sq.Plan(**kw, fused=False)
+    assert {0, 1} <= fused.fused_dtypes and not pipe.fused_dtypes
+    x = torch.tensor(noise_plus_sines(50000, 44100.0, 12), dtype=torch_dtype(dt), device=dev)
+    cf, cp = fused.analyze(x), pipe.analyze(x)
+    yf, yp = fused.synthesize(cf, 50000), pipe.synthesize(cp, 50000)
+    af, ap = fused.adjoint(cf, 50000), pipe.adjoint(cp, 50000)
+    torch.cuda.synchronize()
+    t = TOL[dt]
+    assert rel(cf.cpu().numpy(), cp.cpu().numpy()) <= t
+    assert rel(yf.cpu().numpy(), yp.cpu().numpy()) <= t
+    assert rel(af.cpu().numpy(), ap.cpu().numpy()) <= t
 
 
 OPTION_SETS = [
@@ -136,7 +163,7 @@ def test_tuning_options(sq, dev, opts, name, T, dt):
     import torch
     kw = preset(name)
     _, opl = gpu_plan(sq, kw)
-    plan = sq.Plan(**kw, **opts)
+    plan = sq.Plan(**kw, **opts, fused=False)     # the options cut the pipeline's work items
     print(f"case {name} T={T} {dt} {opts}", flush=True)
     x = pink_plus_tones(T, kw["fs"], 91)
     c_ref = analyze(opl, x)

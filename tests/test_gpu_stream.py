@@ -98,13 +98,13 @@ def test_alone_equals_in_the_mix_bitwise(sq, plan):
 def test_admission_by_memory_budget(sq, plan):
     # every device buffer counts against the budget: per stream two rings of
     # 4N float32 samples plus its 4N-sample share of the staging buffer (and
-    # two 16-byte copy records); fixed: the workspace and coefficients of
+    # two 32-byte copy records); fixed: the workspace and coefficients of
     # max_batch slices
     import torch
     probe = sq.StreamServer(plan, "f32", max_streams=1, max_batch=8)
     st0 = probe.stats()
     per, fixed = st0["bytes_per_stream"], st0["fixed_bytes"]
-    assert per == 3 * 4 * plan.N * 4 + 32
+    assert per == 3 * 4 * plan.N * 4 + 64
     assert fixed >= plan.workspace_bytes(0, 8) + 8 * plan.coefs_per_slice * 8
     del probe
     torch.cuda.synchronize()
