@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -454,6 +455,55 @@ def bench_stream(args):
             "device_bytes": {"per_stream": un["bytes_per_stream"], "fixed": un["fixed_bytes"]}}
 
 
+def bench_approx(args):
+    """Section 5.3's approximation study: SNR of the sliCQ layer sum s^0 + s^1
+    (GPU, FP32: complex analysis onto all bands, then the layer kernel)
+    against the full-length CQ-NSGT on the same Blackman-Harris band windows
+    (FP64 oracle, rescaled by sqrt(2N / L)), for slice lengths 4096, 16384 and
+    65536, transitions 1/4 and 1/128 of the slice, minimal filter lengths 4,
+    8, 16 and 32 bins; random complex signals of 2^20 samples (the paper's
+    Set 1, seeded). Mean and spread over the signals."""
+    import torch
+    import paper_1210_0084_amd as sq
+    from oracle import OraclePlan
+    from oracle.fullnsgt import full_length_bands, nsgt_full, snr_db
+    dev = torch.device("cuda:0")
+    L = 1 << args.approx_log2_len
+    sigs = []
+    for s in range(args.approx_signals):
+        g = np.random.default_rng(100 + s)
+        sigs.append(g.standard_normal(L) + 1j * g.standard_normal(L))
+    table = []
+    full_cache = {}
+    t0 = time.perf_counter()
+    for two_n in (4096, 16384, 65536):
+        for frac in (4, 128):
+            for mw in (4, 8, 16, 32):
+                kw = dict(fs=44100.0, fmin=200.0, fmax=22000.0, bins_per_octave=48, slice_len=two_n,
+                          transition=two_n // frac, window="blackman_harris", min_win=float(mw))
+                plan = sq.Plan(**kw)
+                opl = OraclePlan(**kw)
+                r = math.sqrt(two_n / L)
+                snrs = []
+                for si, f in enumerate(sigs):
+                    key = (two_n, mw, si)
+                    if key not in full_cache:         # the full-length transform does not depend on M
+                        full_cache[key] = nsgt_full(full_length_bands(opl, L, all_bands=False), f)
+                    cf = full_cache[key]
+                    c = plan.analyze_complex(torch.tensor(f, dtype=torch.complex64, device=dev))
+                    S = plan.num_slices(L)
+                    ls = plan.layers(c[:S * plan.coefs_per_slice], S).cpu().numpy().astype(np.complex128)
+                    approx = [ls[(S // 2) * off:(S // 2) * (off + b.M)] for off, b in zip(opl.offsets, opl.bands)]
+                    snrs.append(snr_db([r * x for x in cf], approx))
+                table.append({"slice_len": two_n, "transition": two_n // frac, "min_win": mw,
+                              "snr_db_mean": round(float(np.mean(snrs)), 2),
+                              "snr_db_spread": round(float(np.max(snrs) - np.min(snrs)), 3)})
+                print(json.dumps(table[-1]), file=sys.stderr, flush=True)
+    return {"workload": "approximation study (Section 5.3): sliCQ s^0+s^1 on the GPU vs full-length CQ-NSGT (FP64)",
+            "signals": args.approx_signals, "length": L, "bins_per_octave": 48, "fmin": 200.0,
+            "window": "blackman_harris", "seconds": round(time.perf_counter() - t0, 1), "table": table}
+
+
 def _form_summary(rec):
     """The key figures of a form's record, for the default line."""
     keep = {k: rec[k] for k in ("value", "unit", "ms_per_step") if k in rec}
@@ -476,9 +526,11 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (scale for HBM byte counters)")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "approx"], default="c2",
                     help="c2 (default): 60 s stereo; c3: ragged batch in a HIP graph; c4: differentiable; "
-                         "c5: streaming service")
+                         "c5: streaming service; approx: the Section 5.3 approximation study")
+    ap.add_argument("--approx-signals", type=int, default=3)
+    ap.add_argument("--approx-log2-len", type=int, default=20)
     ap.add_argument("--c3-signals", type=int, default=256)
     ap.add_argument("--c3-tune", action="store_true", help="autotune the ragged batch's work items first")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
@@ -492,7 +544,7 @@ def main():
         sys.exit(2)
 
     if args.workload != "c2":
-        fn = {"c3": bench_batched, "c4": bench_differentiable, "c5": bench_stream}[args.workload]
+        fn = {"c3": bench_batched, "c4": bench_differentiable, "c5": bench_stream, "approx": bench_approx}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 

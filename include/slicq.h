@@ -76,6 +76,18 @@ typedef struct {
                                into its bins may exceed it, up to 16384 */
   int32_t pass_cap;         /* tuning: complex values per slice-FFT work item (power of two), default 4096 */
   int32_t coef_layout;      /* SLICQ_BAND_MAJOR (0) or SLICQ_SLICE_MAJOR (1), see below */
+  int32_t window;           /* band window on |x| < 1/2: 0 Hann (default), 1 Blackman-Harris
+                               (4 terms, the window of the approximation study, Section 5.3) */
+  int32_t scale;            /* centre frequencies: 0 constant-Q (geometric, Section 3), 1 mel, 2 Bark
+                               (Section 7): as many bands as constant-Q would place between fmin and
+                               fmax, equally spaced on the scale, bandwidth = distance of the two
+                               neighbouring centres (xi_k / Q for constant-Q) */
+  int32_t slicing;          /* slicing window: 0 Tukey with sum_m h_m = 1 (default), 1 its square root,
+                               sum_m h_m^2 = 1, so that the same windows serve in the overlap-add
+                               (the other design of Section 4.3) */
+  int32_t m_policy;         /* coefficients per band: 0 the smallest power of two >= |J_k| (default),
+                               1 one M for every band, the largest of those (the rectangular
+                               representation of Section 6) */
   int32_t unfused;          /* 0 (default): where a slice's half spectrum and its largest band
                                transform fit one workgroup's LDS, each slice's analysis (and
                                synthesis) runs in one workgroup with no intermediate in HBM;
@@ -96,6 +108,7 @@ typedef struct {
   int32_t n_syn_items;      /* synthesis work items per slice */
   int32_t coef_layout;      /* SLICQ_BAND_MAJOR or SLICQ_SLICE_MAJOR */
   int32_t fused;            /* bit d set: dtype d (SLICQ_F32 = 0, SLICQ_F64 = 1) runs one workgroup per slice */
+  int64_t coefs_per_slice_all;  /* sum_k M_k over all 2K+2 bands (complex-signal calls) */
 } slicq_plan_info;
 
 /* Design a plan from the paper's parameters (Section 3, Table 1; Section
@@ -180,6 +193,57 @@ int slicq_synthesize(slicq_plan plan, slicq_dtype dtype, const void* coef, int64
  * slicq_analyze for the real inner product. Same arguments as synthesis. */
 int slicq_adjoint(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t coef_count, void* y,
                   int64_t T, void* work, size_t work_bytes, void* hip_stream);
+
+/* Adjoint of synthesis (the gradient of a loss of the synthesised signal with
+ * respect to the coefficients, for the real inner products): with w_k = 2 on
+ * bands 1..K (each also synthesises through its conjugate mirror) and 1 on the
+ * DC and Nyquist bands, coef = w_k <y, gamma_k> for the dual atoms gamma_k of
+ * Algorithm 4 (dual windows g~_k = g_k / D of Proposition 2, dual slicing
+ * window h~_0 of equation dualwincond): the analysis of y (T real samples)
+ * with h~_0 in place of h_0 and w_k g~_k in place of g_k. Arguments as for
+ * slicq_analyze. */
+int slicq_synthesize_adjoint(slicq_plan plan, slicq_dtype dtype, const void* y, int64_t T, void* coef,
+                             int64_t coef_count, void* work, size_t work_bytes, void* hip_stream);
+
+/* Complex signals (the transform of Sections 2-4 before the restriction to
+ * real signals): analysis onto all 2K+2 bands, band-major in the order
+ * 0..K+1 (the stored bands, same offsets as for real signals) then the
+ * mirrored bands K+2..2K+1 (band 2K+2-k has M_k coefficients per slice),
+ * slicq_plan_info.coefs_per_slice_all per slice. x and y are T complex values
+ * of the dtype, interleaved. The transform is complex linear: analysis runs
+ * the real analysis on the real and imaginary parts and combines them
+ * (mirror bands take conj c_k(Re x) + i conj c_k(Im x)); synthesis splits the
+ * coefficients into the two Hermitian-symmetric sets whose real syntheses are
+ * the real and imaginary parts of y. The workspace (at least
+ * slicq_complex_workspace_size bytes) holds the real workspace, the two parts
+ * and two coefficient sets. Band-major plans only (SLICQ_EINVAL otherwise). */
+int slicq_complex_workspace_size(slicq_plan plan, slicq_dtype dtype, int64_t T, size_t* bytes);
+int slicq_analyze_complex(slicq_plan plan, slicq_dtype dtype, const void* x, int64_t T, void* coef,
+                          int64_t coef_count, void* work, size_t work_bytes, void* hip_stream);
+int slicq_synthesize_complex(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t coef_count, void* y,
+                             int64_t T, void* work, size_t work_bytes, void* hip_stream);
+
+/* Coefficient domain (Algorithm 3's 2-layer array; Sections 4.3 and 6), for
+ * the coefficients of one signal of S (even) slices in the plan's layout.
+ * Slice m's coefficients of band k belong to layer m mod 2 at positions
+ * (m - 1) M_k / 2 + n, n < M_k, circular modulo S M_k / 2. Layer-grid arrays
+ * are band-major: band k's S M_k / 2 values start at (S / 2) off_k.
+ * slicq_layers writes s^0 + s^1 (mode 0, complex) or the sliCQ spectrogram
+ * |s^0 + s^1|^2 (mode 1, real) into out ((S / 2) coefs_per_slice values).
+ * slicq_mask_db scales every coefficient in place by 10^{5 (v - 1)}, v in
+ * [0, 1] the mask value of its layer position (mask on the layer grid: 0 is
+ * -100 dB, 1 is 0 dB; one value serves both layers). slicq_transpose writes
+ * out band t = in band t - d for constant-Q bands 1..K (d bands up: 8 bands
+ * are 2 semitones at 48 bands per octave), zero for vacated bands and for the
+ * DC and Nyquist bands; every moved band must have the M_k of its target
+ * (SLICQ_EINVAL otherwise: use m_policy 1 or a shift inside a run of equal
+ * M_k). in and out must not alias. */
+int slicq_layers(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t S, int mode, void* out,
+                 int64_t out_count, void* hip_stream);
+int slicq_mask_db(slicq_plan plan, slicq_dtype dtype, void* coef, int64_t S, const void* mask, int64_t mask_count,
+                  void* hip_stream);
+int slicq_transpose(slicq_plan plan, slicq_dtype dtype, const void* in, void* out, int64_t S, int32_t d,
+                    void* hip_stream);
 
 /* Ragged batches. Signal b holds samples x_off[b] .. x_off[b+1]-1 of the
  * packed x (x_off: nsig + 1 int64 in device memory, x_len = packed length)

@@ -18,6 +18,10 @@ Layout
 ``brute``      the plain definitions: atoms T_{n a_k} F^{-1} g_k, coefficients
                as inner products (equation CQ_coeff), the dense frame operator
                (equation frameop) and dual atoms (equation candual).
+``layers``     the 2-layer array of Algorithm 3, the sliCQ spectrogram, dB
+               masks and band transposition (Sections 4.3 and 6).
+``fullnsgt``   the full-length CQ-NSGT on the same band windows, the SNR of
+               Section 5.3 and the bound of Proposition 4.
 
 Every function that has no independent pin says "parity unpinned" in its
 docstring; all functions here are pinned by tests under ``tests/`` marked
@@ -26,5 +30,6 @@ docstring; all functions here are pinned by tests under ``tests/`` marked
 from .plan import OraclePlan, BandTable, plan_from_tables, q_factor  # noqa: F401
 from .transform import (analyze, synthesize, adjoint, analyze_full, synthesize_full,  # noqa: F401
                         num_slices, padded_length, analyze_stream, synthesize_stream, pack, unpack,
-                        analyze_slices, synthesize_slices)
+                        analyze_slices, synthesize_slices, synthesize_adjoint, pack_full, unpack_full)
+from . import layers, fullnsgt  # noqa: F401
 from . import brute  # noqa: F401

@@ -48,6 +48,41 @@ def q_factor(B: int) -> float:
     return 1.0 / (2.0 ** (1.0 / B) - 2.0 ** (-1.0 / B))
 
 
+# Nonlinear frequency scales (Section 7 names mel and Bark as the obvious
+# generalisations): a scale maps Hz to a unit in which the centre frequencies
+# are equally spaced. Constant-Q is log2 (equally spaced in octaves).
+def _mel(f):
+    return 2595.0 * math.log10(1.0 + f / 700.0)
+
+
+def _mel_inv(u):
+    return 700.0 * (10.0 ** (u / 2595.0) - 1.0)
+
+
+def _bark(f):
+    # Traunmueller's critical-band rate
+    return 26.81 * f / (1960.0 + f) - 0.53
+
+
+def _bark_inv(z):
+    return 1960.0 * (z + 0.53) / (26.28 - z)
+
+
+SCALES = {"mel": (_mel, _mel_inv), "bark": (_bark, _bark_inv)}
+
+
+def window_value(kind: str, x: float) -> float:
+    """Frequency window shape on |x| < 1/2 (x in units of the bandwidth):
+    Hann (the configurations) or the 4-term Blackman-Harris window the paper
+    uses for its approximation study (Section 5.3)."""
+    if kind == "hann":
+        return 0.5 + 0.5 * math.cos(2.0 * math.pi * x)
+    if kind == "blackman_harris":
+        return (0.35875 + 0.48829 * math.cos(2.0 * math.pi * x) + 0.14128 * math.cos(4.0 * math.pi * x)
+                + 0.01168 * math.cos(6.0 * math.pi * x))
+    raise ValueError("window is 'hann' or 'blackman_harris'")
+
+
 def _next_pow2(n: int) -> int:
     return 1 << (max(n, 1) - 1).bit_length()
 
@@ -106,7 +141,8 @@ class OraclePlan:
 
     def __init__(self, fs: float, fmin: float, fmax: float, bins_per_octave: int,
                  slice_len: int, transition: int, min_win: float = 16.0,
-                 dual_slice: str = "canonical"):
+                 dual_slice: str = "canonical", window: str = "hann", scale: str = "cq",
+                 slicing: str = "tukey", m_policy: str = "pow2"):
         fs = float(fs)
         fmin = float(fmin)
         fmax = float(fmax)
@@ -122,6 +158,14 @@ class OraclePlan:
             raise ValueError("transition M needs 0 < M < N and N - M even")
         if dual_slice not in ("canonical", "indicator"):
             raise ValueError("dual_slice is 'canonical' or 'indicator'")
+        window_value(window, 0.0)
+        if scale not in ("cq", "mel", "bark"):
+            raise ValueError("scale is 'cq', 'mel' or 'bark'")
+        if slicing not in ("tukey", "sqrt_tukey"):
+            raise ValueError("slicing is 'tukey' or 'sqrt_tukey'")
+        if m_policy not in ("pow2", "rect"):
+            raise ValueError("m_policy is 'pow2' or 'rect'")
+        self.window, self.scale, self.slicing, self.m_policy = window, scale, slicing, m_policy
         self.fs, self.fmin, self.fmax, self.B = fs, fmin, fmax, B
         self.two_n, self.N, self.M = two_n, N, Mt
         self.min_win = float(min_win)
@@ -131,8 +175,19 @@ class OraclePlan:
         # --- centres and bandwidths (Table 1; readings on K and min_win) ---
         K0 = 1 + math.ceil(B * math.log2(fmax / fmin) - 1e-12)
         bw_min = self.min_win * fs / two_n
-        xi = [fmin * 2.0 ** ((k - 1) / B) for k in range(1, K0 + 1)]
-        om = [max(x / self.Q, bw_min) for x in xi]
+        if scale == "cq":
+            xi = [fmin * 2.0 ** ((k - 1) / B) for k in range(1, K0 + 1)]
+            om = [max(x / self.Q, bw_min) for x in xi]
+        else:
+            # as many bands as constant-Q would place, equally spaced on the
+            # scale from fmin to fmax; the bandwidth is the distance between
+            # the two neighbouring centres, which for constant-Q is xi_k / Q
+            fwd, inv = SCALES[scale]
+            u0, u1 = fwd(fmin), fwd(fmax)
+            du = (u1 - u0) / max(K0 - 1, 1)
+            ext = [inv(u0 + (k - 1) * du) for k in range(0, K0 + 2)]   # xi_0 .. xi_{K0+1}
+            xi = ext[1:K0 + 1]
+            om = [max(ext[k + 1] - ext[k - 1], bw_min) for k in range(1, K0 + 1)]
         K = K0
         while K >= 1 and not (xi[K - 1] + om[K - 1] / 2 < fs / 2):
             K -= 1
@@ -147,13 +202,20 @@ class OraclePlan:
         R0 = xi[0]
         w0 = min(om[0] / 2, R0)
         bands.append(self._plateau_band(0, 0, R0, w0, 0.0, 2.0 * xi[0]))
-        # constant-Q bands 1..K, Hann
+        # constant-Q bands 1..K
         for k in range(1, K + 1):
             bands.append(self._hann_band(k, xi[k - 1], om[k - 1]))
+
         # Nyquist band: plateau around N of radius fs/2 - xi_K
         RN = fs / 2 - xi[K - 1]
         wN = min(om[K - 1] / 2, RN)
         bands.append(self._plateau_band(K + 1, N, RN, wN, fs / 2, fs - 2 * xi[K - 1]))
+        if m_policy == "rect":
+            # rectangular representation (Section 6): one M for every band,
+            # the smallest power of two that holds the widest support
+            Mr = max(b.M for b in bands)
+            for b in bands:
+                b.M = Mr
         # validity of the real-signal band layout
         for b in bands:
             if b.length == 0:
@@ -175,6 +237,8 @@ class OraclePlan:
 
     # -- band constructors ---------------------------------------------------
     def _hann_band(self, k, xi_k, om_k) -> BandTable:
+        """Band k: the window shape (Hann unless ``window`` says otherwise) on
+        the open interval |nu - xi_k| < Omega_k / 2."""
         fs, two_n = self.fs, self.two_n
 
         def x_of(j):
@@ -190,8 +254,7 @@ class OraclePlan:
         if iv is None:
             return BandTable(k, 0, np.zeros(0), 2, xi=xi_k, omega=om_k)
         a, b = iv
-        x = np.array([x_of(j) for j in range(a, b + 1)])
-        g = 0.5 + 0.5 * np.cos(2.0 * math.pi * x)
+        g = np.array([window_value(self.window, x_of(j)) for j in range(a, b + 1)])
         return BandTable(k, a, g, max(2, _next_pow2(b - a + 1)), xi=xi_k, omega=om_k)
 
     def _plateau_band(self, k, centre_bin, R, w, xi_hz, om_hz) -> BandTable:
@@ -230,6 +293,10 @@ class OraclePlan:
         h = np.where(a <= flat, 1.0,
                      np.where(a < (N + Mt) / 2,
                               0.5 + 0.5 * np.cos(math.pi * (a - flat) / Mt), 0.0))
+        if getattr(self, "slicing", "tukey") == "sqrt_tukey":
+            # the other slicing design of Section 4.3: sum_m h_m^2 = 1, so the
+            # same windows serve in the overlap-add (the canonical dual is h_0)
+            h = np.sqrt(h)
         self.h0 = h
         if self.dual_slice == "indicator":
             self.hd = (h != 0).astype(np.float64)

@@ -167,6 +167,54 @@ def adjoint(plan, c, T: int) -> np.ndarray:
     return out[:T]
 
 
+def synthesize_adjoint(plan, y, T: int) -> List[np.ndarray]:
+    """Adjoint of ``synthesize`` for the real inner products (the gradient of
+    a loss of the synthesised signal with respect to the coefficients).
+
+    Synthesis writes y = sum_k w_k Re(c_k gamma_k) over the stored bands,
+    with gamma_k the dual atoms (dual windows g~_k on the 2N grid, dual
+    slicing window h~_0, Algorithms 2 and 4) and w_k = 2 for bands 1..K
+    (each also synthesises through its conjugate mirror) and 1 for the
+    self-mirrored DC and Nyquist bands. Its transpose maps y to
+    w_k <y, gamma_k>: the analysis of y (Algorithm 3 with Algorithm 1) with
+    h~_0 in place of h_0 and g~_k in place of g_k, times w_k.
+    """
+    two_n, N = plan.two_n, plan.N
+    y = np.asarray(y, dtype=np.float64)
+    L = padded_length(T, two_n)
+    S = 2 * L // two_n
+    yp = np.zeros(L)
+    yp[:len(y)] = y
+    out = [np.zeros((S, b.M), dtype=np.complex128) for b in plan.bands]
+    scale = 1.0 / math.sqrt(two_n)
+    K = plan.K
+    for m in range(S):
+        Y = np.fft.fft(yp[_slice_index(m, N, L)] * plan.hd) * scale
+        for kk, b in enumerate(plan.bands):
+            j = b.bins()
+            buf = np.zeros(b.M, dtype=np.complex128)
+            buf[j % b.M] = Y[j % two_n] * b.gd
+            w = 1.0 if kk in (0, K + 1) else 2.0
+            out[kk][m] = w * np.fft.ifft(buf) * b.M
+    return out
+
+
+def pack_full(plan, c) -> np.ndarray:
+    """Band-major packing over every band of the plan (stored bands 0..K+1,
+    then the mirrors K+2..2K+1): the layout of the complex-signal transform."""
+    return np.concatenate([ck.reshape(-1) for ck in c])
+
+
+def unpack_full(plan, flat, S: int) -> List[np.ndarray]:
+    out = []
+    pos = 0
+    for b in plan.all_bands:
+        n = S * b.M
+        out.append(np.asarray(flat[pos:pos + n]).reshape(S, b.M))
+        pos += n
+    return out
+
+
 def pack(plan, c) -> np.ndarray:
     """Band-major packing: band k, slice m, index n at S*off_k + m*M_k + n."""
     return np.concatenate([ck.reshape(-1) for ck in c])

@@ -18,8 +18,8 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Plan", "SliCQFunction", "slicq", "library_path", "SlicqError", "SlicqBusy", "StreamServer",
-           "load_library"]
+__all__ = ["Plan", "SliCQFunction", "SliCQSynthesisFunction", "slicq", "islicq", "library_path", "SlicqError",
+           "SlicqBusy", "StreamServer", "load_library"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libslicq.so")
@@ -52,14 +52,16 @@ class _Opts(ctypes.Structure):
                 ("transition_len", ctypes.c_int64), ("min_win", ctypes.c_double),
                 ("dual_slice", ctypes.c_int32), ("group_cap", ctypes.c_int32),
                 ("lds_cap", ctypes.c_int32), ("pass_cap", ctypes.c_int32), ("coef_layout", ctypes.c_int32),
-                ("unfused", ctypes.c_int32)]
+                ("window", ctypes.c_int32), ("scale", ctypes.c_int32), ("slicing", ctypes.c_int32),
+                ("m_policy", ctypes.c_int32), ("unfused", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("nbands", ctypes.c_int32), ("slice_len", ctypes.c_int64),
                 ("transition_len", ctypes.c_int64), ("coefs_per_slice", ctypes.c_int64),
                 ("Q", ctypes.c_double), ("max_M", ctypes.c_int32), ("n_ana_items", ctypes.c_int32),
-                ("n_syn_items", ctypes.c_int32), ("coef_layout", ctypes.c_int32), ("fused", ctypes.c_int32)]
+                ("n_syn_items", ctypes.c_int32), ("coef_layout", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("coefs_per_slice_all", ctypes.c_int64)]
 
 
 def library_path() -> str:
@@ -95,6 +97,13 @@ def load_library():
         "slicq_synthesize_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_adjoint_batched": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, I64, P, I32, I64, P, SZ, P]),
         "slicq_profile_stage": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, I64, P, P, P, P, SZ, P]),
+        "slicq_synthesize_adjoint": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_complex_workspace_size": (ctypes.c_int, [P, ctypes.c_int, I64, ctypes.POINTER(SZ)]),
+        "slicq_analyze_complex": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_synthesize_complex": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P, SZ, P]),
+        "slicq_layers": (ctypes.c_int, [P, ctypes.c_int, P, I64, ctypes.c_int, P, I64, P]),
+        "slicq_mask_db": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P]),
+        "slicq_transpose": (ctypes.c_int, [P, ctypes.c_int, P, P, I64, I32, P]),
         "slicq_batched_status": (ctypes.c_int, [P, ctypes.c_int, I64, P, SZ, ctypes.POINTER(I32),
                                                 ctypes.POINTER(I64), P]),
         "slicq_batch_tasks_bytes": (SZ, [I64]),
@@ -232,11 +241,14 @@ class Plan:
     def __init__(self, fs: float, fmin: float, fmax: float, bins_per_octave: int, slice_len: int,
                  transition: int, min_win: float = 16.0, dual_slice: str = "canonical",
                  group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: str = "band",
-                 fused: bool = True):
+                 fused: bool = True, window: str = "hann", scale: str = "cq", slicing: str = "tukey",
+                 m_policy: str = "pow2"):
         lib = load_library()
         o = _Opts(float(fs), float(fmin), float(fmax), int(bins_per_octave), int(slice_len), int(transition),
                   float(min_win), {"canonical": 0, "indicator": 1}[dual_slice], int(group_cap), int(lds_cap),
-                  int(pass_cap), {"band": 0, "slice": 1}[layout], 0 if fused else 1)
+                  int(pass_cap), {"band": 0, "slice": 1}[layout],
+                  {"hann": 0, "blackman_harris": 1}[window], {"cq": 0, "mel": 1, "bark": 2}[scale],
+                  {"tukey": 0, "sqrt_tukey": 1}[slicing], {"pow2": 0, "rect": 1}[m_policy], 0 if fused else 1)
         h = ctypes.c_void_p()
         _check(lib.nsgt_plan_ex(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -255,6 +267,7 @@ class Plan:
         self.n_syn_items = info.n_syn_items
         self.layout = "slice" if info.coef_layout == 1 else "band"
         self.fused_dtypes = {d for d, bit in ((F32, 1), (F64, 2)) if info.fused & bit}
+        self.coefs_per_slice_all = info.coefs_per_slice_all
         self.fs, self.fmin, self.fmax, self.bins_per_octave = float(fs), float(fmin), float(fmax), int(bins_per_octave)
         nb = self.nbands
         self.M = np.zeros(nb, dtype=np.int32)
@@ -406,6 +419,129 @@ class Plan:
     def adjoint(self, coef, T: int, out=None, work=None):
         """Re(A^H coef): the transpose of ``analyze`` for the real inner product."""
         return self._synth(coef, T, True, out, work)
+
+    def synthesize_adjoint(self, y, out=None, work=None):
+        """Adjoint of ``synthesize`` (coefficient gradient of a loss of the
+        synthesised signal): the analysis of y with the dual windows."""
+        torch = _torch()
+        _require_cuda(y, "y")
+        dt = _dtype_code(y)
+        T = y.numel()
+        S = self.num_slices(T)
+        if out is None:
+            out = torch.empty(S * self.coefs_per_slice, dtype=torch.complex64 if dt == F32 else torch.complex128,
+                              device=y.device)
+        _require_cuda(out, "out")
+        self._ensure_tables(dt, y.device)
+        w, wb = self._workspace(dt, S, y.device, work)
+        _check(self._lib.slicq_synthesize_adjoint(self._h, dt, ctypes.c_void_p(y.data_ptr()), T,
+                                                  ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                                  ctypes.c_void_p(w.data_ptr()), wb,
+                                                  ctypes.c_void_p(_stream_ptr(y.device))))
+        self._note_tasks(dt, y.device, S, work)
+        return out
+
+    # -- complex signals ------------------------------------------------------
+    def _complex_work(self, dt, T, device):
+        torch = _torch()
+        b = ctypes.c_size_t()
+        _check(self._lib.slicq_complex_workspace_size(self._h, dt, int(T), ctypes.byref(b)))
+        key = ("complex", dt, str(device))
+        w = self._work.get(key)
+        if w is None or w.numel() < b.value:
+            w = torch.empty(max(b.value, 1), dtype=torch.uint8, device=device)
+            self._work[key] = w
+        return w
+
+    def analyze_complex(self, x, out=None):
+        """Coefficients of a complex signal on all 2K+2 bands (stored bands,
+        then the mirrors K+2..2K+1), band-major."""
+        torch = _torch()
+        _require_cuda(x, "x")
+        if not x.is_complex():
+            raise SlicqError("x must be complex")
+        dt = _dtype_code(x)
+        T = x.numel()
+        S = self.num_slices(T)
+        if out is None:
+            out = torch.empty(S * self.coefs_per_slice_all, dtype=x.dtype, device=x.device)
+        self._ensure_tables(dt, x.device)
+        w = self._complex_work(dt, T, x.device)
+        _check(self._lib.slicq_analyze_complex(self._h, dt, ctypes.c_void_p(x.data_ptr()), T,
+                                               ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                               ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                               ctypes.c_void_p(_stream_ptr(x.device))))
+        return out
+
+    def synthesize_complex(self, coef, T: int, out=None):
+        """Complex signal of T samples from coefficients on all 2K+2 bands."""
+        torch = _torch()
+        _require_cuda(coef, "coef")
+        dt = _dtype_code(coef)
+        if out is None:
+            out = torch.empty(int(T), dtype=coef.dtype, device=coef.device)
+        self._ensure_tables(dt, coef.device)
+        w = self._complex_work(dt, T, coef.device)
+        _check(self._lib.slicq_synthesize_complex(self._h, dt, ctypes.c_void_p(coef.data_ptr()), coef.numel(),
+                                                  ctypes.c_void_p(out.data_ptr()), int(T),
+                                                  ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                                  ctypes.c_void_p(_stream_ptr(coef.device))))
+        return out
+
+    # -- coefficient domain (2-layer array, spectrogram, masks, transposition) --
+    def layer_views(self, coef, k: int, S: int):
+        """Zero-copy (S/2, M_k) views of band k's even and odd slices (band-major
+        plans): layer 1 is the odd slices in order; layer 0 is the even slices,
+        whose flattened layer position is the view's flat index minus M_k / 2
+        (circularly), as Algorithm 3 places them."""
+        b = self.band(coef, k, S)
+        return b[0::2], b[1::2]
+
+    def layers(self, coef, S: int, spectrogram: bool = False, out=None):
+        """s^0 + s^1 (complex) or the sliCQ spectrogram |s^0 + s^1|^2 (real)
+        on the layer grid, band k's S M_k / 2 values at (S / 2) off_k."""
+        torch = _torch()
+        _require_cuda(coef, "coef")
+        dt = _dtype_code(coef)
+        n = (S // 2) * self.coefs_per_slice
+        if out is None:
+            rt = (torch.float32 if dt == F32 else torch.float64) if spectrogram else coef.dtype
+            out = torch.empty(max(n, 1), dtype=rt, device=coef.device)
+        self._ensure_tables(dt, coef.device)
+        _check(self._lib.slicq_layers(self._h, dt, ctypes.c_void_p(coef.data_ptr()), int(S), 1 if spectrogram else 0,
+                                      ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                      ctypes.c_void_p(_stream_ptr(coef.device))))
+        return out
+
+    def layer_band(self, grid, k: int, S: int):
+        """Band k's S M_k / 2 values of a layer-grid array."""
+        off, Mk = int(self.offsets[k]), int(self.M[k])
+        return grid[(S // 2) * off:(S // 2) * (off + Mk)]
+
+    def mask_db(self, coef, S: int, mask):
+        """In place: coef scaled by 10^{5 (v - 1)} of the mask value v of its
+        layer position (mask on the layer grid, values in [0, 1])."""
+        _require_cuda(coef, "coef")
+        _require_cuda(mask, "mask")
+        dt = _dtype_code(coef)
+        self._ensure_tables(dt, coef.device)
+        _check(self._lib.slicq_mask_db(self._h, dt, ctypes.c_void_p(coef.data_ptr()), int(S),
+                                       ctypes.c_void_p(mask.data_ptr()), mask.numel(),
+                                       ctypes.c_void_p(_stream_ptr(coef.device))))
+        return coef
+
+    def transpose(self, coef, S: int, d: int, out=None):
+        """Constant-Q bands moved up by d (8 bands = 2 semitones at 48 per octave)."""
+        torch = _torch()
+        _require_cuda(coef, "coef")
+        dt = _dtype_code(coef)
+        if out is None:
+            out = torch.empty_like(coef)
+        self._ensure_tables(dt, coef.device)
+        _check(self._lib.slicq_transpose(self._h, dt, ctypes.c_void_p(coef.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), int(S), int(d),
+                                         ctypes.c_void_p(_stream_ptr(coef.device))))
+        return out
 
     # -- ragged batches -----------------------------------------------------
     def batch_layout(self, lengths: Sequence[int]) -> BatchLayout:
@@ -662,18 +798,43 @@ def _make_function():
     return SliCQFunction
 
 
-_SliCQFunction = None
+def _make_synthesis_function():
+    torch = _torch()
+
+    class SliCQSynthesisFunction(torch.autograd.Function):
+        """Differentiable synthesis: forward = slicq_synthesize (coefficients to
+        a real signal of T samples), backward = slicq_synthesize_adjoint (the
+        dual-window analysis), for losses on the synthesised audio."""
+
+        @staticmethod
+        def forward(ctx, coef, plan, T):
+            ctx.plan, ctx.T = plan, int(T)
+            return plan.synthesize(coef.contiguous(), int(T))
+
+        @staticmethod
+        def backward(ctx, grad):
+            return ctx.plan.synthesize_adjoint(grad.contiguous()), None, None
+
+    return SliCQSynthesisFunction
+
+
+_FUNCS = {}
 
 
 def __getattr__(name):
-    global _SliCQFunction
-    if name == "SliCQFunction":
-        if _SliCQFunction is None:
-            _SliCQFunction = _make_function()
-        return _SliCQFunction
+    makers = {"SliCQFunction": _make_function, "SliCQSynthesisFunction": _make_synthesis_function}
+    if name in makers:
+        if name not in _FUNCS:
+            _FUNCS[name] = makers[name]()
+        return _FUNCS[name]
     raise AttributeError(name)
 
 
 def slicq(x, plan: Plan):
     """Differentiable sliCQ analysis (see SliCQFunction)."""
     return __getattr__("SliCQFunction").apply(x, plan)
+
+
+def islicq(coef, plan: Plan, T: int):
+    """Differentiable sliCQ synthesis of one signal (see SliCQSynthesisFunction)."""
+    return __getattr__("SliCQSynthesisFunction").apply(coef, plan, T)

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/slicq.h"
+#include "coefops.hpp"
 #include "pipeline.hpp"
 #include "stream_server.hpp"
 
@@ -122,9 +123,9 @@ int layout_or_fail(const slicq::Plan& p, int dt, int64_t ntasks, size_t bytes, s
 
 template <class T>
 int run_analysis(slicq::Plan& p, int dt, const slicq::SliceTask* tasks, int64_t ntasks, const void* x,
-                 void* coef, const slicq::WorkLayout& w, char* work, hipStream_t st) {
+                 void* coef, const slicq::WorkLayout& w, char* work, hipStream_t st, bool dual = false) {
   using namespace slicq;
-  KArgs<T> a = make_args<T>(p, dt, false);
+  KArgs<T> a = make_args<T>(p, dt, false, dual);
   const Geometry<T> g = geometry<T>(p);
   HipLaunch L{st};
   C2<T>* W1 = reinterpret_cast<C2<T>*>(work + w.w1_off);
@@ -511,6 +512,10 @@ int nsgt_plan_ex(const slicq_plan_opts* o, slicq_plan* out) {
   if (o->pass_cap) pp.pass_cap = o->pass_cap;
   pp.coef_layout = o->coef_layout;
   pp.fused = o->unfused ? 0 : 1;
+  pp.window = o->window;
+  pp.scale = o->scale;
+  pp.slicing = o->slicing;
+  pp.m_policy = o->m_policy;
   slicq_plan h = new (std::nothrow) slicq_plan_s;
   if (!h) return fail(SLICQ_ENOMEM, "out of host memory");
   std::string err;
@@ -560,6 +565,8 @@ int nsgt_plan_info(slicq_plan plan, slicq_plan_info* info) {
   info->n_syn_items = (int32_t)p.syn.size();
   info->coef_layout = p.prm.coef_layout;
   info->fused = (p.fused[0].ok ? 1 : 0) | (p.fused[1].ok ? 2 : 0);
+  info->coefs_per_slice_all = p.coefs_per_slice;
+  for (int k = 1; k <= p.K; ++k) info->coefs_per_slice_all += p.bands[k].M;
   return SLICQ_OK;
 }
 
@@ -627,8 +634,10 @@ int slicq_workspace_size(slicq_plan plan, slicq_dtype dt, int64_t n_slices, size
   return SLICQ_OK;
 }
 
-int slicq_analyze(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, void* coef, int64_t coef_count,
-                  void* work, size_t work_bytes, void* stream) {
+// Analysis-shaped calls on one signal (plain task table): analysis, or with
+// dual the adjoint of synthesis (dual windows, doubled weights on bands 1..K).
+static int analyze_common(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, void* coef, int64_t coef_count,
+                          void* work, size_t work_bytes, void* stream, bool dual) {
   int rc = check_plan(plan, dt);
   if (rc) return rc;
   slicq::Plan& p = plan->p;
@@ -644,8 +653,221 @@ int slicq_analyze(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, voi
   auto* tasks = reinterpret_cast<slicq::SliceTask*>(wk + w.tasks_off);
   hipStream_t st = static_cast<hipStream_t>(stream);
   plain_tasks(p, T, S, tasks, st);
-  return dt == SLICQ_F32 ? run_analysis<float>(p, dt, tasks, S, x, coef, w, wk, st)
-                         : run_analysis<double>(p, dt, tasks, S, x, coef, w, wk, st);
+  return dt == SLICQ_F32 ? run_analysis<float>(p, dt, tasks, S, x, coef, w, wk, st, dual)
+                         : run_analysis<double>(p, dt, tasks, S, x, coef, w, wk, st, dual);
+}
+
+int slicq_synthesize_adjoint(slicq_plan plan, slicq_dtype dt, const void* y, int64_t T, void* coef,
+                             int64_t coef_count, void* work, size_t work_bytes, void* stream) {
+  return analyze_common(plan, dt, y, T, coef, coef_count, work, work_bytes, stream, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of the complex-signal calls: the real workspace, then two real
+// sample arrays of T and two coefficient sets of the stored bands.
+struct ComplexLayout {
+  size_t real_bytes = 0, re_off = 0, im_off = 0, ca_off = 0, cb_off = 0, total = 0;
+};
+
+ComplexLayout complex_layout(const slicq::Plan& p, int dt, int64_t T) {
+  using slicq::align256;
+  ComplexLayout c;
+  const int64_t S = slices_of(p, T);
+  const size_t b = dt ? 8 : 4;
+  c.real_bytes = slicq::workspace_bytes(p, dt, S);
+  c.re_off = align256(c.real_bytes);
+  c.im_off = align256(c.re_off + (size_t)T * b);
+  c.ca_off = align256(c.im_off + (size_t)T * b);
+  c.cb_off = align256(c.ca_off + (size_t)S * p.coefs_per_slice * 2 * b);
+  c.total = align256(c.cb_off + (size_t)S * p.coefs_per_slice * 2 * b);
+  return c;
+}
+
+int64_t coefs_all(const slicq::Plan& p) {
+  int64_t n = p.coefs_per_slice;
+  for (int k = 1; k <= p.K; ++k) n += p.bands[k].M;
+  return n;
+}
+
+int check_complex(slicq_plan plan, slicq_dtype dt, int64_t T) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  if (plan->p.prm.coef_layout != 0) return fail(SLICQ_EINVAL, "complex-signal calls need the band-major layout");
+  if (T < 0) return fail(SLICQ_EINVAL, "T must be >= 0");
+  return check_signal_size(plan->p, T);
+}
+
+template <class T, class K, class... A>
+void launch_flat(hipStream_t st, K kernel, int64_t n, A... args) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, args...);
+}
+
+const slicq::BandDev* dev_bands(const slicq::Plan& p, int dt) {
+  return reinterpret_cast<const slicq::BandDev*>(static_cast<const char*>(p.dev[dt]) + p.layout[dt].bands);
+}
+
+}  // namespace
+
+extern "C" {
+
+int slicq_complex_workspace_size(slicq_plan plan, slicq_dtype dt, int64_t T, size_t* bytes) {
+  if (!plan || !bytes) return fail(SLICQ_EINVAL, "null argument");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "bad dtype");
+  if (T < 0) return fail(SLICQ_EINVAL, "T must be >= 0");
+  *bytes = complex_layout(plan->p, dt, T).total;
+  return SLICQ_OK;
+}
+
+int slicq_analyze_complex(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, void* coef, int64_t coef_count,
+                          void* work, size_t work_bytes, void* stream) {
+  int rc = check_complex(plan, dt, T);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  const int64_t S = slices_of(p, T);
+  if (S == 0) return SLICQ_OK;
+  if (!x || !coef || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (coef_count < S * coefs_all(p)) return fail(SLICQ_ESIZE, "coef_count < S * coefs_per_slice_all");
+  const ComplexLayout cl = complex_layout(p, dt, T);
+  if (work_bytes < cl.total) return fail(SLICQ_ESIZE, "workspace below slicq_complex_workspace_size");
+  char* wk = static_cast<char*>(work);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto go = [&](auto tag) -> int {
+    using F = decltype(tag);
+    using namespace slicq;
+    F* re = reinterpret_cast<F*>(wk + cl.re_off);
+    F* im = reinterpret_cast<F*>(wk + cl.im_off);
+    C2<F>* cb = reinterpret_cast<C2<F>*>(wk + cl.cb_off);
+    launch_flat<F>(st, k_split_complex<F>, T, static_cast<const C2<F>*>(x), T, re, im);
+    int r = analyze_common(plan, dt, re, T, coef, S * p.coefs_per_slice, wk, cl.real_bytes, stream, false);
+    if (!r) r = analyze_common(plan, dt, im, T, cb, S * p.coefs_per_slice, wk, cl.real_bytes, stream, false);
+    if (r) return r;
+    launch_flat<F>(st, k_combine_complex<F>, S * p.coefs_per_slice, dev_bands(p, dt), S * p.coefs_per_slice,
+                   p.nb, (int)S, S * p.coefs_per_slice, (const C2<F>*)cb, static_cast<C2<F>*>(coef));
+    return SLICQ_OK;
+  };
+  rc = dt == SLICQ_F32 ? go(float{}) : go(double{});
+  if (rc) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "complex analysis launch");
+}
+
+int slicq_synthesize_complex(slicq_plan plan, slicq_dtype dt, const void* coef, int64_t coef_count, void* y,
+                             int64_t T, void* work, size_t work_bytes, void* stream) {
+  int rc = check_complex(plan, dt, T);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  const int64_t S = slices_of(p, T);
+  if (S == 0) return SLICQ_OK;
+  if (!y || !coef || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (coef_count < S * coefs_all(p)) return fail(SLICQ_ESIZE, "coef_count < S * coefs_per_slice_all");
+  const ComplexLayout cl = complex_layout(p, dt, T);
+  if (work_bytes < cl.total) return fail(SLICQ_ESIZE, "workspace below slicq_complex_workspace_size");
+  char* wk = static_cast<char*>(work);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto go = [&](auto tag) -> int {
+    using F = decltype(tag);
+    using namespace slicq;
+    F* re = reinterpret_cast<F*>(wk + cl.re_off);
+    F* im = reinterpret_cast<F*>(wk + cl.im_off);
+    C2<F>* u = reinterpret_cast<C2<F>*>(wk + cl.ca_off);
+    C2<F>* v = reinterpret_cast<C2<F>*>(wk + cl.cb_off);
+    launch_flat<F>(st, k_hermitian_parts<F>, S * p.coefs_per_slice, dev_bands(p, dt), S * p.coefs_per_slice,
+                   p.nb, (int)S, S * p.coefs_per_slice, static_cast<const C2<F>*>(coef), u, v);
+    int r = synth_common(plan, dt, false, u, S * p.coefs_per_slice, re, T, wk, cl.real_bytes, stream);
+    if (!r) r = synth_common(plan, dt, false, v, S * p.coefs_per_slice, im, T, wk, cl.real_bytes, stream);
+    if (r) return r;
+    launch_flat<F>(st, k_join_complex<F>, T, (const F*)re, (const F*)im, T, static_cast<C2<F>*>(y));
+    return SLICQ_OK;
+  };
+  rc = dt == SLICQ_F32 ? go(float{}) : go(double{});
+  if (rc) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "complex synthesis launch");
+}
+
+int slicq_layers(slicq_plan plan, slicq_dtype dt, const void* coef, int64_t S, int mode, void* out,
+                 int64_t out_count, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (S < 0 || (S & 1)) return fail(SLICQ_EINVAL, "S must be an even slice count >= 0");
+  if (mode != 0 && mode != 1) return fail(SLICQ_EINVAL, "mode is 0 (layer sum) or 1 (spectrogram)");
+  if (S == 0) return SLICQ_OK;
+  if (!coef || !out) return fail(SLICQ_EINVAL, "null buffer");
+  const int64_t n = (S / 2) * p.coefs_per_slice;
+  if (out_count < n) return fail(SLICQ_ESIZE, "out_count < (S / 2) * coefs_per_slice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const slicq::CoefAddr ca{p.prm.coef_layout, (int32_t)p.coefs_per_slice, (int32_t)S};
+  if (dt == SLICQ_F32) {
+    if (mode == 0) launch_flat<float>(st, slicq::k_layer_sum<float, 0>, n, dev_bands(p, dt), n, p.nb, ca,
+                                      static_cast<const slicq::C2<float>*>(coef), out);
+    else launch_flat<float>(st, slicq::k_layer_sum<float, 1>, n, dev_bands(p, dt), n, p.nb, ca,
+                            static_cast<const slicq::C2<float>*>(coef), out);
+  } else {
+    if (mode == 0) launch_flat<double>(st, slicq::k_layer_sum<double, 0>, n, dev_bands(p, dt), n, p.nb, ca,
+                                       static_cast<const slicq::C2<double>*>(coef), out);
+    else launch_flat<double>(st, slicq::k_layer_sum<double, 1>, n, dev_bands(p, dt), n, p.nb, ca,
+                             static_cast<const slicq::C2<double>*>(coef), out);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "layer launch");
+}
+
+int slicq_mask_db(slicq_plan plan, slicq_dtype dt, void* coef, int64_t S, const void* mask, int64_t mask_count,
+                  void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (S < 0 || (S & 1)) return fail(SLICQ_EINVAL, "S must be an even slice count >= 0");
+  if (S == 0) return SLICQ_OK;
+  if (!coef || !mask) return fail(SLICQ_EINVAL, "null buffer");
+  if (mask_count < (S / 2) * p.coefs_per_slice) return fail(SLICQ_ESIZE, "mask_count < (S / 2) * coefs_per_slice");
+  const int64_t n = S * p.coefs_per_slice;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const slicq::CoefAddr ca{p.prm.coef_layout, (int32_t)p.coefs_per_slice, (int32_t)S};
+  if (dt == SLICQ_F32)
+    launch_flat<float>(st, slicq::k_mask_db<float>, n, dev_bands(p, dt), n, p.nb, ca, static_cast<const float*>(mask),
+                       static_cast<slicq::C2<float>*>(coef));
+  else
+    launch_flat<double>(st, slicq::k_mask_db<double>, n, dev_bands(p, dt), n, p.nb, ca,
+                        static_cast<const double*>(mask), static_cast<slicq::C2<double>*>(coef));
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "mask launch");
+}
+
+int slicq_transpose(slicq_plan plan, slicq_dtype dt, const void* in, void* out, int64_t S, int32_t d, void* stream) {
+  int rc = check_plan(plan, dt);
+  if (rc) return rc;
+  slicq::Plan& p = plan->p;
+  if (S < 0) return fail(SLICQ_EINVAL, "S must be >= 0");
+  if (S == 0) return SLICQ_OK;
+  if (!in || !out || in == out) return fail(SLICQ_EINVAL, "null or aliased buffers");
+  for (int t = 1; t <= p.K; ++t) {
+    const int s = t - d;
+    if (s >= 1 && s <= p.K && p.bands[s].M != p.bands[t].M)
+      return fail(SLICQ_EINVAL, "transposition moves a band onto one with a different M_k (use m_policy 1, "
+                                "the rectangular representation, or a shift inside a run of equal M_k)");
+  }
+  const int64_t n = S * p.coefs_per_slice;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const slicq::CoefAddr ca{p.prm.coef_layout, (int32_t)p.coefs_per_slice, (int32_t)S};
+  if (dt == SLICQ_F32)
+    launch_flat<float>(st, slicq::k_transpose<float>, n, dev_bands(p, dt), n, p.nb, ca, (int)d,
+                       static_cast<const slicq::C2<float>*>(in), static_cast<slicq::C2<float>*>(out));
+  else
+    launch_flat<double>(st, slicq::k_transpose<double>, n, dev_bands(p, dt), n, p.nb, ca, (int)d,
+                        static_cast<const slicq::C2<double>*>(in), static_cast<slicq::C2<double>*>(out));
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "transpose launch");
+}
+
+int slicq_analyze(slicq_plan plan, slicq_dtype dt, const void* x, int64_t T, void* coef, int64_t coef_count,
+                  void* work, size_t work_bytes, void* stream) {
+  return analyze_common(plan, dt, x, T, coef, coef_count, work, work_bytes, stream, false);
 }
 
 

@@ -100,7 +100,7 @@ struct alignas(16) RingCopy {
 constexpr int kPow8Entries = 7 * 8 + 7 * 64;
 
 struct TableLayout {
-  uint64_t tw, tw8, h0, hd, g, gd, bands, ana, syn, runs;
+  uint64_t tw, tw8, h0, hd, g, gd, gdw, bands, ana, syn, runs;
   uint64_t ola_syn, ola_adj, ent_off, ent_pos, ent_wsyn, ent_wadj;
   uint64_t fana, fsyn, fola_syn, fola_adj, fent_off, fent_pos, fent_wsyn, fent_wadj;
   uint64_t total;

@@ -66,15 +66,18 @@ inline bool work_layout(const Plan& p, int dtype, int64_t ntasks, size_t bytes, 
   return w.total <= bytes;
 }
 
+// Kernel arguments. adjoint: the synthesis kernels with the analysis windows
+// (adjoint of analysis); dual: the analysis kernels with the dual windows
+// h~_0 and w_k g~_k (adjoint of synthesis, w_k = 2 on bands 1..K).
 template <class T>
-KArgs<T> make_args(const Plan& p, int dtype, bool adjoint) {
+KArgs<T> make_args(const Plan& p, int dtype, bool adjoint, bool dual = false) {
   const TableLayout& L = p.layout[dtype];
   const char* base = static_cast<const char*>(p.dev[dtype]);
   KArgs<T> a{};
   a.tw = reinterpret_cast<const C2<T>*>(base + L.tw);
-  a.h0 = reinterpret_cast<const T*>(base + L.h0);
+  a.h0 = reinterpret_cast<const T*>(base + (dual ? L.hd : L.h0));
   a.hsyn = reinterpret_cast<const T*>(base + (adjoint ? L.h0 : L.hd));
-  a.g = reinterpret_cast<const T*>(base + L.g);
+  a.g = reinterpret_cast<const T*>(base + (dual ? L.gdw : L.g));
   a.bands = reinterpret_cast<const BandDev*>(base + L.bands);
   a.ana = reinterpret_cast<const AnaGroupDev*>(base + L.ana);
   a.syn = reinterpret_cast<const SynGroupDev*>(base + L.syn);

@@ -15,7 +15,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <functional>
 
 namespace slicq {
 
@@ -35,25 +34,6 @@ int ilog2(int64_t n) {
   return l;
 }
 
-// Integer interval on which pred holds, located from guesses and settled by
-// pred itself (pred must hold on an interval). Returns false if empty.
-bool find_interval(const std::function<bool(int64_t)>& pred, int64_t glo, int64_t ghi,
-                   int64_t& a, int64_t& b) {
-  const int64_t margin = 3;
-  bool found = false;
-  for (int64_t j = glo - margin; j <= ghi + margin; ++j) {
-    if (pred(j)) {
-      if (!found) a = j;
-      b = j;
-      found = true;
-    }
-  }
-  if (!found) return false;
-  while (pred(a - 1)) --a;
-  while (pred(b + 1)) ++b;
-  return true;
-}
-
 struct RawBand {
   int64_t start = 0;
   std::vector<double> g;
@@ -61,26 +41,49 @@ struct RawBand {
   double xi = 0, omega = 0;
 };
 
-RawBand hann_band(double fs, int64_t two_n, double xi, double om) {
-  auto x_of = [&](int64_t j) { return ((double)j * fs / (double)two_n - xi) / om; };
+// Window shape on |x| < 1/2 (x in bandwidths from the centre).
+double shape(int window, double x) {
+  const double c1 = std::cos(2.0 * M_PI * x);
+  if (window == 0) return 0.5 + 0.5 * c1;
+  return 0.35875 + 0.48829 * c1 + 0.14128 * std::cos(4.0 * M_PI * x) + 0.01168 * std::cos(6.0 * M_PI * x);
+}
+
+// Band with centre xi and bandwidth om (Hz): the bins j whose frequency lies
+// strictly inside (xi - om/2, xi + om/2). The end bins come from the closed
+// form of that interval, then each end is moved by at most a bin until the
+// window argument computed for the table itself decides it.
+RawBand cq_band(int window, double fs, int64_t two_n, double xi, double om) {
+  const double bin = fs / (double)two_n;
+  auto x_of = [&](int64_t j) { return ((double)j * bin - xi) / om; };
   auto inside = [&](int64_t j) {
-    double x = x_of(j);
-    return -0.5 < x && x < 0.5;
+    const double x = x_of(j);
+    return x > -0.5 && x < 0.5;
   };
   RawBand r;
   r.xi = xi;
   r.omega = om;
-  int64_t glo = (int64_t)std::floor((xi - om / 2) * (double)two_n / fs);
-  int64_t ghi = (int64_t)std::ceil((xi + om / 2) * (double)two_n / fs);
-  int64_t a = 0, b = -1;
-  if (!find_interval(inside, glo, ghi, a, b)) {
+  int64_t a = (int64_t)std::floor((xi - om / 2) / bin) + 1;   // first bin above the lower edge
+  int64_t b = (int64_t)std::ceil((xi + om / 2) / bin) - 1;    // last bin below the upper edge
+  if (!inside(a) && inside(a + 1)) ++a;
+  else if (inside(a - 1)) --a;
+  if (!inside(b) && inside(b - 1)) --b;
+  else if (inside(b + 1)) ++b;
+  if (b < a || !inside(a) || !inside(b)) {
     r.M = 2;
     return r;
   }
   r.start = a;
-  for (int64_t j = a; j <= b; ++j) r.g.push_back(0.5 + 0.5 * std::cos(2.0 * M_PI * x_of(j)));
+  for (int64_t j = a; j <= b; ++j) r.g.push_back(shape(window, x_of(j)));
   r.M = std::max<int64_t>(2, next_pow2(b - a + 1));
   return r;
+}
+
+// Frequency scales for the centres: u(f) and its inverse.
+double scale_fwd(int scale, double f) {
+  return scale == 1 ? 2595.0 * std::log10(1.0 + f / 700.0) : 26.81 * f / (1960.0 + f) - 0.53;
+}
+double scale_inv(int scale, double u) {
+  return scale == 1 ? 700.0 * (std::pow(10.0, u / 2595.0) - 1.0) : 1960.0 * (u + 0.53) / (26.28 - u);
 }
 
 // Plateau P(d; R, w) in the distance d (Hz) from centre_bin.
@@ -273,6 +276,12 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     err = "min_win must be >= 0, dual_kind and coef_layout 0 or 1";
     return -1;
   }
+  if (p.window < 0 || p.window > 1 || p.scale < 0 || p.scale > 2 || p.slicing < 0 || p.slicing > 1 ||
+      p.m_policy < 0 || p.m_policy > 1) {
+    err = "window (0 Hann, 1 Blackman-Harris), scale (0 cq, 1 mel, 2 Bark), slicing (0 Tukey, 1 root "
+          "Tukey) or m_policy (0 power of two, 1 rectangular) out of range";
+    return -1;
+  }
   if (p.group_cap < 16 || p.group_cap > 4096 || p.lds_cap < 64 || p.lds_cap > kSynMaxValues ||
       p.pass_cap < 64 || p.pass_cap > 4096 ||
       (p.group_cap & (p.group_cap - 1)) || (p.pass_cap & (p.pass_cap - 1))) {
@@ -291,9 +300,20 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
   const int K0 = 1 + (int)std::ceil((double)B * std::log2(fmax / fmin) - 1e-12);
   const double bw_min = p.min_win * fs / (double)two_n;
   std::vector<double> xi(K0), om(K0);
-  for (int k = 1; k <= K0; ++k) {
-    xi[k - 1] = fmin * std::pow(2.0, (double)(k - 1) / (double)B);
-    om[k - 1] = std::max(xi[k - 1] / Q, bw_min);
+  if (p.scale == 0) {
+    for (int k = 1; k <= K0; ++k) {
+      xi[k - 1] = fmin * std::pow(2.0, (double)(k - 1) / (double)B);
+      om[k - 1] = std::max(xi[k - 1] / Q, bw_min);
+    }
+  } else {
+    // K0 centres equally spaced on the mel or Bark scale from fmin to fmax;
+    // bandwidth = distance of the two neighbouring centres (xi_k / Q for constant Q)
+    const double u0 = scale_fwd(p.scale, fmin), du = (scale_fwd(p.scale, fmax) - u0) / std::max(K0 - 1, 1);
+    auto centre = [&](int k) { return scale_inv(p.scale, u0 + (double)(k - 1) * du); };
+    for (int k = 1; k <= K0; ++k) {
+      xi[k - 1] = centre(k);
+      om[k - 1] = std::max(centre(k + 1) - centre(k - 1), bw_min);
+    }
   }
   int K = K0;
   while (K >= 1 && !(xi[K - 1] + om[K - 1] / 2 < fs / 2)) --K;
@@ -310,10 +330,15 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     const double R0 = xi[0];
     const double w0 = std::min(om[0] / 2, R0);
     raw.push_back(plateau_band(fs, two_n, 0, R0, w0, 0.0, 2.0 * xi[0]));
-    for (int k = 1; k <= K; ++k) raw.push_back(hann_band(fs, two_n, xi[k - 1], om[k - 1]));
+    for (int k = 1; k <= K; ++k) raw.push_back(cq_band(p.window, fs, two_n, xi[k - 1], om[k - 1]));
     const double RN = fs / 2 - xi[K - 1];
     const double wN = std::min(om[K - 1] / 2, RN);
     raw.push_back(plateau_band(fs, two_n, N, RN, wN, fs / 2, fs - 2 * xi[K - 1]));
+  }
+  if (p.m_policy == 1) {       // rectangular: every band takes the largest M
+    int64_t Mr = 0;
+    for (const RawBand& r : raw) Mr = std::max(Mr, r.M);
+    for (RawBand& r : raw) r.M = Mr;
   }
   for (int k = 0; k < K + 2; ++k) {
     if (raw[k].g.empty()) {
@@ -433,7 +458,7 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     double h = 0.0;
     if (a <= flat) h = 1.0;
     else if ((double)a < (double)(N + Mt) / 2) h = 0.5 + 0.5 * std::cos(M_PI * (double)(a - flat) / (double)Mt);
-    out.h0[j] = h;
+    out.h0[j] = p.slicing == 1 ? std::sqrt(h) : h;   // sum_m h_m^2 = 1 for the square root
   }
   for (int64_t j = 0; j < two_n; ++j) {
     const double h = out.h0[j];
@@ -647,6 +672,12 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
         tw8.push_back(8 * ns <= two_n ? tw[2 * e] : 1.0);
         tw8.push_back(8 * ns <= two_n ? tw[2 * e + 1] : 0.0);
       }
+  // dual windows weighted for the adjoint of synthesis: 2 g~_k on bands 1..K
+  // (each synthesises also through its mirror), g~_k on the DC and Nyquist bands
+  std::vector<double> gdw_d(p.gd);
+  for (const BandInfo& b : p.bands)
+    if (b.k >= 1 && b.k <= p.K)
+      for (int32_t t = 0; t < b.len; ++t) gdw_d[b.goff + t] *= 2.0;
   std::vector<BandDev> bd;
   for (const BandInfo& b : p.bands) {
     BandDev d{};
@@ -666,7 +697,7 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
       for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
       return f;
     };
-    std::vector<float> twf = cvt(tw), h0 = cvt(p.h0), hd = cvt(p.hd), g = cvt(p.g), gd = cvt(p.gd);
+    std::vector<float> twf = cvt(tw), h0 = cvt(p.h0), hd = cvt(p.hd), g = cvt(p.g), gd = cvt(p.gd), gdw = cvt(gdw_d);
     lay.tw = append(blob, twf.data(), twf.size());
     const std::vector<float> tw8f = cvt(tw8);
     lay.tw8 = append(blob, tw8f.data(), tw8f.size());
@@ -674,6 +705,7 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
     lay.hd = append(blob, hd.data(), hd.size());
     lay.g = append(blob, g.data(), g.size());
     lay.gd = append(blob, gd.data(), gd.size());
+    lay.gdw = append(blob, gdw.data(), gdw.size());
   } else {
     lay.tw = append(blob, tw.data(), tw.size());
     lay.tw8 = append(blob, tw8.data(), tw8.size());
@@ -681,6 +713,7 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
     lay.hd = append(blob, p.hd.data(), p.hd.size());
     lay.g = append(blob, p.g.data(), p.g.size());
     lay.gd = append(blob, p.gd.data(), p.gd.size());
+    lay.gdw = append(blob, gdw_d.data(), gdw_d.size());
   }
   lay.bands = append(blob, bd.data(), bd.size());
   lay.ana = append(blob, p.ana.data(), p.ana.size());

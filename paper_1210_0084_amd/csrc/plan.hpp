@@ -22,6 +22,10 @@ struct PlanParams {
   int32_t pass_cap = 4096;      // complex values per four-step FFT work item
   int32_t coef_layout = 0;      // 0: band-major, 1: slice-major
   int32_t fused = 1;            // 1: one workgroup per slice where the half spectrum fits in LDS, 0: never
+  int32_t window = 0;           // band window: 0 Hann, 1 Blackman-Harris (4 terms)
+  int32_t scale = 0;            // centres: 0 constant-Q (geometric), 1 mel, 2 Bark
+  int32_t slicing = 0;          // 0 Tukey (sum_m h_m = 1), 1 square root of Tukey (sum_m h_m^2 = 1)
+  int32_t m_policy = 0;         // 0 smallest power of two >= |J_k|, 1 one M for every band (rectangular)
 };
 
 // The fused per-slice schedule of one dtype (see FusedItemDev).

@@ -9,6 +9,14 @@ from workloads import PRESETS
 CASES = [dict(fs=p.fs, fmin=p.fmin, fmax=p.fmax, bins_per_octave=p.bins_per_octave, slice_len=p.slice_len,
               transition=p.transition) for p in PRESETS.values()]
 CASES += [
+    dict(fs=44100.0, fmin=100.0, fmax=16000.0, bins_per_octave=12, slice_len=4096, transition=1024, min_win=8.0,
+         window="blackman_harris"),
+    dict(fs=44100.0, fmin=60.0, fmax=18000.0, bins_per_octave=24, slice_len=16384, transition=2048, scale="mel"),
+    dict(fs=48000.0, fmin=50.0, fmax=15000.0, bins_per_octave=16, slice_len=8192, transition=1024, scale="bark"),
+    dict(fs=44100.0, fmin=110.0, fmax=11025.0, bins_per_octave=12, slice_len=8192, transition=1024,
+         slicing="sqrt_tukey"),
+    dict(fs=8000.0, fmin=200.0, fmax=3000.0, bins_per_octave=48, slice_len=4096, transition=1024, min_win=4.0,
+         m_policy="rect"),
     dict(fs=64.0, fmin=4.0, fmax=16.0, bins_per_octave=3, slice_len=64, transition=8, min_win=0.0),
     dict(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0),
     dict(fs=44100.0, fmin=50.0, fmax=22000.0, bins_per_octave=48, slice_len=4096, transition=1024, min_win=8.0),
@@ -17,7 +25,12 @@ CASES += [
 ]
 
 
-@pytest.mark.parametrize("kw", CASES, ids=lambda k: f"B{k['bins_per_octave']}-2N{k['slice_len']}")
+def _id(k):
+    extra = "-".join(str(k[o]) for o in ("window", "scale", "slicing", "m_policy") if o in k)
+    return f"B{k['bins_per_octave']}-2N{k['slice_len']}" + (f"-{extra}" if extra else "")
+
+
+@pytest.mark.parametrize("kw", CASES, ids=_id)
 def test_cpp_plan_matches_oracle(kw):
     import paper_1210_0084_amd as sq
     o = OraclePlan(**kw)
@@ -28,11 +41,12 @@ def test_cpp_plan_matches_oracle(kw):
     np.testing.assert_array_equal(p.starts, [b.start for b in o.bands])
     np.testing.assert_array_equal(p.lengths, [b.length for b in o.bands])
     assert p.coefs_per_slice == o.coefs_per_slice
-    np.testing.assert_allclose(p.fc[1:-1], o.xi, rtol=1e-15)
-    np.testing.assert_allclose(p.bw[1:-1], o.omega, rtol=1e-15)
+    tol = 1e-15 if kw.get("scale", "cq") == "cq" else 1e-13   # pow / log10 of the scales
+    np.testing.assert_allclose(p.fc[1:-1], o.xi, rtol=tol)
+    np.testing.assert_allclose(p.bw[1:-1], o.omega, rtol=tol)
     assert abs(p.Q - o.Q) <= 1e-15 * o.Q
     g, gd, h0, hd, D = p.windows()
-    np.testing.assert_allclose(g, np.concatenate([b.g for b in o.bands]), rtol=0, atol=4e-16)
+    np.testing.assert_allclose(g, np.concatenate([b.g for b in o.bands]), rtol=0, atol=4e-16 if tol < 1e-14 else 1e-12)
     np.testing.assert_allclose(gd, np.concatenate([b.gd for b in o.bands]), rtol=1e-14, atol=1e-18)
     np.testing.assert_allclose(h0, o.h0, rtol=0, atol=4e-16)
     np.testing.assert_allclose(hd, o.hd, rtol=1e-15, atol=1e-18)
