@@ -262,6 +262,8 @@ def bench_batched(args, copy_gbs=None):
     if args.c3_tune:
         tuned = autotune(prm, lens, "f32", cache=args.tune_cache, reps=3)
         opts = dict(tuned["options"])
+    if args.unfused:
+        opts.setdefault("fused", False)
     plan = sq.Plan(**prm, **opts)
     lay = plan.batch_layout(lens)
     x = torch.tensor(np.concatenate([base[o:o + t] for o, t in zip(offs0, lens)]), device=dev)
@@ -310,7 +312,7 @@ def bench_differentiable(args, copy_gbs=None):
     import paper_1210_0084_amd as sq
     from workloads import make_c4
     dev = torch.device("cuda:0")
-    plan = sq.Plan(**_preset("c4"))
+    plan = sq.Plan(**_preset("c4"), fused=not args.unfused)
     xb = make_c4(args.c4_batch)
     yb = make_c4(args.c4_batch, target=True)
     B, T = xb.shape
@@ -371,7 +373,7 @@ def bench_stream(args):
     import paper_1210_0084_amd as sq
     from workloads import make_c5_stream
     torch.cuda.init()
-    plan = sq.Plan(**_preset("c5"), layout="slice")
+    plan = sq.Plan(**_preset("c5"), layout="slice", fused=not args.unfused)
     fs, hop, n_streams = 48000.0, 4096, args.c5_streams
     pool = [make_c5_stream(i, int(fs * 10)).astype(np.float32) for i in range(16)]
     srv = sq.StreamServer(plan, "f32", max_streams=n_streams + 64, max_batch=2 * n_streams)
@@ -535,6 +537,8 @@ def main():
     ap.add_argument("--c3-tune", action="store_true", help="autotune the ragged batch's work items first")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--c4-batch", type=int, default=32)
+    ap.add_argument("--unfused", action="store_true",
+                    help="batched, differentiable and streaming forms on the multi-kernel pipeline only")
     ap.add_argument("--c5-streams", type=int, default=512)
     ap.add_argument("--c5-seconds", type=float, default=10.0)
     args = ap.parse_args()
