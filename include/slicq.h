@@ -205,6 +205,18 @@ int slicq_adjoint(slicq_plan plan, slicq_dtype dtype, const void* coef, int64_t 
 int slicq_synthesize_adjoint(slicq_plan plan, slicq_dtype dtype, const void* y, int64_t T, void* coef,
                              int64_t coef_count, void* work, size_t work_bytes, void* hip_stream);
 
+/* Log-magnitude loss of coefficients against target log-magnitudes t (the
+ * differentiable workload's loss, not part of the paper's transform): with
+ * d = log(1 + |c|^2) - t over n complex coefficients, *loss = sum d^2 and
+ * grad = 4 d c / (1 + |c|^2) (the derivative with respect to the real and
+ * imaginary parts), in one pass over c and t. partial: device scratch of at
+ * least slicq_logmag_loss_partials(n) values of the dtype; loss: one value of
+ * the dtype in device memory. Blocks sum fixed strides and the partials are
+ * added in order: the result is the same on every run. */
+int64_t slicq_logmag_loss_partials(int64_t n);
+int slicq_logmag_loss(slicq_dtype dtype, const void* coef, const void* target, int64_t n, void* grad, void* partial,
+                      int64_t partial_count, void* loss, void* hip_stream);
+
 /* Complex signals (the transform of Sections 2-4 before the restriction to
  * real signals): analysis onto all 2K+2 bands, band-major in the order
  * 0..K+1 (the stored bands, same offsets as for real signals) then the

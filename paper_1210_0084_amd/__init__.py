@@ -104,6 +104,8 @@ def load_library():
         "slicq_layers": (ctypes.c_int, [P, ctypes.c_int, P, I64, ctypes.c_int, P, I64, P]),
         "slicq_mask_db": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, I64, P]),
         "slicq_transpose": (ctypes.c_int, [P, ctypes.c_int, P, P, I64, I32, P]),
+        "slicq_logmag_loss_partials": (I64, [I64]),
+        "slicq_logmag_loss": (ctypes.c_int, [ctypes.c_int, P, P, I64, P, P, I64, P, P]),
         "slicq_batched_status": (ctypes.c_int, [P, ctypes.c_int, I64, P, SZ, ctypes.POINTER(I32),
                                                 ctypes.POINTER(I64), P]),
         "slicq_batch_tasks_bytes": (SZ, [I64]),
@@ -798,6 +800,42 @@ def _make_function():
     return SliCQFunction
 
 
+def _make_loss_function():
+    torch = _torch()
+
+    class LogMagLoss(torch.autograd.Function):
+        """sum (log(1 + |c|^2) - target)^2 by one HIP kernel that also writes
+        the gradient (saved for backward)."""
+
+        @staticmethod
+        def forward(ctx, coef, target):
+            lib = load_library()
+            _require_cuda(coef, "coef")
+            _require_cuda(target, "target")
+            dt = _dtype_code(coef)
+            c = coef.contiguous()
+            t = target.contiguous()
+            if t.numel() != c.numel():
+                raise SlicqError("target must have one value per coefficient")
+            rt = torch.float32 if dt == F32 else torch.float64
+            grad = torch.empty_like(c)
+            part = torch.empty(int(lib.slicq_logmag_loss_partials(c.numel())), dtype=rt, device=c.device)
+            loss = torch.empty((), dtype=rt, device=c.device)
+            _check(lib.slicq_logmag_loss(dt, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(t.data_ptr()), c.numel(),
+                                         ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(part.data_ptr()),
+                                         part.numel(), ctypes.c_void_p(loss.data_ptr()),
+                                         ctypes.c_void_p(_stream_ptr(c.device))))
+            ctx.save_for_backward(grad)
+            return loss
+
+        @staticmethod
+        def backward(ctx, g):
+            (grad,) = ctx.saved_tensors
+            return grad * g, None
+
+    return LogMagLoss
+
+
 def _make_synthesis_function():
     torch = _torch()
 
@@ -822,7 +860,8 @@ _FUNCS = {}
 
 
 def __getattr__(name):
-    makers = {"SliCQFunction": _make_function, "SliCQSynthesisFunction": _make_synthesis_function}
+    makers = {"SliCQFunction": _make_function, "SliCQSynthesisFunction": _make_synthesis_function,
+              "LogMagLoss": _make_loss_function}
     if name in makers:
         if name not in _FUNCS:
             _FUNCS[name] = makers[name]()
@@ -833,6 +872,11 @@ def __getattr__(name):
 def slicq(x, plan: Plan):
     """Differentiable sliCQ analysis (see SliCQFunction)."""
     return __getattr__("SliCQFunction").apply(x, plan)
+
+
+def logmag_loss(coef, target):
+    """sum (log(1 + |coef|^2) - target)^2, differentiable (see LogMagLoss)."""
+    return __getattr__("LogMagLoss").apply(coef, target)
 
 
 def islicq(coef, plan: Plan, T: int):

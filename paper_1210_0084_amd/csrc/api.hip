@@ -902,6 +902,36 @@ int slicq_analyze_static(slicq_plan plan, slicq_dtype dt, const void* x, int64_t
                          : run_analysis<double>(p, dt, tasks, S, x, coef, w, wk, st);
 }
 
+int64_t slicq_logmag_loss_partials(int64_t n) {
+  if (n <= 0) return 1;
+  return std::min<int64_t>(4096, (n + 4 * slicq::kLossThreads - 1) / (4 * slicq::kLossThreads));
+}
+
+int slicq_logmag_loss(slicq_dtype dt, const void* coef, const void* target, int64_t n, void* grad, void* partial,
+                      int64_t partial_count, void* loss, void* stream) {
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "bad dtype");
+  if (n < 0) return fail(SLICQ_EINVAL, "n must be >= 0");
+  if (!coef || !target || !grad || !partial || !loss) return fail(SLICQ_EINVAL, "null buffer");
+  const int64_t nb = slicq_logmag_loss_partials(n);
+  if (partial_count < nb) return fail(SLICQ_ESIZE, "partial_count < slicq_logmag_loss_partials(n)");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dt == SLICQ_F32) {
+    hipLaunchKernelGGL(slicq::k_logmag_loss<float>, dim3((unsigned)nb), dim3(slicq::kLossThreads), 0, st,
+                       static_cast<const slicq::C2<float>*>(coef), static_cast<const float*>(target), n,
+                       static_cast<slicq::C2<float>*>(grad), static_cast<float*>(partial));
+    hipLaunchKernelGGL(slicq::k_loss_sum<float>, dim3(1), dim3(slicq::kLossThreads), 0, st,
+                       static_cast<const float*>(partial), (int)nb, static_cast<float*>(loss));
+  } else {
+    hipLaunchKernelGGL(slicq::k_logmag_loss<double>, dim3((unsigned)nb), dim3(slicq::kLossThreads), 0, st,
+                       static_cast<const slicq::C2<double>*>(coef), static_cast<const double*>(target), n,
+                       static_cast<slicq::C2<double>*>(grad), static_cast<double*>(partial));
+    hipLaunchKernelGGL(slicq::k_loss_sum<double>, dim3(1), dim3(slicq::kLossThreads), 0, st,
+                       static_cast<const double*>(partial), (int)nb, static_cast<double*>(loss));
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "loss launch");
+}
+
 int slicq_synthesize(slicq_plan plan, slicq_dtype dt, const void* coef, int64_t coef_count, void* y, int64_t T,
                      void* work, size_t work_bytes, void* stream) {
   return synth_common(plan, dt, false, coef, coef_count, y, T, work, work_bytes, stream);

@@ -179,3 +179,54 @@ __global__ void __launch_bounds__(256) k_hermitian_parts(const BandDev* __restri
 }
 
 }  // namespace slicq
+
+namespace slicq {
+
+// Log-magnitude loss of the differentiable workload: with d = log(1 + |c|^2)
+// - t (t the target's log-magnitudes), L = sum d^2 and its gradient with
+// respect to c (real and imaginary parts: the convention of a real loss of a
+// complex variable) dL/dc = 4 d c / (1 + |c|^2). One pass over c and t: every
+// block of kLossThreads threads takes a fixed stride of elements and writes
+// its partial sum (a tree in LDS, fixed order), k_loss_sum adds the partials
+// in order, so the loss is the same on every run.
+constexpr int kLossThreads = 256;
+
+template <class T>
+__global__ void __launch_bounds__(kLossThreads) k_logmag_loss(const C2<T>* __restrict__ c, const T* __restrict__ t,
+                                                              int64_t n, C2<T>* __restrict__ grad,
+                                                              T* __restrict__ partial) {
+  __shared__ T red[kLossThreads];
+  T acc = T(0);
+  const int64_t stride = (int64_t)gridDim.x * kLossThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kLossThreads + threadIdx.x; i < n; i += stride) {
+    const C2<T> v = c[i];
+    const T p = v.x * v.x + v.y * v.y;
+    const T d = log1p(p) - t[i];
+    acc += d * d;
+    const T s = T(4) * d / (T(1) + p);
+    grad[i] = {s * v.x, s * v.y};
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kLossThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kLossThreads) k_loss_sum(const T* __restrict__ partial, int nb, T* __restrict__ out) {
+  __shared__ T red[kLossThreads];
+  T acc = T(0);
+  for (int i = threadIdx.x; i < nb; i += kLossThreads) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kLossThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace slicq

@@ -29,13 +29,49 @@ namespace slicq {
 template <int LOGN>
 constexpr int kSliceE = LOGN >= 14 ? 16 : 8;
 
-// Analysis of one fused item: bands k0 .. k0 + cnt - 1 with M = 2^LOGM. The
-// first FFT pass is fused with the gather from the LDS spectrum, the last one
-// with the coefficient stores. DIR = +1 (e^{+}). Ends with a barrier.
+// Global data of one thread for the first FFT pass of a fused analysis item
+// (bands k0 .. k0 + cnt - 1, M >= 8: unit tid takes slots j + r M/8 of band
+// k0 + sb), loaded one item ahead so that the loads overlap the current
+// item's transform: spectrum index of each value (~index marks a conjugate),
+// the window value as loaded, and a bit per value that holds one.
+template <class T>
+struct AnaPrefetch {
+  int xi[8];
+  T gv[8];
+  int live;
+};
+
+template <class T>
+__device__ __forceinline__ AnaPrefetch<T> ana_prefetch(const KArgs<T>& a, const FusedItemDev& G, int tid) {
+  AnaPrefetch<T> f;
+  const int lu = G.logM - 3, units = G.cnt << lu, mask = G.M - 1, N = a.N;
+  const int u = imin(tid, units - 1);
+  const int sb = u >> lu, j = u & ((1 << lu) - 1);
+  const BandDev B = a.bands[G.k0 + sb];
+  f.live = 0;
+  int wi[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int t = (j + (r << lu) - B.start) & mask;
+    const int jb = B.start + t;                 // signed bin, -N < jb < 2N
+    const bool in = tid < units && t < B.len;
+    const int jj = jb < 0 ? -jb : (jb > N ? 2 * N - jb : jb);
+    f.xi[r] = (jb < 0 || jb > N) ? ~jj : jj;
+    wi[r] = in ? B.goff + t : 0;
+    f.live |= in ? (1 << r) : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) f.gv[r] = a.g[wi[r]];
+  return f;
+}
+
+// Analysis of one fused item with M = 2^LOGM: the first FFT pass takes the
+// prefetched gather (M >= 8; smaller M gather here), the last one stores the
+// coefficients. DIR = +1 (e^{+}). Ends with a barrier.
 template <class T, int LOGM, class TW>
 __device__ __forceinline__ void fused_ana_item(const KArgs<T>& a, const SliceTask& tk, const FusedItemDev& G,
-                                               C2<T>* buf, C2<T>* __restrict__ cs, const TW& tws, int tid,
-                                               int nthr) {
+                                               const AnaPrefetch<T>& pf, C2<T>* buf, C2<T>* __restrict__ cs,
+                                               const TW& tws, int tid, int nthr) {
   constexpr int E = kFusedE;
   constexpr int M = 1 << LOGM, MASK = M - 1;
   constexpr int LR1 = pass_log_radix(LOGM, 0, 8), R1 = 1 << LR1, U1 = E / R1;
@@ -47,34 +83,48 @@ __device__ __forceinline__ void fused_ana_item(const KArgs<T>& a, const SliceTas
   const int cbase = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * M;
   const int bstride = a.slice_major ? M : tk.S * M;   // band k0 + s starts s bstride later
   C2<T> v[U1][R1];
+  if constexpr (R1 == 8) {
+    // U1 = 1: unit tid, its gather prefetched with the item
+    if (wave_has(tid, units1)) {
 #pragma unroll
-  for (int i = 0; i < U1; ++i) {
-    if (!wave_has(tid + i * nthr, units1)) continue;   // idle waves skip the gather
-    const int u = imin(tid + i * nthr, units1 - 1);
-    const int sb = u >> LU1, j = u & ((1 << LU1) - 1);
-    const BandDev B = a.bands[G.k0 + sb];
-    const bool live = tid + i * nthr < units1;
-    int xi[R1], wi[R1];
-#pragma unroll
-    for (int r = 0; r < R1; ++r) {
-      const int slot = j + (r << LU1);
-      const int t = (slot - B.start) & MASK;
-      const int jb = B.start + t;               // signed bin, -N < jb < 2N
-      const bool in = live && t < B.len;
-      const int jj = jb < 0 ? -jb : (jb > N ? 2 * N - jb : jb);
-      xi[r] = in ? ((jb < 0 || jb > N) ? ~jj : jj) : 0;   // ~jj (< 0) marks a conjugate
-      wi[r] = in ? B.goff + t : -1;
+      for (int r = 0; r < 8; ++r) {
+        const int x = pf.xi[r];
+        const C2<T> xv = buf[pidx(x < 0 ? ~x : x)];
+        const T w = ((pf.live >> r) & 1) ? pf.gv[r] : T(0);
+        v[0][r] = {xv.x * w, (x < 0 ? -xv.y : xv.y) * w};
+      }
+      dft_reg<T, 8, 1>(v[0]);
     }
-    T gv[R1];
+  } else {
 #pragma unroll
-    for (int r = 0; r < R1; ++r) gv[r] = a.g[imax(wi[r], 0)];
+    for (int i = 0; i < U1; ++i) {
+      if (!wave_has(tid + i * nthr, units1)) continue;   // idle waves skip the gather
+      const int u = imin(tid + i * nthr, units1 - 1);
+      const int sb = u >> LU1, j = u & ((1 << LU1) - 1);
+      const BandDev B = a.bands[G.k0 + sb];
+      const bool live = tid + i * nthr < units1;
+      int xi[R1], wi[R1];
 #pragma unroll
-    for (int r = 0; r < R1; ++r) {
-      const C2<T> xv = buf[pidx(xi[r] < 0 ? ~xi[r] : xi[r])];
-      const T w = wi[r] < 0 ? T(0) : gv[r];
-      v[i][r] = {xv.x * w, (xi[r] < 0 ? -xv.y : xv.y) * w};
+      for (int r = 0; r < R1; ++r) {
+        const int slot = j + (r << LU1);
+        const int t = (slot - B.start) & MASK;
+        const int jb = B.start + t;
+        const bool in = live && t < B.len;
+        const int jj = jb < 0 ? -jb : (jb > N ? 2 * N - jb : jb);
+        xi[r] = in ? ((jb < 0 || jb > N) ? ~jj : jj) : 0;
+        wi[r] = in ? B.goff + t : -1;
+      }
+      T gv[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) gv[r] = a.g[imax(wi[r], 0)];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const C2<T> xv = buf[pidx(xi[r] < 0 ? ~xi[r] : xi[r])];
+        const T w = wi[r] < 0 ? T(0) : gv[r];
+        v[i][r] = {xv.x * w, (xi[r] < 0 ? -xv.y : xv.y) * w};
+      }
+      dft_reg<T, R1, 1>(v[i]);
     }
-    dft_reg<T, R1, 1>(v[i]);
   }
   if constexpr (LAST == 0) {
     // a single pass: outputs n = r of unit j = 0
@@ -128,46 +178,100 @@ __device__ __forceinline__ void fused_ana_item(const KArgs<T>& a, const SliceTas
   __syncthreads();    // the next item may overwrite this item's indices
 }
 
-// Band transforms of one fused synthesis item: the coefficients of bands
-// k0 .. k0 + cnt - 1 (M = 2^LOGM) loaded, DFT of length M (e^{-}) at LDS
-// indices lds .. lds + cnt M - 1 (the first radix-8 pass fused with the loads).
-// Ends with a barrier.
+// Global data of one thread for a fused synthesis item, loaded one item ahead:
+// the eight coefficients of its first-pass unit (M >= 8: unit tid takes
+// coefficients j + r M/8 of band k0 + s) and the overlap-add records of its
+// first kSynPre bins (olo + tid + q nthr; fewer in FP64, whose records and
+// values take twice the registers).
+template <class T>
+constexpr int kSynPre = sizeof(T) == 4 ? 2 : 1;
+// FP32 loads the next item's data during the current item; FP64 (the check
+// path, twice the registers per value) loads each item's data at its start.
+template <class T>
+constexpr bool kAhead = sizeof(T) == 4;
+
+template <class T>
+struct SynPrefetch {
+  C2<T> v[8];
+  FOlaRec<T> rec[kSynPre<T>];
+};
+
+template <class T>
+__device__ __forceinline__ SynPrefetch<T> syn_prefetch(const KArgs<T>& a, const SliceTask& tk,
+                                                       const FusedItemDev& G, const C2<T>* __restrict__ cs, int tid,
+                                                       int nthr) {
+  SynPrefetch<T> f;
+  if (G.logM >= 3) {
+    const int lu = G.logM - 3, units = G.cnt << lu;
+    const int u = imin(tid, units - 1);
+    const int s = u >> lu, j = u & ((1 << lu) - 1);
+    const int off0 = a.bands[G.k0].off;
+    const int cb0 = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * G.M;
+    const int bstride = a.slice_major ? G.M : tk.S * G.M;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) f.v[r] = cs[cb0 + s * bstride + j + (r << lu)];
+  }
+#pragma unroll
+  for (int q = 0; q < kSynPre<T>; ++q) f.rec[q] = a.fola[G.rec0 + imin(tid + q * nthr, G.ohi - G.olo)];
+  return f;
+}
+
+// Band transforms of one fused synthesis item: DFT of length M = 2^LOGM
+// (e^{-}) of bands k0 .. k0 + cnt - 1 at LDS indices lds .. lds + cnt M - 1,
+// the first radix-8 pass on the prefetched coefficients. Ends with a barrier.
 template <class T, int LOGM, class TW>
 __device__ __forceinline__ void fused_syn_item(const KArgs<T>& a, const SliceTask& tk, const FusedItemDev& G,
-                                               C2<T>* buf, const C2<T>* __restrict__ cs, const TW& tws, int tid,
-                                               int nthr) {
+                                               const SynPrefetch<T>& pf, C2<T>* buf, const C2<T>* __restrict__ cs,
+                                               const TW& tws, int tid, int nthr) {
   constexpr int M = 1 << LOGM;
   const int base = G.lds;
-  const int off0 = a.bands[G.k0].off;
-  // element n of band k0 + s
-  const int cb0 = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * M;
-  const int bstride = a.slice_major ? M : tk.S * M;
   if constexpr (LOGM >= 3) {
     constexpr int LU = LOGM - 3;
     const int units = G.cnt << LU;
-    for (int u0 = 0; u0 < units; u0 += nthr) {          // one round unless the block is small
-      if (wave_has(u0 + tid, units)) {
-        const int u = imin(u0 + tid, units - 1);
-        const int s = u >> LU, j = u & ((1 << LU) - 1);
-        C2<T> v[8];
+    if (wave_has(tid, units)) {
+      C2<T> v[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = cs[cb0 + s * bstride + j + (r << LU)];
-        dft_reg<T, 8, -1>(v);
-        if (u0 + tid < units) {
-          const int p0 = base + (s << LOGM) + (j << 3);
+      for (int r = 0; r < 8; ++r) v[r] = pf.v[r];
+      dft_reg<T, 8, -1>(v);
+      if (tid < units) {
+        const int s = tid >> LU, j = tid & ((1 << LU) - 1);
+        const int p0 = base + (s << LOGM) + (j << 3);
 #pragma unroll
-          for (int r = 0; r < 8; ++r) buf[pidx(p0 + r)] = v[r];
-        }
+        for (int r = 0; r < 8; ++r) buf[pidx(p0 + r)] = v[r];
       }
     }
     __syncthreads();
     lds_fft_c<T, -1, kFusedE, 8, LOGM, 3, TW, LOGM, true>(buf, base, G.cnt, tws, tid, nthr);
   } else {
+    const int off0 = a.bands[G.k0].off;
+    const int cb0 = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * M;
+    const int bstride = a.slice_major ? M : tk.S * M;
     const int total = G.cnt << LOGM;
     for (int p = tid; p < total; p += nthr) buf[pidx(base + p)] = cs[cb0 + (p >> LOGM) * bstride + (p & (M - 1))];
     __syncthreads();
     lds_fft_c<T, -1, kFusedE, 8, LOGM, 0, TW, LOGM, true>(buf, base, G.cnt, tws, tid, nthr);
   }
+}
+
+// Frequency overlap-add of one bin j of a fused synthesis item from its record
+// (rec index ri): Z[j] = (first writer ? 0 : Z[j]) + sum of the item's entries.
+template <class T>
+__device__ __forceinline__ void fused_ola_bin(const KArgs<T>& a, C2<T>* buf, int j, int ri, const FOlaRec<T>& rec) {
+  const uint32_t y0 = rec.yy & 0xffffu, y1 = rec.yy >> 16;
+  C2<T> c0 = buf[pidx(rec.xx & kFPos)], c1 = buf[pidx((rec.xx >> 16) & kFPos)];
+  if (y0 != 0xffffu) c0 = cadd(c0, cconj(buf[pidx(y0)]));
+  if (y1 != 0xffffu) c1 = cadd(c1, cconj(buf[pidx(y1)]));
+  C2<T> acc = cadd(cscale(c0, rec.w0), cscale(c1, rec.w1));
+  if (rec.xx & kFMore) {
+    for (int e = a.fent_off[ri]; e < a.fent_off[ri + 1]; ++e) {
+      const int2 pe = a.fent_pos[e];
+      C2<T> c = buf[pidx(pe.x)];
+      if (pe.y >= 0) c = cadd(c, cconj(buf[pidx(pe.y)]));
+      acc = cadd(acc, cscale(c, a.fent_w[e]));
+    }
+  }
+  if (!(rec.xx & kFInit)) acc = cadd(buf[pidx(j)], acc);
+  buf[pidx(j)] = acc;
 }
 
 // Dispatches a fused item's band length 2^logM (1 <= logM <= MAXL) to BODY<L>.
@@ -248,13 +352,30 @@ k_ana_fused(KArgs<T> a, const SliceTask* __restrict__ tasks, const T* __restrict
   __syncthreads();
   C2<T>* __restrict__ cs = coef + tk.coef_base;
   const TwBand<T, false> tb = band_tw<false>(twB, a.flogM);
+  // each item's global gather data is loaded while the previous item transforms
+  FusedItemDev Gn = a.fana[0];
+  AnaPrefetch<T> pn{};
+  if constexpr (kAhead<T>) {
+    if (Gn.logM >= 3) pn = ana_prefetch(a, Gn, tid);
+  }
   for (int it = 0; it < a.nfana; ++it) {
-    const FusedItemDev G = a.fana[it];
+    const FusedItemDev G = Gn;
+    AnaPrefetch<T> pf{};
+    if constexpr (kAhead<T>) {
+      pf = pn;
+      if (it + 1 < a.nfana) {
+        Gn = a.fana[it + 1];
+        if (Gn.logM >= 3) pn = ana_prefetch(a, Gn, tid);
+      }
+    } else {
+      if (G.logM >= 3) pf = ana_prefetch(a, G, tid);
+      if (it + 1 < a.nfana) Gn = a.fana[it + 1];
+    }
     // an opaque copy of the thread index keeps each length's address
     // arithmetic inside the loop (registers)
     int t = tid;
     asm volatile("" : "+v"(t));
-#define SLICQ_FA(L) fused_ana_item<T, L>(a, tk, G, buf, cs, tb, t, nthr)
+#define SLICQ_FA(L) fused_ana_item<T, L>(a, tk, G, pf, buf, cs, tb, t, nthr)
     SLICQ_FUSED_SWITCH(G.logM, MAXL, SLICQ_FA)
 #undef SLICQ_FA
   }
@@ -283,33 +404,38 @@ k_syn_fused(KArgs<T> a, const SliceTask* __restrict__ tasks, const C2<T>* __rest
   __syncthreads();
   const C2<T>* __restrict__ cs = coef + tk.coef_base;
   const TwBand<T, false> tb = band_tw<false>(twB, a.flogM);
+  // each item's coefficients and first overlap-add records are loaded while
+  // the previous item transforms
+  FusedItemDev Gn = a.fsyn[0];
+  SynPrefetch<T> pn;
+  if constexpr (kAhead<T>) pn = syn_prefetch(a, tk, Gn, cs, tid, nthr);
   for (int it = 0; it < a.nfsyn; ++it) {
-    const FusedItemDev G = a.fsyn[it];
+    const FusedItemDev G = Gn;
+    SynPrefetch<T> pf;
+    if constexpr (kAhead<T>) {
+      pf = pn;
+      if (it + 1 < a.nfsyn) {
+        Gn = a.fsyn[it + 1];
+        pn = syn_prefetch(a, tk, Gn, cs, tid, nthr);
+      }
+    } else {
+      pf = syn_prefetch(a, tk, G, cs, tid, nthr);
+      if (it + 1 < a.nfsyn) Gn = a.fsyn[it + 1];
+    }
     int t = tid;
     asm volatile("" : "+v"(t));
-#define SLICQ_FS(L) fused_syn_item<T, L>(a, tk, G, buf, cs, tb, t, nthr)
+#define SLICQ_FS(L) fused_syn_item<T, L>(a, tk, G, pf, buf, cs, tb, t, nthr)
     SLICQ_FUSED_SWITCH(G.logM, MAXL, SLICQ_FS)
 #undef SLICQ_FS
     // frequency overlap-add of this item's bands into Z[olo..ohi]
-    for (int j = G.olo + tid; j <= G.ohi; j += nthr) {
-      const int ri = G.rec0 + (j - G.olo);
-      const FOlaRec<T> rec = a.fola[ri];
-      const uint32_t y0 = rec.yy & 0xffffu, y1 = rec.yy >> 16;
-      C2<T> c0 = buf[pidx(rec.xx & kFPos)], c1 = buf[pidx((rec.xx >> 16) & kFPos)];
-      if (y0 != 0xffffu) c0 = cadd(c0, cconj(buf[pidx(y0)]));
-      if (y1 != 0xffffu) c1 = cadd(c1, cconj(buf[pidx(y1)]));
-      C2<T> acc = cadd(cscale(c0, rec.w0), cscale(c1, rec.w1));
-      if (rec.xx & kFMore) {
-        for (int e = a.fent_off[ri]; e < a.fent_off[ri + 1]; ++e) {
-          const int2 pe = a.fent_pos[e];
-          C2<T> c = buf[pidx(pe.x)];
-          if (pe.y >= 0) c = cadd(c, cconj(buf[pidx(pe.y)]));
-          acc = cadd(acc, cscale(c, a.fent_w[e]));
-        }
-      }
-      if (!(rec.xx & kFInit)) acc = cadd(buf[pidx(j)], acc);
-      buf[pidx(j)] = acc;
+    const int nbin = G.ohi - G.olo + 1;
+#pragma unroll
+    for (int q = 0; q < kSynPre<T>; ++q) {
+      const int d = tid + q * nthr;
+      if (d < nbin) fused_ola_bin(a, buf, G.olo + d, G.rec0 + d, pf.rec[q]);
     }
+    for (int d = tid + kSynPre<T> * nthr; d < nbin; d += nthr)
+      fused_ola_bin(a, buf, G.olo + d, G.rec0 + d, a.fola[G.rec0 + d]);
     __syncthreads();
   }
   // Hermitian packing of Z[0..N] into the N-point spectrum of y[2n] + i y[2n+1]

@@ -120,3 +120,51 @@ def test_batched_autograd_equals_per_signal(sq, dev, plan):
         assert torch.equal(cb.detach(), c.detach()[b])
         ((cb.real ** 2 + cb.imag ** 2) * w[b]).sum().backward()
         assert torch.equal(xb.grad, gb[b])
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_loss_kernel_matches_torch_and_is_deterministic(sq, dev, dt):
+    # the one-pass loss kernel (value and gradient) against the same loss in
+    # FP64 torch operations; two runs give identical results
+    import torch
+    ctype = torch.complex64 if dt == "f32" else torch.complex128
+    g = np.random.default_rng(31)
+    n = 1_000_003
+    c = torch.tensor(g.standard_normal(n) + 1j * g.standard_normal(n), dtype=ctype, device=dev, requires_grad=True)
+    t = torch.tensor(g.uniform(0, 2, n), dtype=c.real.dtype, device=dev)
+    loss = sq.logmag_loss(c, t)
+    loss.backward()
+    cd = c.detach().to(torch.complex128).requires_grad_(True)
+    ref = ((torch.log1p(cd.real ** 2 + cd.imag ** 2) - t.double()) ** 2).sum()
+    ref.backward()
+    tol = 1e-5 if dt == "f32" else 1e-12
+    assert abs(loss.item() - ref.item()) <= tol * abs(ref.item())
+    gd = c.grad.to(torch.complex128)
+    assert (torch.linalg.vector_norm(gd - cd.grad) / torch.linalg.vector_norm(cd.grad)).item() <= tol
+    again = sq.logmag_loss(c.detach(), t)
+    assert again.item() == loss.item()
+
+
+def test_gradient_through_loss_kernel_fd(sq, dev, plan):
+    # analysis -> loss kernel -> adjoint: gradient against FP64 central differences
+    import torch
+    T = 20000
+    x0 = noise_plus_sines(T, 44100.0, 41)
+    y = noise_plus_sines(T, 44100.0, 1041)
+    xd = torch.tensor(x0, dtype=torch.float64, device=dev, requires_grad=True)
+    with torch.no_grad():
+        cy = plan.analyze(torch.tensor(y, dtype=torch.float64, device=dev))
+        ty = torch.log1p(cy.real ** 2 + cy.imag ** 2)
+    sq.logmag_loss(sq.slicq(xd, plan), ty).backward()
+    grad = xd.grad.cpu().numpy()
+
+    def f(v):
+        with torch.no_grad():
+            return sq.logmag_loss(plan.analyze(torch.tensor(v, dtype=torch.float64, device=dev)), ty).item()
+    g = np.random.default_rng(6)
+    for i in g.integers(0, T, 8):
+        h = 1e-4
+        e = np.zeros(T)
+        e[i] = h
+        fd = (f(x0 + e) - f(x0 - e)) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, grad[i])
