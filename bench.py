@@ -90,7 +90,8 @@ def copy_rate(nbytes: int = 1 << 30, reps: int = 10) -> float:
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "fft_device.hpp", "pipeline.hpp", "common.hpp", "plan.hpp", "plan.cpp"):
+    for f in ("kernels.hpp", "fused.hpp", "coefops.hpp", "fft_device.hpp", "pipeline.hpp", "common.hpp",
+              "plan.hpp", "plan.cpp"):
         with open(os.path.join(ROOT, "paper_1210_0084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -262,8 +263,8 @@ def bench_batched(args, copy_gbs=None):
     if args.c3_tune:
         tuned = autotune(prm, lens, "f32", cache=args.tune_cache, reps=3)
         opts = dict(tuned["options"])
-    if args.unfused:
-        opts.setdefault("fused", False)
+    if args.fused:
+        opts.setdefault("fused", True)
     plan = sq.Plan(**prm, **opts)
     lay = plan.batch_layout(lens)
     x = torch.tensor(np.concatenate([base[o:o + t] for o, t in zip(offs0, lens)]), device=dev)
@@ -312,7 +313,7 @@ def bench_differentiable(args, copy_gbs=None):
     import paper_1210_0084_amd as sq
     from workloads import make_c4
     dev = torch.device("cuda:0")
-    plan = sq.Plan(**_preset("c4"), fused=not args.unfused)
+    plan = sq.Plan(**_preset("c4"), fused=args.fused)
     xb = make_c4(args.c4_batch)
     yb = make_c4(args.c4_batch, target=True)
     B, T = xb.shape
@@ -382,7 +383,7 @@ def bench_stream(args):
     import paper_1210_0084_amd as sq
     from workloads import make_c5_stream
     torch.cuda.init()
-    plan = sq.Plan(**_preset("c5"), layout="slice", fused=not args.unfused)
+    plan = sq.Plan(**_preset("c5"), layout="slice", fused=args.fused)
     fs, hop, n_streams = 48000.0, 4096, args.c5_streams
     pool = [make_c5_stream(i, int(fs * 10)).astype(np.float32) for i in range(16)]
     srv = sq.StreamServer(plan, "f32", max_streams=n_streams + 64, max_batch=2 * n_streams)
@@ -546,14 +547,15 @@ def main():
     ap.add_argument("--c3-tune", action="store_true", help="autotune the ragged batch's work items first")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--c4-batch", type=int, default=32)
-    ap.add_argument("--unfused", action="store_true",
-                    help="batched, differentiable and streaming forms on the multi-kernel pipeline only")
+    ap.add_argument("--fused", action="store_true",
+                    help="batched, differentiable and streaming forms with one workgroup per slice where "
+                         "the half spectrum fits in LDS (default: the multi-kernel pipeline)")
     ap.add_argument("--c5-streams", type=int, default=512)
     ap.add_argument("--c5-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (slices would shard with a "
-              "one-time overlap halo exchange; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+              "one-time overlap halo exchange). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload != "c2":

@@ -88,10 +88,13 @@ typedef struct {
   int32_t m_policy;         /* coefficients per band: 0 the smallest power of two >= |J_k| (default),
                                1 one M for every band, the largest of those (the rectangular
                                representation of Section 6) */
-  int32_t unfused;          /* 0 (default): where a slice's half spectrum and its largest band
-                               transform fit one workgroup's LDS, each slice's analysis (and
-                               synthesis) runs in one workgroup with no intermediate in HBM;
-                               1: always the multi-kernel pipeline (the same results to rounding) */
+  int32_t fused;            /* 0 (default): the multi-kernel pipeline; 1: where a slice's half
+                               spectrum and its largest band transform fit one workgroup's LDS,
+                               each slice's analysis (and synthesis) runs in one workgroup with no
+                               intermediate in HBM (the same results to rounding; about 1.1x the
+                               algorithmic HBM bytes instead of about 2.6x, but bound by LDS
+                               latency and barriers at one workgroup per CU, and slower on
+                               MI355X for 2N = 16384 and 32768) */
 } slicq_plan_opts;
 
 enum { SLICQ_BAND_MAJOR = 0, SLICQ_SLICE_MAJOR = 1 };

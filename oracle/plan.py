@@ -20,7 +20,7 @@ Sources in the paper
   (equation dualwincond).
 * Section 5.3: a lower bound on the filter length ("minimal filter length").
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
 * Hann H(x) = 1/2 + 1/2 cos(2 pi x) on |x| < 1/2.
 * Minimal filter length: Omega_k is widened to ``min_win * fs / 2N`` with the
   centre kept.

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-Conventions (readings listed in the design doc):
+Conventions (readings where the paper is silent):
 * Unitary DFT  F f[j] = (2N)^{-1/2} sum_l f[l] e^{-2 pi i l j / 2N}  (Section 2.1).
 * Coefficients are the inner products of equation CQ_coeff:
   c^m_{n,k} = <F x_m, M_{-n a_k} g_k> = sum_{j in J_k} X_m[j] g_k[j] e^{2 pi i j n / M_k},

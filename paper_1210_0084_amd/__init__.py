@@ -53,7 +53,7 @@ class _Opts(ctypes.Structure):
                 ("dual_slice", ctypes.c_int32), ("group_cap", ctypes.c_int32),
                 ("lds_cap", ctypes.c_int32), ("pass_cap", ctypes.c_int32), ("coef_layout", ctypes.c_int32),
                 ("window", ctypes.c_int32), ("scale", ctypes.c_int32), ("slicing", ctypes.c_int32),
-                ("m_policy", ctypes.c_int32), ("unfused", ctypes.c_int32)]
+                ("m_policy", ctypes.c_int32), ("fused", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -243,14 +243,14 @@ class Plan:
     def __init__(self, fs: float, fmin: float, fmax: float, bins_per_octave: int, slice_len: int,
                  transition: int, min_win: float = 16.0, dual_slice: str = "canonical",
                  group_cap: int = 0, lds_cap: int = 0, pass_cap: int = 0, layout: str = "band",
-                 fused: bool = True, window: str = "hann", scale: str = "cq", slicing: str = "tukey",
+                 fused: bool = False, window: str = "hann", scale: str = "cq", slicing: str = "tukey",
                  m_policy: str = "pow2"):
         lib = load_library()
         o = _Opts(float(fs), float(fmin), float(fmax), int(bins_per_octave), int(slice_len), int(transition),
                   float(min_win), {"canonical": 0, "indicator": 1}[dual_slice], int(group_cap), int(lds_cap),
                   int(pass_cap), {"band": 0, "slice": 1}[layout],
                   {"hann": 0, "blackman_harris": 1}[window], {"cq": 0, "mel": 1, "bark": 2}[scale],
-                  {"tukey": 0, "sqrt_tukey": 1}[slicing], {"pow2": 0, "rect": 1}[m_policy], 0 if fused else 1)
+                  {"tukey": 0, "sqrt_tukey": 1}[slicing], {"pow2": 0, "rect": 1}[m_policy], 1 if fused else 0)
         h = ctypes.c_void_p()
         _check(lib.nsgt_plan_ex(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -511,7 +511,7 @@ int nsgt_plan_ex(const slicq_plan_opts* o, slicq_plan* out) {
   if (o->lds_cap) pp.lds_cap = o->lds_cap;
   if (o->pass_cap) pp.pass_cap = o->pass_cap;
   pp.coef_layout = o->coef_layout;
-  pp.fused = o->unfused ? 0 : 1;
+  pp.fused = o->fused ? 1 : 0;
   pp.window = o->window;
   pp.scale = o->scale;
   pp.slicing = o->slicing;

@@ -134,7 +134,7 @@ def test_fused_and_pipeline_agree(sq, dev, dt):
     # fits one workgroup in both FP32 and FP64
     import torch
     kw = preset("c1")
-    fused = sq.Plan(**kw)
+    fused = sq.Plan(**kw, fused=True)
     pipe = sq.Plan(**kw, fused=False)
     assert {0, 1} <= fused.fused_dtypes and not pipe.fused_dtypes
     x = torch.tensor(noise_plus_sines(50000, 44100.0, 12), dtype=torch_dtype(dt), device=dev)
