@@ -5,10 +5,16 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 For a sliCQ plan with slice length 2N and a signal length L (a multiple of
 2N), the full-length system uses the same band windows in Hz, sampled on the
-L-point grid: g^L_k[j L / 2N] = g_k[j] (Proposition 4's relation), with
-L / a_k = M_k L / 2N coefficients per band, so that both transforms sample
-the same time-frequency lattice. Its coefficients are (Algorithm 1 at length
-L, unitary DFT) c_{n,k} = sum_j (F_L f)[j] g^L_k[j] e^{2 pi i j n / M^L_k}.
+L-point grid: g^L_k[j L / 2N] = g_k[j] (Proposition 4's relation). Two
+lattices: "slicq" takes L / a_k = M_k L / 2N coefficients per band, so that
+both transforms sample the same time-frequency lattice (the comparison of
+Proposition 4); "painless" takes the smallest power of two >= |J^L_k| (at
+least 2; one M for all bands on a rectangular plan), the condition of
+Proposition 2 under which the frame operator is diagonal. Its coefficients
+are (Algorithm 1 at length L, unitary DFT)
+c_{n,k} = sum_j (F_L f)[j] g^L_k[j] e^{2 pi i j n / M^L_k}, and synthesis is
+Algorithm 2 at length L with the canonical duals g^L_k / D^L,
+D^L = sum_k M^L_k |g^L_k|^2 over all 2K+2 bands.
 """
 from __future__ import annotations
 
@@ -20,9 +26,12 @@ import numpy as np
 from .plan import BandTable, window_value
 
 
-def full_length_bands(plan, L: int, all_bands: bool = True) -> List[BandTable]:
+def full_length_bands(plan, L: int, all_bands: bool = True, lattice: str = "slicq") -> List[BandTable]:
     """Band windows of ``plan`` (same centres, bandwidths, widening and
-    plateaus, in Hz) on the L-point grid, M^L_k = M_k L / 2N."""
+    plateaus, in Hz) on the L-point grid; M^L_k = M_k L / 2N ("slicq") or
+    the smallest power of two >= |J^L_k| ("painless")."""
+    if lattice not in ("slicq", "painless"):
+        raise ValueError("lattice must be 'slicq' or 'painless'")
     fs, two_n = plan.fs, plan.two_n
     if L % two_n:
         raise ValueError("L must be a multiple of 2N")
@@ -49,6 +58,13 @@ def full_length_bands(plan, L: int, all_bands: bool = True) -> List[BandTable]:
             js = [j for j in range(lo, hi + 1) if abs((j * fs / L - xi) / om) < 0.5]
             g = np.array([window_value(plan.window, (j * fs / L - xi) / om) for j in js])
             out.append(BandTable(b.k, js[0], g, b.M * r))
+    if lattice == "painless":
+        for b in out:
+            b.M = max(2, 1 << max(0, int(b.length - 1).bit_length()))
+        if getattr(plan, "m_policy", "pow2") == "rect":
+            Mr = max(b.M for b in out)
+            for b in out:
+                b.M = Mr
     if all_bands:
         for k in range(K + 2, 2 * K + 2):
             src = out[2 * K + 2 - k]
@@ -69,6 +85,31 @@ def nsgt_full(bands, f) -> List[np.ndarray]:
         np.add.at(buf, j % b.M, X[j % L] * b.g)
         out.append(np.fft.ifft(buf) * b.M)
     return out
+
+
+def full_dual(bands, L: int) -> List[np.ndarray]:
+    """Canonical dual windows g^L_k / D^L over each J^L_k (Proposition 2 at
+    length L), D^L[j] = sum_k M^L_k g^L_k[j]^2 over the given bands (all
+    2K+2 of them for the complex transform)."""
+    D = np.zeros(L)
+    for b in bands:
+        np.add.at(D, b.bins() % L, b.M * b.g ** 2)
+    if np.any(D <= 0):
+        raise ValueError("frame condition fails: D^L has a zero")
+    return [b.g / D[b.bins() % L] for b in bands]
+
+
+def nsgt_full_synthesize(bands, coefs, L: int) -> np.ndarray:
+    """Algorithm 2 at length L: C_k = DFT_{M_k}(c_k) (unnormalised, e^-),
+    Z[j] = sum_k gd_k[j] C_k[j mod M_k] over j in J^L_k, then the unitary
+    inverse DFT of length L. The inverse of ``nsgt_full`` when every band
+    satisfies M^L_k >= |J^L_k| (the painless case)."""
+    Z = np.zeros(L, dtype=np.complex128)
+    for b, gd, c in zip(bands, full_dual(bands, L), coefs):
+        C = np.fft.fft(np.asarray(c, dtype=np.complex128))
+        j = b.bins()
+        np.add.at(Z, j % L, gd * C[j % b.M])
+    return np.fft.ifft(Z) * math.sqrt(L)
 
 
 def snr_db(c, approx) -> float:
