@@ -413,6 +413,78 @@ int slicq_profile_stage_batch(slicq_batch batch, slicq_dtype dtype, int stage, c
                               void* coef, int64_t coef_len, void* y, int64_t y_len, void* work, size_t work_bytes,
                               void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Full-length CQ-NSGT: Algorithms 1 and 2 run at the signal length L instead
+ * of the slice length (Section 3), on a complex signal, onto all 2K+2 bands.
+ * The band windows are the sliCQ plan's (same centres, bandwidths after the
+ * minimal filter length, plateaus, window shape) sampled on the L-point grid,
+ * so that g_k[j] = g^L_k[j L / 2N] (the relation of Proposition 4). Bands
+ * 0..K+1 come first, then the mirrors K+2..2K+1 of bands K..1.
+ *
+ * lattice 0: M^L_k = M_k L / 2N coefficients per band, the sliCQ's
+ *   time-frequency lattice (what Proposition 4 and the approximation study of
+ *   Section 5.3 compare s^0 + s^1 with, after rescaling by sqrt(2N / L) with
+ *   unitary DFTs). A band may alias (|J^L_k| > M^L_k): analysis is still the
+ *   inner products of equation CQ_coeff, but synthesis is refused.
+ * lattice 1: M^L_k the smallest power of two >= |J^L_k| (>= 2; one M for all
+ *   bands on a rectangular plan): the painless case of Proposition 2, whose
+ *   canonical dual g^L_k / D^L, D^L = sum_k M^L_k |g^L_k|^2, gives perfect
+ *   reconstruction.
+ *
+ * L must be a power of two, at least 2N and at most 2^24; every M^L_k at most
+ * 2^24. Coefficients are complex interleaved (f32 or f64), band k at
+ * off_k .. off_k + M^L_k - 1 (nsgt_full_bands):
+ *   c_{n,k} = sum_j (F_L f)[j] g^L_k[j] e^{2 pi i j n / M^L_k}
+ * with the unitary DFT F_L. Signals are L complex values, interleaved.
+ * Tables are uploaded once per dtype into caller-owned device memory
+ * (256-byte aligned, kept alive while the plan is used), as for the sliCQ
+ * plan. The transforms enqueue on hip_stream, never synchronise and never
+ * allocate; the workspace (nsgt_full_workspace_size) is caller-owned and
+ * may be reused once the call's work is complete. */
+typedef struct slicq_full_s* slicq_full;
+
+typedef struct {
+  int64_t L;              /* signal length */
+  int32_t nbands;         /* 2K + 2 */
+  int32_t lattice;        /* 0 sliCQ hops, 1 painless */
+  int32_t painless;       /* 1 when every band has M^L_k >= |J^L_k| (synthesis allowed) */
+  int32_t pad_;
+  int64_t coef_count;     /* sum_k M^L_k */
+  int64_t max_M;          /* largest M^L_k */
+  int64_t entries;        /* sum_k |J^L_k| (synthesis overlap-add entries) */
+} slicq_full_info;
+
+/* Builds the full-length plan of `plan` at length L (host only; FP64).
+ * SLICQ_EINVAL for L or lattice out of range, a band with no bin on the
+ * L-point grid, a zero of D^L, or coefficient counts reaching 2^31. */
+int nsgt_full_plan(slicq_plan plan, int64_t L, int32_t lattice, slicq_full* out);
+void nsgt_full_destroy(slicq_full full);
+int nsgt_full_info(slicq_full full, slicq_full_info* info);
+/* Per band (arrays of nbands, any may be NULL): first signed bin of J^L_k,
+ * |J^L_k|, M^L_k and the coefficient offset. */
+int nsgt_full_bands(slicq_full full, int64_t* start, int32_t* len, int32_t* M, int64_t* off);
+/* g^L_k and the canonical dual g^L_k / D^L over each J^L_k, concatenated in
+ * band order (entries doubles each; either may be NULL). */
+int nsgt_full_windows(slicq_full full, double* g, double* gd);
+int nsgt_full_table_bytes(slicq_full full, slicq_dtype dtype, size_t* bytes);
+int nsgt_full_upload(slicq_full full, slicq_dtype dtype, void* dev_tables, size_t bytes, void* hip_stream);
+/* Bytes of workspace for either transform: complex values for the band
+ * spectra (coef_count), one length-L spectrum and the scratch of the
+ * four-step FFTs (max(L, coef_count)). */
+int nsgt_full_workspace_size(slicq_full full, slicq_dtype dtype, size_t* bytes);
+/* Analysis (Algorithm 1 at length L): unitary DFT of x (L complex values),
+ * X g^L_k wrapped modulo M^L_k, inverse DFTs of length M^L_k (unnormalised)
+ * into coef (coef_count >= info.coef_count complex values, else
+ * SLICQ_ESIZE). */
+int nsgt_full_analyze(slicq_full full, slicq_dtype dtype, const void* x, void* coef, int64_t coef_count, void* work,
+                      size_t work_bytes, void* hip_stream);
+/* Synthesis (Algorithm 2 at length L): DFTs of length M^L_k, overlap-add of
+ * g^L_k / D^L times each band's spectrum at j mod M^L_k, unitary inverse DFT
+ * into y (L complex values). The inverse of nsgt_full_analyze; SLICQ_EINVAL
+ * on a plan whose lattice aliases a band (info.painless == 0). */
+int nsgt_full_synthesize(slicq_full full, slicq_dtype dtype, const void* coef, int64_t coef_count, void* y,
+                         void* work, size_t work_bytes, void* hip_stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* slicq_last_error(void);
 

@@ -64,6 +64,12 @@ class _Info(ctypes.Structure):
                 ("coefs_per_slice_all", ctypes.c_int64)]
 
 
+class _FullInfo(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int64), ("nbands", ctypes.c_int32), ("lattice", ctypes.c_int32),
+                ("painless", ctypes.c_int32), ("pad_", ctypes.c_int32), ("coef_count", ctypes.c_int64),
+                ("max_M", ctypes.c_int64), ("entries", ctypes.c_int64)]
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -130,6 +136,16 @@ def load_library():
         "slicq_stream_stats_reset": (ctypes.c_int, [P]),
         "slicq_stream_snapshot": (ctypes.c_int, [P, I32, P, SZ, ctypes.POINTER(SZ)]),
         "slicq_stream_restore": (ctypes.c_int, [P, I32, P, SZ]),
+        "nsgt_full_plan": (ctypes.c_int, [P, I64, I32, ctypes.POINTER(P)]),
+        "nsgt_full_destroy": (None, [P]),
+        "nsgt_full_info": (ctypes.c_int, [P, ctypes.POINTER(_FullInfo)]),
+        "nsgt_full_bands": (ctypes.c_int, [P, P, P, P, P]),
+        "nsgt_full_windows": (ctypes.c_int, [P, P, P]),
+        "nsgt_full_table_bytes": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(SZ)]),
+        "nsgt_full_upload": (ctypes.c_int, [P, ctypes.c_int, P, SZ, P]),
+        "nsgt_full_workspace_size": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(SZ)]),
+        "nsgt_full_analyze": (ctypes.c_int, [P, ctypes.c_int, P, P, I64, P, SZ, P]),
+        "nsgt_full_synthesize": (ctypes.c_int, [P, ctypes.c_int, P, I64, P, P, SZ, P]),
         "slicq_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -644,6 +660,105 @@ class Plan:
                                              ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                              ctypes.c_void_p(w.data_ptr()), wb,
                                              ctypes.c_void_p(_stream_ptr(x.device))))
+
+
+class FullPlan:
+    """The full-length CQ-NSGT of complex signals of length L (Algorithms 1
+    and 2 at length L, Section 3) on the band windows of a sliCQ ``plan``
+    sampled on the L-point grid, all 2K+2 bands (0..K+1, then the mirrors of
+    K..1). ``lattice="slicq"`` keeps the sliCQ hops (M^L_k = M_k L / 2N: the
+    lattice Proposition 4 compares s^0 + s^1 with); ``lattice="painless"``
+    takes the smallest power of two >= |J^L_k|, for which synthesis is the
+    exact inverse (Proposition 2)."""
+
+    def __init__(self, plan: "Plan", L: int, lattice: str = "slicq"):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.nsgt_full_plan(plan._h, int(L), {"slicq": 0, "painless": 1}[lattice], ctypes.byref(h)))
+        self._h, self._lib, self.plan = h, lib, plan
+        info = _FullInfo()
+        _check(lib.nsgt_full_info(h, ctypes.byref(info)))
+        self.L, self.nbands, self.coef_count = info.L, info.nbands, info.coef_count
+        self.painless, self.max_M, self.entries = bool(info.painless), info.max_M, info.entries
+        self.lattice = lattice
+        nb = self.nbands
+        self.starts = np.zeros(nb, dtype=np.int64)
+        self.lengths = np.zeros(nb, dtype=np.int32)
+        self.M = np.zeros(nb, dtype=np.int32)
+        self.offsets = np.zeros(nb, dtype=np.int64)
+        _check(lib.nsgt_full_bands(h, self.starts.ctypes.data, self.lengths.ctypes.data, self.M.ctypes.data,
+                                   self.offsets.ctypes.data))
+        self._tables, self._work = {}, {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.nsgt_full_destroy(h)
+            self._h = None
+
+    def windows(self):
+        """FP64 host tables (g^L, its canonical dual), concatenated over J^L_k."""
+        tot = int(self.lengths.sum())
+        g, gd = np.zeros(tot), np.zeros(tot)
+        _check(self._lib.nsgt_full_windows(self._h, g.ctypes.data, gd.ctypes.data))
+        return g, gd
+
+    def band(self, coef, k: int):
+        """View of band k's M^L_k coefficients."""
+        o = int(self.offsets[k])
+        return coef[o:o + int(self.M[k])]
+
+    def _prepare(self, dt: int, device):
+        torch = _torch()
+        key = (dt, str(device))
+        if key not in self._tables:
+            nbytes = ctypes.c_size_t()
+            _check(self._lib.nsgt_full_table_bytes(self._h, dt, ctypes.byref(nbytes)))
+            buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+            off = (-buf.data_ptr()) % 256
+            _check(self._lib.nsgt_full_upload(self._h, dt, ctypes.c_void_p(buf.data_ptr() + off), nbytes.value,
+                                              ctypes.c_void_p(_stream_ptr(device))))
+            self._tables[key] = buf
+        if key not in self._work:
+            b = ctypes.c_size_t()
+            _check(self._lib.nsgt_full_workspace_size(self._h, dt, ctypes.byref(b)))
+            self._work[key] = torch.empty(b.value, dtype=torch.uint8, device=device)
+        return self._work[key]
+
+    def analyze(self, x, out=None):
+        """Coefficients (coef_count complex values, band k at offsets[k]) of the
+        complex signal x (L values)."""
+        torch = _torch()
+        _require_cuda(x, "x")
+        if not x.is_complex() or x.numel() != self.L:
+            raise SlicqError(f"x must be a complex tensor of L = {self.L} values")
+        dt = _dtype_code(x)
+        if out is None:
+            out = torch.empty(self.coef_count, dtype=x.dtype, device=x.device)
+        _require_cuda(out, "out")
+        w = self._prepare(dt, x.device)
+        _check(self._lib.nsgt_full_analyze(self._h, dt, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                           out.numel(), ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                           ctypes.c_void_p(_stream_ptr(x.device))))
+        return out
+
+    def synthesize(self, coef, out=None):
+        """The complex signal (L values) of coefficients on every band."""
+        torch = _torch()
+        _require_cuda(coef, "coef")
+        if not coef.is_complex():
+            raise SlicqError("coef must be complex")
+        dt = _dtype_code(coef)
+        if out is None:
+            out = torch.empty(self.L, dtype=coef.dtype, device=coef.device)
+        _require_cuda(out, "out")
+        if out.numel() < self.L:
+            raise SlicqError("out must hold L values")
+        w = self._prepare(dt, coef.device)
+        _check(self._lib.nsgt_full_synthesize(self._h, dt, ctypes.c_void_p(coef.data_ptr()), coef.numel(),
+                                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                              w.numel(), ctypes.c_void_p(_stream_ptr(coef.device))))
+        return out
 
 
 class StreamServer:

@@ -12,6 +12,7 @@
 
 #include "../../include/slicq.h"
 #include "coefops.hpp"
+#include "fullnsgt.hpp"
 #include "pipeline.hpp"
 #include "stream_server.hpp"
 
@@ -24,6 +25,11 @@ static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 struct slicq_plan_s {
   slicq::Plan p;
+  std::vector<unsigned char> blob[2];   // packed tables, kept alive for async uploads
+};
+
+struct slicq_full_s {
+  slicq::FullPlan f;
   std::vector<unsigned char> blob[2];   // packed tables, kept alive for async uploads
 };
 
@@ -1153,5 +1159,156 @@ int slicq_profile_stage_batch(slicq_batch b, slicq_dtype dt, int stage, const vo
 }
 
 const char* slicq_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Full-length CQ-NSGT (Algorithms 1 and 2 at the signal length L)
+
+namespace {
+
+int check_full(slicq_full full, slicq_dtype dt) {
+  if (!full) return fail(SLICQ_EINVAL, "null full-length plan");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "dtype must be SLICQ_F32 or SLICQ_F64");
+  if (!full->f.dev[dt]) return fail(SLICQ_ESTATE, "full-length tables not uploaded for this dtype (nsgt_full_upload)");
+  return SLICQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nsgt_full_plan(slicq_plan plan, int64_t L, int32_t lattice, slicq_full* out) {
+  if (!plan || !out) return fail(SLICQ_EINVAL, "null argument");
+  *out = nullptr;
+  auto* h = new (std::nothrow) slicq_full_s();
+  if (!h) return fail(SLICQ_ENOMEM, "out of host memory");
+  std::string err;
+  if (slicq::build_full(plan->p, L, lattice, h->f, err) != 0) {
+    delete h;
+    return fail(SLICQ_EINVAL, err);
+  }
+  *out = h;
+  return SLICQ_OK;
+}
+
+void nsgt_full_destroy(slicq_full full) { delete full; }
+
+int nsgt_full_info(slicq_full full, slicq_full_info* info) {
+  if (!full || !info) return fail(SLICQ_EINVAL, "null argument");
+  const slicq::FullPlan& f = full->f;
+  std::memset(info, 0, sizeof *info);
+  info->L = f.L;
+  info->nbands = f.nb;
+  info->lattice = f.lattice;
+  info->painless = f.painless ? 1 : 0;
+  info->coef_count = f.coef_count;
+  info->max_M = f.max_M;
+  info->entries = (int64_t)f.ent_idx.size();
+  return SLICQ_OK;
+}
+
+int nsgt_full_bands(slicq_full full, int64_t* start, int32_t* len, int32_t* M, int64_t* off) {
+  if (!full) return fail(SLICQ_EINVAL, "null full-length plan");
+  const auto& b = full->f.bands;
+  for (size_t k = 0; k < b.size(); ++k) {
+    if (start) start[k] = b[k].start;
+    if (len) len[k] = b[k].len;
+    if (M) M[k] = b[k].M;
+    if (off) off[k] = b[k].off;
+  }
+  return SLICQ_OK;
+}
+
+int nsgt_full_windows(slicq_full full, double* g, double* gd) {
+  if (!full) return fail(SLICQ_EINVAL, "null full-length plan");
+  const slicq::FullPlan& f = full->f;
+  if (g) std::memcpy(g, f.g.data(), f.g.size() * sizeof(double));
+  if (gd)
+    for (const auto& b : f.bands)
+      for (int32_t t = 0; t < b.len; ++t) {
+        int64_t j = (b.start + t) % f.L;
+        if (j < 0) j += f.L;
+        gd[b.goff + t] = f.g[b.goff + t] / f.D[j];
+      }
+  return SLICQ_OK;
+}
+
+int nsgt_full_table_bytes(slicq_full full, slicq_dtype dt, size_t* bytes) {
+  if (!full || !bytes) return fail(SLICQ_EINVAL, "null argument");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "bad dtype");
+  std::lock_guard<std::mutex> lk(full->f.mu);
+  if (full->blob[dt].empty()) slicq::pack_full_tables(full->f, dt, full->blob[dt], full->f.layout[dt]);
+  *bytes = full->blob[dt].size();
+  return SLICQ_OK;
+}
+
+int nsgt_full_upload(slicq_full full, slicq_dtype dt, void* dev, size_t bytes, void* stream) {
+  size_t need = 0;
+  int rc = nsgt_full_table_bytes(full, dt, &need);
+  if (rc) return rc;
+  if (!dev) return fail(SLICQ_EINVAL, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(SLICQ_EINVAL, "device tables must be 256-byte aligned");
+  if (bytes < need) return fail(SLICQ_ESIZE, "device table buffer too small");
+  std::lock_guard<std::mutex> lk(full->f.mu);
+  hipError_t e = hipMemcpyAsync(dev, full->blob[dt].data(), need, hipMemcpyHostToDevice,
+                                static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  full->f.dev[dt] = dev;
+  full->f.dev_bytes[dt] = bytes;
+  return SLICQ_OK;
+}
+
+int nsgt_full_workspace_size(slicq_full full, slicq_dtype dt, size_t* bytes) {
+  if (!full || !bytes) return fail(SLICQ_EINVAL, "null argument");
+  if (dt != SLICQ_F32 && dt != SLICQ_F64) return fail(SLICQ_EINVAL, "bad dtype");
+  *bytes = slicq::full_work(full->f, dt).total;
+  return SLICQ_OK;
+}
+
+int nsgt_full_analyze(slicq_full full, slicq_dtype dt, const void* x, void* coef, int64_t coef_count, void* work,
+                      size_t work_bytes, void* stream) {
+  int rc = check_full(full, dt);
+  if (rc) return rc;
+  const slicq::FullPlan& f = full->f;
+  if (!x || !coef || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (coef_count < f.coef_count) return fail(SLICQ_ESIZE, "coef_count below the plan's coefficient count");
+  const slicq::FullWork w = slicq::full_work(f, dt);
+  if (work_bytes < w.total) return fail(SLICQ_ESIZE, "workspace smaller than nsgt_full_workspace_size");
+  const char* tabs = static_cast<const char*>(f.dev[dt]);
+  HipLaunch ln{static_cast<hipStream_t>(stream)};
+  if (dt == SLICQ_F32)
+    slicq::full_analyze_launch<float>(ln, f, tabs, f.layout[dt], static_cast<const slicq::C2<float>*>(x),
+                                      static_cast<slicq::C2<float>*>(coef), static_cast<char*>(work), w);
+  else
+    slicq::full_analyze_launch<double>(ln, f, tabs, f.layout[dt], static_cast<const slicq::C2<double>*>(x),
+                                       static_cast<slicq::C2<double>*>(coef), static_cast<char*>(work), w);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "full-length analysis launch");
+}
+
+int nsgt_full_synthesize(slicq_full full, slicq_dtype dt, const void* coef, int64_t coef_count, void* y, void* work,
+                         size_t work_bytes, void* stream) {
+  int rc = check_full(full, dt);
+  if (rc) return rc;
+  const slicq::FullPlan& f = full->f;
+  if (!f.painless)
+    return fail(SLICQ_EINVAL, "synthesis needs M_k >= |J_k| on every band (painless lattice, Proposition 2); "
+                              "this plan's lattice aliases some band");
+  if (!y || !coef || !work) return fail(SLICQ_EINVAL, "null buffer");
+  if (coef_count < f.coef_count) return fail(SLICQ_ESIZE, "coef_count below the plan's coefficient count");
+  const slicq::FullWork w = slicq::full_work(f, dt);
+  if (work_bytes < w.total) return fail(SLICQ_ESIZE, "workspace smaller than nsgt_full_workspace_size");
+  const char* tabs = static_cast<const char*>(f.dev[dt]);
+  HipLaunch ln{static_cast<hipStream_t>(stream)};
+  if (dt == SLICQ_F32)
+    slicq::full_synthesize_launch<float>(ln, f, tabs, f.layout[dt], static_cast<const slicq::C2<float>*>(coef),
+                                         static_cast<slicq::C2<float>*>(y), static_cast<char*>(work), w);
+  else
+    slicq::full_synthesize_launch<double>(ln, f, tabs, f.layout[dt], static_cast<const slicq::C2<double>*>(coef),
+                                          static_cast<slicq::C2<double>*>(y), static_cast<char*>(work), w);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SLICQ_OK : hip_fail(e, "full-length synthesis launch");
+}
 
 }  // extern "C"

@@ -146,4 +146,24 @@ struct alignas(16) OlaRec {
 constexpr uint32_t kOlaMore = 0x8000u, kOlaPosMask = 0x3fffu, kOlaNone = 0xffffu;
 static_assert(kSynMaxValues <= 0x4000, "overlap-add positions must fit 14 bits");
 
+// Full-length CQ-NSGT (Algorithms 1 and 2 at the signal length L): band k
+// over J^L_k = {start, ..., start + len - 1} (signed bins, circular modulo
+// L), M^L_k coefficients at offset off, window values at goff.
+struct alignas(16) FullBandDev {
+  int64_t start, off, goff;
+  int32_t len, M;
+};
+
+// Device tables of a full-length plan (byte offsets in one blob).
+struct FullLayout {
+  size_t bands = 0, g = 0, ent_off = 0, ent_idx = 0, ent_w = 0, tw = 0, total = 0;
+};
+
+// Complex values one block of the long-transform kernels holds in LDS (16
+// per thread of 256): transforms up to this length run in one block, longer
+// ones (up to kLongVals^2) as two passes of a four-step FFT.
+constexpr int kLongVals = 4096;
+constexpr int kLongLog = 12;
+constexpr int kLongThreads = 256;
+
 }  // namespace slicq

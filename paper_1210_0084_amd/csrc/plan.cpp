@@ -779,4 +779,154 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
   lay.total = blob.size();
 }
 
+int build_full(const Plan& p, int64_t L, int lattice, FullPlan& out, std::string& err) {
+  const double fs = p.prm.fs;
+  if (lattice < 0 || lattice > 1) {
+    err = "lattice must be 0 (sliCQ hops) or 1 (painless)";
+    return -1;
+  }
+  if (L < p.two_n || (L & (L - 1)) || L > (int64_t(1) << (2 * kLongLog))) {
+    err = "L must be a power of two, at least the slice length 2N and at most 2^24";
+    return -1;
+  }
+  const int64_t r = L / p.two_n;
+  const int K = p.K;
+  out.L = L;
+  out.two_n = p.two_n;
+  out.logL = ilog2(L);
+  out.lattice = lattice;
+  out.nb = 2 * K + 2;
+  // the slice plan's bands (centres, bandwidths after widening, plateau
+  // radii and flanks in Hz) sampled on the L-point grid
+  std::vector<RawBand> raw;
+  {
+    const double R0 = p.bands[1].xi, w0 = std::min(p.bands[1].omega / 2, R0);
+    raw.push_back(plateau_band(fs, L, 0, R0, w0, 0.0, 2.0 * R0));
+    for (int k = 1; k <= K; ++k) raw.push_back(cq_band(p.prm.window, fs, L, p.bands[k].xi, p.bands[k].omega));
+    const double RN = fs / 2 - p.bands[K].xi, wN = std::min(p.bands[K].omega / 2, RN);
+    raw.push_back(plateau_band(fs, L, L / 2, RN, wN, fs / 2, fs - 2 * p.bands[K].xi));
+  }
+  for (int k = 0; k < K + 2; ++k) {
+    if (raw[k].g.empty()) {
+      err = "a band has no bin on the L-point grid";
+      return -1;
+    }
+    if (lattice == 0) raw[k].M = (int64_t)p.bands[k].M * r;
+  }
+  if (lattice == 1 && p.prm.m_policy == 1) {
+    int64_t Mr = 0;
+    for (const RawBand& b : raw) Mr = std::max(Mr, b.M);
+    for (RawBand& b : raw) b.M = Mr;
+  }
+  // mirrors K+2 .. 2K+1 of bands K .. 1: reversed supports, reversed windows
+  for (int k = K + 2; k < 2 * K + 2; ++k) {
+    const RawBand& s = raw[2 * K + 2 - k];
+    RawBand m;
+    m.start = -(s.start + (int64_t)s.g.size() - 1);
+    m.g.assign(s.g.rbegin(), s.g.rend());
+    m.M = s.M;
+    raw.push_back(m);
+  }
+  auto wrap = [L](int64_t j) {
+    j %= L;
+    return j < 0 ? j + L : j;
+  };
+  out.D.assign(L, 0.0);
+  out.painless = true;
+  out.max_M = 0;
+  for (const RawBand& b : raw) {
+    for (size_t t = 0; t < b.g.size(); ++t) out.D[wrap(b.start + (int64_t)t)] += (double)b.M * b.g[t] * b.g[t];
+    if ((int64_t)b.g.size() > b.M) out.painless = false;
+    if (b.M > (int64_t(1) << (2 * kLongLog))) {
+      err = "a band's coefficient count exceeds 2^24";
+      return -1;
+    }
+    out.max_M = std::max(out.max_M, b.M);
+  }
+  for (int64_t j = 0; j < L; ++j)
+    if (!(out.D[j] > 0)) {
+      err = "frame condition fails on the L-point grid: the frame-operator diagonal has a zero";
+      return -1;
+    }
+  out.bands.clear();
+  out.g.clear();
+  out.runs.clear();
+  int64_t off = 0, goff = 0;
+  for (size_t k = 0; k < raw.size(); ++k) {
+    const RawBand& b = raw[k];
+    FullBandDev d{};
+    d.start = b.start;
+    d.off = off;
+    d.goff = goff;
+    d.len = (int32_t)b.g.size();
+    d.M = (int32_t)b.M;
+    out.bands.push_back(d);
+    out.g.insert(out.g.end(), b.g.begin(), b.g.end());
+    if (!out.runs.empty() && (int64_t(1) << out.runs.back().logn) == b.M) ++out.runs.back().count;
+    else out.runs.push_back(FullRun{off, 1, ilog2(b.M)});
+    off += b.M;
+    goff += d.len;
+  }
+  out.coef_count = off;
+  if (off >= (int64_t(1) << 31) || goff >= (int64_t(1) << 31)) {
+    err = "coefficient count or synthesis entries reach 2^31";
+    return -1;
+  }
+  // synthesis entries sorted by bin (counting sort), bands in increasing order
+  out.ent_off.assign(L + 1, 0);
+  for (const FullBandDev& b : out.bands)
+    for (int32_t t = 0; t < b.len; ++t) ++out.ent_off[wrap(b.start + t) + 1];
+  for (int64_t j = 0; j < L; ++j) out.ent_off[j + 1] += out.ent_off[j];
+  out.ent_idx.assign(goff, 0);
+  out.ent_w.assign(goff, 0.0);
+  std::vector<int32_t> fill(out.ent_off.begin(), out.ent_off.end() - 1);
+  for (const FullBandDev& b : out.bands)
+    for (int32_t t = 0; t < b.len; ++t) {
+      const int64_t j = wrap(b.start + t);
+      int64_t q = (b.start + t) % b.M;
+      if (q < 0) q += b.M;
+      const int32_t e = fill[j]++;
+      out.ent_idx[e] = (int32_t)(b.off + q);
+      out.ent_w[e] = out.g[b.goff + t] / out.D[j];
+    }
+  return 0;
+}
+
+void pack_full_tables(const FullPlan& f, int dtype, std::vector<unsigned char>& blob, FullLayout& lay) {
+  blob.clear();
+  // twiddle pyramid of the one-block transforms: entry n + k holds e^{-2 pi i k / n}, n <= kLongVals
+  std::vector<double> tw(4 * kLongVals, 0.0);
+  for (int64_t n = 1; n <= kLongVals; n <<= 1)
+    for (int64_t k = 0; k < n; ++k) {
+      const double a = 2.0 * M_PI * (double)k / (double)n;
+      double c = std::cos(a), s = -std::sin(a);
+      if (4 * k == n) { c = 0.0; s = -1.0; }
+      if (2 * k == n) { c = -1.0; s = 0.0; }
+      if (4 * k == 3 * n) { c = 0.0; s = 1.0; }
+      if (8 * k == n) { c = std::sqrt(0.5); s = -std::sqrt(0.5); }
+      tw[2 * (n + k)] = c;
+      tw[2 * (n + k) + 1] = s;
+    }
+  lay.bands = append(blob, f.bands.data(), f.bands.size());
+  lay.ent_off = append(blob, f.ent_off.data(), f.ent_off.size());
+  lay.ent_idx = append(blob, f.ent_idx.data(), f.ent_idx.size());
+  if (dtype == 0) {
+    auto cvt = [](const std::vector<double>& v) {
+      std::vector<float> o(v.size());
+      for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+      return o;
+    };
+    const std::vector<float> g = cvt(f.g), w = cvt(f.ent_w), t = cvt(tw);
+    lay.g = append(blob, g.data(), g.size());
+    lay.ent_w = append(blob, w.data(), w.size());
+    lay.tw = append(blob, t.data(), t.size());
+  } else {
+    lay.g = append(blob, f.g.data(), f.g.size());
+    lay.ent_w = append(blob, f.ent_w.data(), f.ent_w.size());
+    lay.tw = append(blob, tw.data(), tw.size());
+  }
+  blob.resize((blob.size() + 255) & ~size_t(255));
+  lay.total = blob.size();
+}
+
 }  // namespace slicq

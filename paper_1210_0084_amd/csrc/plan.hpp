@@ -21,7 +21,7 @@ struct PlanParams {
   int32_t lds_cap = 4096;       // target complex values per synthesis work item
   int32_t pass_cap = 4096;      // complex values per four-step FFT work item
   int32_t coef_layout = 0;      // 0: band-major, 1: slice-major
-  int32_t fused = 1;            // 1: one workgroup per slice where the half spectrum fits in LDS, 0: never
+  int32_t fused = 0;            // 1: one workgroup per slice where the half spectrum fits in LDS, 0: never
   int32_t window = 0;           // band window: 0 Hann, 1 Blackman-Harris (4 terms)
   int32_t scale = 0;            // centres: 0 constant-Q (geometric), 1 mel, 2 Bark
   int32_t slicing = 0;          // 0 Tukey (sum_m h_m = 1), 1 square root of Tukey (sum_m h_m^2 = 1)
@@ -98,6 +98,46 @@ struct Plan {
   size_t dev_bytes[2] = {0, 0};
   TableLayout layout[2] = {};
 };
+
+// Full-length CQ-NSGT of a complex signal of length L (Algorithms 1 and 2 at
+// length L, Section 3) on the band windows of a sliCQ plan sampled on the
+// L-point grid (g_k[j] = g^L_k[j L / 2N], Proposition 4), all 2K+2 bands:
+// 0..K+1, then the mirrors of K..1. Lattice 0 keeps the sliCQ hops
+// (M^L_k = M_k L / 2N), lattice 1 takes the smallest power of two >= |J^L_k|
+// (the painless case of Proposition 2).
+struct FullRun {
+  int64_t off;          // first coefficient of the run
+  int32_t count;        // consecutive bands with equal M^L_k
+  int32_t logn;         // log2 M^L_k
+};
+
+struct FullPlan {
+  int64_t L = 0, two_n = 0;
+  int32_t logL = 0, lattice = 0, nb = 0;
+  bool painless = false;               // every band has M^L_k >= |J^L_k|
+  std::vector<FullBandDev> bands;
+  std::vector<double> g;               // windows over each J^L_k, concatenated
+  std::vector<double> D;               // frame-operator diagonal, L bins
+  // synthesis gather: bin j takes entries [ent_off[j], ent_off[j + 1]) of
+  // (coefficient index, dual weight), bands in increasing order
+  std::vector<int32_t> ent_off, ent_idx;
+  std::vector<double> ent_w;
+  std::vector<FullRun> runs;
+  int64_t coef_count = 0, max_M = 0;
+
+  // device tables, per dtype; owned by the caller
+  std::mutex mu;
+  void* dev[2] = {nullptr, nullptr};
+  size_t dev_bytes[2] = {0, 0};
+  FullLayout layout[2] = {};
+};
+
+// Builds the full-length plan of p at length L; returns 0 or a negative
+// status with a message in err.
+int build_full(const Plan& p, int64_t L, int lattice, FullPlan& out, std::string& err);
+
+// Packs a full-length plan's device tables for dtype into a host byte vector.
+void pack_full_tables(const FullPlan& f, int dtype, std::vector<unsigned char>& blob, FullLayout& lay);
 
 // Builds the plan; returns 0 or a negative status with a message in err.
 int build_plan(const PlanParams& p, Plan& out, std::string& err);

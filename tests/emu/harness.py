@@ -20,8 +20,9 @@ BUILD = os.path.join(HERE, "_build")
 EXE = os.path.join(BUILD, "emu_runner")
 SOURCES = [os.path.join(HERE, "emu_runner.cpp"), os.path.join(CSRC, "plan.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "fft_device.hpp", "fused.hpp", "pipeline.hpp", "plan.hpp",
-                                            "common.hpp", "stream_server.hpp")]
+                                            "common.hpp", "stream_server.hpp", "fullnsgt.hpp")]
 STREAM_EXE = os.path.join(BUILD, "stream_runner")
+FULL_EXE = os.path.join(BUILD, "full_runner")
 
 
 def _build(exe: str, main_src: str) -> str:
@@ -30,10 +31,11 @@ def _build(exe: str, main_src: str) -> str:
     deps = srcs + HEADERS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")]
     if os.path.exists(exe) and os.path.getmtime(exe) > max(os.path.getmtime(d) for d in deps):
         return exe
+    tmp = f"{exe}.{os.getpid()}.tmp"       # parallel test workers may build at once
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-           "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", *srcs, "-o", exe + ".tmp"]
+           "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", *srcs, "-o", tmp]
     subprocess.check_call(cmd)
-    os.replace(exe + ".tmp", exe)
+    os.replace(tmp, exe)
     return exe
 
 
@@ -109,3 +111,21 @@ def synthesize_batched(plan: dict, coef: np.ndarray, lens, dtype: int = 1, adjoi
     c = np.asarray(coef, dtype=np.complex128)
     payload = np.concatenate([[len(lens)], lens, np.stack([c.real, c.imag], axis=1).reshape(-1)])
     return run("badj" if adjoint else "bsyn", dtype, plan, payload, **kw)
+
+
+def full(op: str, plan: dict, L: int, lattice: int, data, dtype: int = 1, window: int = 0):
+    """Full-length analysis (op "ana", data: L complex values) or synthesis
+    (op "syn", data: the coefficients) through full_runner.cpp."""
+    exe = _build(FULL_EXE, os.path.join(HERE, "full_runner.cpp"))
+    data = np.asarray(data, dtype=np.complex128)
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
+        data.view(np.float64).tofile(fin)
+        args = [exe, op, str(dtype), repr(float(plan["fs"])), repr(float(plan["fmin"])), repr(float(plan["fmax"])),
+                str(plan["bins_per_octave"]), str(plan["slice_len"]), str(plan["transition"]),
+                repr(float(plan.get("min_win", 16.0))), str(window), str(L), str(lattice), fin, fout]
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
+        r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"full_runner failed ({r.returncode}): {r.stderr[-3000:]}")
+        return np.fromfile(fout, dtype=np.float64).view(np.complex128)

@@ -38,3 +38,9 @@ template <class T>
 inline T unsafeAtomicAdd(T* p, T v) {
   return std::atomic_ref<T>(*p).fetch_add(v);
 }
+
+// sin(pi x) and cos(pi x) (HIP's sincospi), from the C library.
+inline void sincospi(double x, double* s, double* c) {
+  *s = std::sin(M_PI * x);
+  *c = std::cos(M_PI * x);
+}

@@ -94,3 +94,30 @@ def test_prepared_batch_validation_host_only(lib):
     assert lib.slicq_analyze_batch(None, 0, dummy, 1, dummy, 1, dummy, 1 << 20, None) == -1
     assert lib.slicq_synthesize_batch(None, 0, dummy, 1, dummy, 1, dummy, 1 << 20, None) == -1
     lib.slicq_batch_destroy(None)
+
+
+def test_full_length_plan_host_only(lib):
+    # plan checks and table sizes of the full-length transform need no device
+    import paper_1210_0084_amd as sq
+    p = sq.Plan(44100, 200, 22000, 48, 4096, 1024, window="blackman_harris")
+    f = sq.FullPlan(p, 1 << 20, "slicq")
+    assert f.nbands == 2 * p.K + 2 and f.L == 1 << 20
+    assert all(int(m) == int(p.M[k if k < p.nbands else 2 * p.K + 2 - k]) * 256 for k, m in enumerate(f.M))
+    assert not f.painless                                  # this lattice aliases a few bands
+    g = sq.FullPlan(p, 1 << 16, "painless")
+    assert g.painless and all(g.M >= g.lengths)
+    b = ctypes.c_size_t()
+    assert lib.nsgt_full_workspace_size(f._h, 0, ctypes.byref(b)) == 0 and b.value >= 8 * (f.L + 2 * f.coef_count)
+    assert lib.nsgt_full_table_bytes(f._h, 1, ctypes.byref(b)) == 0 and b.value > 0
+    rc = lib.nsgt_full_analyze(f._h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), 10 ** 8, ctypes.c_void_p(16),
+                               10 ** 10, None)
+    assert rc == -6 and b"upload" in lib.slicq_last_error()
+    for L, lat in ((3000, 0), (2048, 0), (1 << 25, 0), (1 << 16, 2)):
+        with pytest.raises(sq.SlicqError, match="-1"):
+            sq.FullPlan(p, L, "slicq") if lat != 2 else lib_call_bad_lattice(lib, p)
+
+
+def lib_call_bad_lattice(lib, p):
+    import paper_1210_0084_amd as sq
+    h = ctypes.c_void_p()
+    sq._check(lib.nsgt_full_plan(p._h, 1 << 16, 2, ctypes.byref(h)))

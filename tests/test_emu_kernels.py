@@ -144,3 +144,31 @@ def test_emu_streaming_round_robin_under_overload():
     for y, x in zip(ys, sig):
         assert np.abs(y - x).max() < 1e-12
     assert stats[4] > 0          # by round 8 every stream has released output
+
+
+FULLP = dict(fs=800.0, fmin=30.0, fmax=380.0, bins_per_octave=6, slice_len=64, transition=16, min_win=4.0)
+
+
+@pytest.mark.parametrize("L,lattice", [(256, "slicq"), (8192, "painless"), (16384, "slicq")])
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_emu_full_length(L, lattice, dtype):
+    # the full-length kernels (one-block FFTs up to 4096 points, four-step
+    # above, band gather, dual overlap-add) against the oracle: analysis, then
+    # synthesis of the oracle's coefficients and reconstruction
+    from oracle.fullnsgt import full_length_bands, nsgt_full, nsgt_full_synthesize
+    opl = OraclePlan(**FULLP)
+    bands = full_length_bands(opl, L, True, lattice)
+    rng = np.random.default_rng(L)
+    f = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    ref = np.concatenate(nsgt_full(bands, f))
+    lat = {"slicq": 0, "painless": 1}[lattice]
+    c = H.full("ana", FULLP, L, lat, f, dtype=dtype)
+    assert rel(c, ref) <= TOL[dtype]
+    assert all(b.length <= b.M for b in bands)      # this plan's lattices do not alias
+    parts, o = [], 0
+    for b in bands:
+        parts.append(ref[o:o + b.M])
+        o += b.M
+    y = H.full("syn", FULLP, L, lat, ref, dtype=dtype)
+    assert rel(y, nsgt_full_synthesize(bands, parts, L)) <= TOL[dtype]
+    assert rel(y, f) <= TOL[dtype]
