@@ -468,25 +468,27 @@ def bench_stream(args):
 
 
 def bench_approx(args):
-    """Section 5.3's approximation study: SNR of the sliCQ layer sum s^0 + s^1
-    (GPU, FP32: complex analysis onto all bands, then the layer kernel)
-    against the full-length CQ-NSGT on the same Blackman-Harris band windows
-    (FP64 oracle, rescaled by sqrt(2N / L)), for slice lengths 4096, 16384 and
-    65536, transitions 1/4 and 1/128 of the slice, minimal filter lengths 4,
-    8, 16 and 32 bins; random complex signals of 2^20 samples (the paper's
-    Set 1, seeded). Mean and spread over the signals."""
+    """Section 5.3's approximation study, all on the GPU: SNR of the sliCQ
+    layer sum s^0 + s^1 (FP32: complex analysis onto all bands, then the
+    layer kernel) against the full-length CQ-NSGT on the same
+    Blackman-Harris band windows (FP64, sliCQ lattice, rescaled by
+    sqrt(2N / L)), for slice lengths 4096, 16384 and 65536, transitions 1/4
+    and 1/128 of the slice, minimal filter lengths 4, 8, 16 and 32 bins;
+    seeded random complex signals of 2^20 samples (a stand-in for the paper's
+    Set 1). Mean and spread over the signals, and the full-length
+    transform's own speed (FP32, the 2N = 4096 plan)."""
     import torch
     import paper_1210_0084_amd as sq
-    from oracle import OraclePlan
-    from oracle.fullnsgt import full_length_bands, nsgt_full, snr_db
     dev = torch.device("cuda:0")
     L = 1 << args.approx_log2_len
     sigs = []
     for s in range(args.approx_signals):
         g = np.random.default_rng(100 + s)
-        sigs.append(g.standard_normal(L) + 1j * g.standard_normal(L))
+        sigs.append(torch.tensor(g.standard_normal(L) + 1j * g.standard_normal(L), dtype=torch.complex128,
+                                 device=dev))
     table = []
     full_cache = {}
+    timing = None
     t0 = time.perf_counter()
     for two_n in (4096, 16384, 65536):
         for frac in (4, 128):
@@ -494,26 +496,56 @@ def bench_approx(args):
                 kw = dict(fs=44100.0, fmin=200.0, fmax=22000.0, bins_per_octave=48, slice_len=two_n,
                           transition=two_n // frac, window="blackman_harris", min_win=float(mw))
                 plan = sq.Plan(**kw)
-                opl = OraclePlan(**kw)
+                S = plan.num_slices(L)
                 r = math.sqrt(two_n / L)
+                stored = (S // 2) * plan.coefs_per_slice
                 snrs = []
                 for si, f in enumerate(sigs):
                     key = (two_n, mw, si)
                     if key not in full_cache:         # the full-length transform does not depend on M
-                        full_cache[key] = nsgt_full(full_length_bands(opl, L, all_bands=False), f)
-                    cf = full_cache[key]
-                    c = plan.analyze_complex(torch.tensor(f, dtype=torch.complex64, device=dev))
-                    S = plan.num_slices(L)
-                    ls = plan.layers(c[:S * plan.coefs_per_slice], S).cpu().numpy().astype(np.complex128)
-                    approx = [ls[(S // 2) * off:(S // 2) * (off + b.M)] for off, b in zip(opl.offsets, opl.bands)]
-                    snrs.append(snr_db([r * x for x in cf], approx))
+                        fp = sq.FullPlan(plan, L, "slicq")
+                        full_cache[key] = fp.analyze(f)[:stored] * r
+                        if timing is None and two_n == 4096:
+                            timing = _full_timing(fp, f.to(torch.complex64), args)
+                    full = full_cache[key]
+                    c = plan.analyze_complex(f.to(torch.complex64))
+                    ls = plan.layers(c[:S * plan.coefs_per_slice], S).to(torch.complex128)
+                    snrs.append(20.0 * math.log10(float(torch.linalg.vector_norm(full)) /
+                                                  float(torch.linalg.vector_norm(full - ls))))
                 table.append({"slice_len": two_n, "transition": two_n // frac, "min_win": mw,
                               "snr_db_mean": round(float(np.mean(snrs)), 2),
                               "snr_db_spread": round(float(np.max(snrs) - np.min(snrs)), 3)})
                 print(json.dumps(table[-1]), file=sys.stderr, flush=True)
-    return {"workload": "approximation study (Section 5.3): sliCQ s^0+s^1 on the GPU vs full-length CQ-NSGT (FP64)",
+        full_cache.clear()
+    return {"workload": "approximation study (Section 5.3): sliCQ s^0+s^1 (FP32) vs full-length CQ-NSGT (FP64), "
+                        "both on the GPU",
             "signals": args.approx_signals, "length": L, "bins_per_octave": 48, "fmin": 200.0,
-            "window": "blackman_harris", "seconds": round(time.perf_counter() - t0, 1), "table": table}
+            "window": "blackman_harris", "seconds": round(time.perf_counter() - t0, 1), "table": table,
+            "full_length_fp32": timing}
+
+
+def _full_timing(fp, x, args):
+    """Speed of the full-length transform (FP32) on one signal: analysis
+    (algorithmic bytes: the signal read once, the coefficients written once)
+    and, on the painless lattice of the same plan, analysis + synthesis."""
+    import torch
+    import paper_1210_0084_amd as sq
+    out = {}
+    c = fp.analyze(x)
+    ms = _time(lambda: fp.analyze(x, out=c), 10, 3)
+    nbytes = 8 * (fp.L + fp.coef_count)
+    out["analysis_slicq_lattice"] = {"ms": round(ms, 4), "Msamples_per_s": round(fp.L / ms / 1e3, 1),
+                                     "GBs": round(nbytes / ms / 1e6, 1), "coef_count": int(fp.coef_count)}
+    pp = sq.FullPlan(fp.plan, fp.L, "painless")
+    cp = pp.analyze(x)
+    y = pp.synthesize(cp)
+    ms = _time(lambda: (pp.analyze(x, out=cp), pp.synthesize(cp, out=y)), 10, 3)
+    nbytes = 16 * (pp.L + pp.coef_count)
+    out["analysis_synthesis_painless"] = {"ms": round(ms, 4), "Msamples_per_s": round(pp.L / ms / 1e3, 1),
+                                          "GBs": round(nbytes / ms / 1e6, 1), "coef_count": int(pp.coef_count),
+                                          "reconstruction_rel_err": float(torch.linalg.vector_norm(y - x) /
+                                                                          torch.linalg.vector_norm(x))}
+    return out
 
 
 def _form_summary(rec):
@@ -544,7 +576,8 @@ def main():
     ap.add_argument("--approx-signals", type=int, default=3)
     ap.add_argument("--approx-log2-len", type=int, default=20)
     ap.add_argument("--c3-signals", type=int, default=256)
-    ap.add_argument("--c3-tune", action="store_true", help="autotune the ragged batch's work items first")
+    ap.add_argument("--no-c3-tune", dest="c3_tune", action="store_false",
+                    help="skip the autotuner for the ragged batch (default: tune, cached per batch shape)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--c4-batch", type=int, default=32)
     ap.add_argument("--fused", action="store_true",

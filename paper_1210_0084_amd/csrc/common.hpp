@@ -154,9 +154,28 @@ struct alignas(16) FullBandDev {
   int32_t len, M;
 };
 
-// Device tables of a full-length plan (byte offsets in one blob).
+// A run of count transforms of length 2^logn at off (complex values) that
+// owns blocks blk0 .. of its launch.
+struct alignas(16) FullRunDev {
+  int64_t off, blk0;
+  int32_t count, logn;
+  int64_t pad_;
+};
+
+// Run tables of one set of transforms (byte offsets in the blob): runs of at
+// most kLongVals points (one LDS block each per kLongVals values) and longer
+// runs (four-step, kLongVals values per block and pass).
+struct FullRunSet {
+  size_t small = 0, large = 0;
+  int32_t nsmall = 0, nlarge = 0;
+  int64_t blk_small = 0, blk_large = 0;
+};
+
+// Device tables of a full-length plan (byte offsets in one blob); sig is the
+// one transform of the signal, bandruns the band transforms.
 struct FullLayout {
   size_t bands = 0, g = 0, ent_off = 0, ent_idx = 0, ent_w = 0, tw = 0, total = 0;
+  FullRunSet sig, bandruns;
 };
 
 // Complex values one block of the long-transform kernels holds in LDS (16

@@ -24,80 +24,103 @@ __device__ __forceinline__ C2<T> long_twiddle(int64_t m, int64_t n) {
   return {(T)c, (T)(DIR > 0 ? s : -s)};
 }
 
-// nseq sequences of length 2^logn <= kLongVals, sequence s at s 2^logn;
-// each block transforms kLongVals >> logn of them in LDS and writes
-// scale * result. in may equal out (a block reads only what it writes).
+// Batched FFTs over a table of runs (FullRunDev): run r holds count
+// sequences of length 2^logn at off (complex values, contiguous) and owns the
+// blocks blk0 .. of its launch; a block finds its run by binary search. One
+// launch transforms every run of a length class, whatever its length.
+__device__ __forceinline__ int find_run(const FullRunDev* __restrict__ runs, int nruns, int64_t b) {
+  int lo = 0, hi = nruns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (runs[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Runs of length 2^logn <= kLongVals: a block transforms kLongVals >> logn
+// sequences in LDS and writes scale * result. in may equal out (a block reads
+// only what it writes).
 template <class T, int DIR>
-__global__ void __launch_bounds__(kLongThreads) k_long_fft(const C2<T>* in, C2<T>* out, int64_t nseq, int logn,
-                                                           T scale, const C2<T>* __restrict__ tw) {
+__global__ void __launch_bounds__(kLongThreads) k_long_fft(const FullRunDev* __restrict__ runs, int nruns,
+                                                           const C2<T>* in, C2<T>* out, T scale,
+                                                           const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int tid = threadIdx.x;
+  const FullRunDev R = runs[find_run(runs, nruns, blockIdx.x)];
+  const int logn = R.logn;
   const int per = kLongVals >> logn;
-  const int64_t s0 = (int64_t)blockIdx.x * per;
-  const int ns = (int)imin64(per, nseq - s0);
+  const int64_t s0 = (int64_t)(blockIdx.x - R.blk0) * per;
+  const int ns = (int)imin64(per, R.count - s0);
   const int cnt = ns << logn;
-  const int64_t g0 = s0 << logn;
+  const int64_t g0 = R.off + (s0 << logn);
   for (int i = tid; i < cnt; i += kLongThreads) buf[pidx(i)] = in[g0 + i];
   __syncthreads();
   lds_fft<T, DIR, CONTIG, 16, 16>(buf, 0, logn, ns, 0, TwGlobal<T>{tw}, tid, kLongThreads);
   for (int i = tid; i < cnt; i += kLongThreads) out[g0 + i] = cscale(buf[pidx(i)], scale);
 }
 
-// Four-step FFT of nseq sequences of length n = n1 n2 (n1 = 2^logn1 <= n2 =
-// 2^logn2 <= kLongVals): element t1 n2 + t2 is row t1, column t2.
-// Columns pass: each block transforms C = kLongVals / n1 adjacent columns
-// over t1, multiplies element (k1, t2) by e^{DIR 2 pi i t2 k1 / n} and writes
-// it to tmp[k1 n2 + t2].
+// Runs longer than kLongVals as a four-step FFT: n = n1 n2 (n1 = 2^logn1 <=
+// n2 = 2^logn2 <= kLongVals, logn1 = logn / 2), element t1 n2 + t2 is row t1,
+// column t2. Columns pass: each block transforms C = kLongVals / n1 adjacent
+// columns over t1, multiplies element (k1, t2) by e^{DIR 2 pi i t2 k1 / n} and
+// writes it to tmp[off + k1 n2 + t2] (tmp laid out like the data).
 template <class T, int DIR>
-__global__ void __launch_bounds__(kLongThreads) k_long_cols(const C2<T>* __restrict__ in, C2<T>* __restrict__ tmp,
-                                                            int logn1, int logn2, const C2<T>* __restrict__ tw) {
+__global__ void __launch_bounds__(kLongThreads) k_long_cols(const FullRunDev* __restrict__ runs, int nruns,
+                                                            const C2<T>* __restrict__ in, C2<T>* __restrict__ tmp,
+                                                            const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int tid = threadIdx.x;
+  const FullRunDev R = runs[find_run(runs, nruns, blockIdx.x)];
+  const int logn1 = R.logn / 2, logn2 = R.logn - logn1;
   const int logC = kLongLog - logn1;
-  const int C = 1 << logC, n1 = 1 << logn1;
-  const int64_t n = int64_t(1) << (logn1 + logn2);
+  const int C = 1 << logC;
+  const int64_t n = int64_t(1) << R.logn;
+  const int64_t lb = blockIdx.x - R.blk0;
   const int blocks_per_seq = 1 << (logn2 - logC);
-  const int64_t s = blockIdx.x / blocks_per_seq;
-  const int t20 = (int)(blockIdx.x % blocks_per_seq) << logC;
-  const C2<T>* src = in + s * n + t20;
+  const int64_t s = lb / blocks_per_seq;
+  const int t20 = (int)(lb % blocks_per_seq) << logC;
+  const C2<T>* src = in + R.off + s * n + t20;
   for (int i = tid; i < kLongVals; i += kLongThreads) {
     const int c = i & (C - 1), t1 = i >> logC;
     buf[pidx((c << logn1) + t1)] = src[((int64_t)t1 << logn2) + c];
   }
   __syncthreads();
   lds_fft<T, DIR, CONTIG, 16, 16>(buf, 0, logn1, C, 0, TwGlobal<T>{tw}, tid, kLongThreads);
-  C2<T>* dst = tmp + s * n + t20;
+  C2<T>* dst = tmp + R.off + s * n + t20;
   for (int i = tid; i < kLongVals; i += kLongThreads) {
     const int c = i & (C - 1), k1 = i >> logC;
     const C2<T> v = buf[pidx((c << logn1) + k1)];
     dst[((int64_t)k1 << logn2) + c] = cmul(v, long_twiddle<T, DIR>((int64_t)(t20 + c) * k1, n));
   }
-  (void)n1;
 }
 
 // Rows pass: each block transforms R = kLongVals / n2 adjacent rows k1 of
 // tmp over t2 and writes scale * X[k1 + n1 k2] to out (out may be the
 // columns pass's input).
 template <class T, int DIR>
-__global__ void __launch_bounds__(kLongThreads) k_long_rows(const C2<T>* __restrict__ tmp, C2<T>* __restrict__ out,
-                                                            int logn1, int logn2, T scale,
-                                                            const C2<T>* __restrict__ tw) {
+__global__ void __launch_bounds__(kLongThreads) k_long_rows(const FullRunDev* __restrict__ runs, int nruns,
+                                                            const C2<T>* __restrict__ tmp, C2<T>* __restrict__ out,
+                                                            T scale, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int tid = threadIdx.x;
+  const FullRunDev Rn = runs[find_run(runs, nruns, blockIdx.x)];
+  const int logn1 = Rn.logn / 2, logn2 = Rn.logn - logn1;
   const int logR = kLongLog - logn2;
   const int R = 1 << logR;
-  const int64_t n = int64_t(1) << (logn1 + logn2);
+  const int64_t n = int64_t(1) << Rn.logn;
+  const int64_t lb = blockIdx.x - Rn.blk0;
   const int blocks_per_seq = 1 << (logn1 - logR);
-  const int64_t s = blockIdx.x / blocks_per_seq;
-  const int k10 = (int)(blockIdx.x % blocks_per_seq) << logR;
-  const C2<T>* src = tmp + s * n + ((int64_t)k10 << logn2);
+  const int64_t s = lb / blocks_per_seq;
+  const int k10 = (int)(lb % blocks_per_seq) << logR;
+  const C2<T>* src = tmp + Rn.off + s * n + ((int64_t)k10 << logn2);
   for (int i = tid; i < kLongVals; i += kLongThreads) buf[pidx(i)] = src[i];
   __syncthreads();
   lds_fft<T, DIR, CONTIG, 16, 16>(buf, 0, logn2, R, 0, TwGlobal<T>{tw}, tid, kLongThreads);
-  C2<T>* dst = out + s * n + k10;
+  C2<T>* dst = out + Rn.off + s * n + k10;
   for (int i = tid; i < kLongVals; i += kLongThreads) {
     const int r = i & (R - 1), k2 = i >> logR;
     dst[((int64_t)k2 << logn1) + r] = cscale(buf[pidx((r << logn2) + k2)], scale);
@@ -179,23 +202,22 @@ inline FullWork full_work(const FullPlan& f, int dtype) {
 template <class T>
 constexpr size_t long_lds_bytes() { return (size_t)padded(kLongVals) * sizeof(C2<T>); }
 
-// nseq transforms of length 2^logn (contiguous), scaled: one LDS block per
-// kLongVals values up to kLongVals points, else columns then rows through tmp.
+// The transforms of one run table set (short runs, then long ones), scaled:
+// short runs in one LDS block per kLongVals values, long ones as columns
+// then rows through tmp.
 template <class T, int DIR, class Ln>
-void long_fft(Ln& ln, const C2<T>* in, C2<T>* out, C2<T>* tmp, int64_t nseq, int logn, T scale,
+void long_fft(Ln& ln, const char* tabs, const FullRunSet& rs, const C2<T>* in, C2<T>* out, C2<T>* tmp, T scale,
               const C2<T>* tw) {
-  if (nseq <= 0) return;
-  if (logn <= kLongLog) {
-    const int64_t per = kLongVals >> logn;
-    ln.launch(k_long_fft<T, DIR>, (nseq + per - 1) / per, kLongThreads, long_lds_bytes<T>(), in, out, nseq, logn,
-              scale, tw);
-    return;
+  const auto* small = reinterpret_cast<const FullRunDev*>(tabs + rs.small);
+  const auto* large = reinterpret_cast<const FullRunDev*>(tabs + rs.large);
+  if (rs.nsmall)
+    ln.launch(k_long_fft<T, DIR>, rs.blk_small, kLongThreads, long_lds_bytes<T>(), small, rs.nsmall, in, out, scale,
+              tw);
+  if (rs.nlarge) {
+    ln.launch(k_long_cols<T, DIR>, rs.blk_large, kLongThreads, long_lds_bytes<T>(), large, rs.nlarge, in, tmp, tw);
+    ln.launch(k_long_rows<T, DIR>, rs.blk_large, kLongThreads, long_lds_bytes<T>(), large, rs.nlarge,
+              static_cast<const C2<T>*>(tmp), out, scale, tw);
   }
-  const int logn1 = logn / 2, logn2 = logn - logn1;
-  const int64_t blocks = nseq << (logn - kLongLog);
-  ln.launch(k_long_cols<T, DIR>, blocks, kLongThreads, long_lds_bytes<T>(), in, tmp, logn1, logn2, tw);
-  ln.launch(k_long_rows<T, DIR>, blocks, kLongThreads, long_lds_bytes<T>(), static_cast<const C2<T>*>(tmp), out,
-            logn1, logn2, scale, tw);
 }
 
 // Analysis: unitary DFT of x into X, X g_k wrapped modulo M_k into coef, the
@@ -206,11 +228,11 @@ void full_analyze_launch(Ln& ln, const FullPlan& f, const char* tabs, const Full
   const auto* tw = reinterpret_cast<const C2<T>*>(tabs + lay.tw);
   auto* X = reinterpret_cast<C2<T>*>(wk + w.x_off);
   auto* tmp = reinterpret_cast<C2<T>*>(wk + w.t_off);
-  long_fft<T, -1>(ln, x, X, tmp, 1, f.logL, (T)(1.0 / std::sqrt((double)f.L)), tw);
+  long_fft<T, -1>(ln, tabs, lay.sig, x, X, tmp, (T)(1.0 / std::sqrt((double)f.L)), tw);
   ln.launch(k_full_gather<T>, (f.coef_count + 255) / 256, 256, 0, reinterpret_cast<const FullBandDev*>(tabs + lay.bands),
             (int)f.bands.size(), static_cast<const C2<T>*>(X), f.L, reinterpret_cast<const T*>(tabs + lay.g),
             f.coef_count, coef);
-  for (const FullRun& r : f.runs) long_fft<T, 1>(ln, coef + r.off, coef + r.off, tmp, r.count, r.logn, T(1), tw);
+  long_fft<T, 1>(ln, tabs, lay.bandruns, static_cast<const C2<T>*>(coef), coef, tmp, T(1), tw);
 }
 
 // Synthesis: DFTs of length M_k (unnormalised) into C, the dual-weighted
@@ -222,11 +244,11 @@ void full_synthesize_launch(Ln& ln, const FullPlan& f, const char* tabs, const F
   auto* C = reinterpret_cast<C2<T>*>(wk + w.c_off);
   auto* Z = reinterpret_cast<C2<T>*>(wk + w.x_off);
   auto* tmp = reinterpret_cast<C2<T>*>(wk + w.t_off);
-  for (const FullRun& r : f.runs) long_fft<T, -1>(ln, coef + r.off, C + r.off, tmp, r.count, r.logn, T(1), tw);
+  long_fft<T, -1>(ln, tabs, lay.bandruns, coef, C, tmp, T(1), tw);
   ln.launch(k_full_ola<T>, (f.L + 255) / 256, 256, 0, reinterpret_cast<const int32_t*>(tabs + lay.ent_off),
             reinterpret_cast<const int32_t*>(tabs + lay.ent_idx), reinterpret_cast<const T*>(tabs + lay.ent_w),
             static_cast<const C2<T>*>(C), f.L, Z);
-  long_fft<T, 1>(ln, static_cast<const C2<T>*>(Z), y, tmp, 1, f.logL, (T)(1.0 / std::sqrt((double)f.L)), tw);
+  long_fft<T, 1>(ln, tabs, lay.sig, static_cast<const C2<T>*>(Z), y, tmp, (T)(1.0 / std::sqrt((double)f.L)), tw);
 }
 
 }  // namespace slicq

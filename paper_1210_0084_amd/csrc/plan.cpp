@@ -908,6 +908,37 @@ void pack_full_tables(const FullPlan& f, int dtype, std::vector<unsigned char>& 
       tw[2 * (n + k) + 1] = s;
     }
   lay.bands = append(blob, f.bands.data(), f.bands.size());
+  // run tables: the signal (one transform of length L), then the band runs,
+  // each split into short and long runs with their blocks numbered
+  auto runset = [&](const std::vector<FullRun>& runs) {
+    std::vector<FullRunDev> sm, lg;
+    FullRunSet rs;
+    for (const FullRun& r : runs) {
+      FullRunDev d{};
+      d.off = r.off;
+      d.count = r.count;
+      d.logn = r.logn;
+      if (r.logn <= kLongLog) {
+        const int64_t per = kLongVals >> r.logn;
+        d.blk0 = rs.blk_small;
+        rs.blk_small += (r.count + per - 1) / per;
+        sm.push_back(d);
+      } else {
+        d.blk0 = rs.blk_large;
+        rs.blk_large += (int64_t)r.count << (r.logn - kLongLog);
+        lg.push_back(d);
+      }
+    }
+    rs.nsmall = (int32_t)sm.size();
+    rs.nlarge = (int32_t)lg.size();
+    if (sm.empty()) sm.resize(1);
+    if (lg.empty()) lg.resize(1);
+    rs.small = append(blob, sm.data(), sm.size());
+    rs.large = append(blob, lg.data(), lg.size());
+    return rs;
+  };
+  lay.sig = runset({FullRun{0, 1, f.logL}});
+  lay.bandruns = runset(f.runs);
   lay.ent_off = append(blob, f.ent_off.data(), f.ent_off.size());
   lay.ent_idx = append(blob, f.ent_idx.data(), f.ent_idx.size());
   if (dtype == 0) {
