@@ -3,7 +3,9 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 * Atoms (Section 2.2): phi_{n,k} = T_{n a_k} g^vee_k with g^vee_k = F^{-1} g_k,
-  a_k = 2N / M_k. The inverse DFT is written as an explicit sum.
+  a_k = 2N / M_k. The inverse DFT is written as an explicit sum; the
+  translation is the modulation e^{-2 pi i j n / M_k} of the band's signed
+  bins (a circular shift when M_k divides 2N).
 * Coefficients (equation CQ_coeff): c_{n,k} = <x, phi_{n,k}> = sum_l x[l] conj(phi[l]).
 * Frame operator (equation frameop): S = sum_{n,k} phi phi^H.
 * Canonical dual atoms (equation candual): S^{-1} phi.
@@ -34,16 +36,20 @@ def atoms(plan, bands=None, window: str = "g") -> list:
     """List over bands of arrays (M_k, 2N): row n is T_{n a_k} F^{-1} w_k.
 
     ``window`` is "g" for the analysis windows or "gd" for the dual windows.
+    The translation by n a_k = n 2N / M_k is the modulation of the band's
+    bins j (signed, j in J_k) by e^{-2 pi i j n / M_k}: for M_k dividing 2N a
+    circular shift by an integer, otherwise the band-limited translation by
+    a fraction of a sample (equation CQ_coeff with L / a_k = M_k).
     """
     two_n = plan.two_n
-    E = idft_matrix(two_n)
+    t = np.arange(two_n)
     out = []
     for b in (plan.all_bands if bands is None else bands):
-        w = np.zeros(two_n)
-        w[b.bins() % two_n] = b.g if window == "g" else b.gd
-        gv = E @ w
-        a = two_n // b.M
-        out.append(np.stack([np.roll(gv, n * a) for n in range(b.M)]))
+        w = b.g if window == "g" else b.gd
+        j = b.bins()
+        E = np.exp(2j * math.pi * np.outer(t, j) / two_n) / math.sqrt(two_n)     # (2N, |J_k|)
+        mod = np.exp(-2j * math.pi * np.outer(np.arange(b.M), j) / b.M)         # (M_k, |J_k|)
+        out.append((mod * w) @ E.T)
     return out
 
 

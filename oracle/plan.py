@@ -87,6 +87,19 @@ def _next_pow2(n: int) -> int:
     return 1 << (max(n, 1) - 1).bit_length()
 
 
+def smooth_even_at_least(n: int) -> int:
+    """Smallest even integer >= max(n, 2) whose only prime factors are 2, 3
+    and 5 with at most one factor 3 or 5 (2^a, 3 2^a, 5 2^a; a >= 1)."""
+    n = max(int(n), 2)
+    best = None
+    for r in (1, 3, 5):
+        m = 2 * r
+        while m < n:
+            m *= 2
+        best = m if best is None else min(best, m)
+    return best
+
+
 @dataclasses.dataclass
 class BandTable:
     """One band k: values of g_k over its circular support J_k.
@@ -163,8 +176,8 @@ class OraclePlan:
             raise ValueError("scale is 'cq', 'mel' or 'bark'")
         if slicing not in ("tukey", "sqrt_tukey"):
             raise ValueError("slicing is 'tukey' or 'sqrt_tukey'")
-        if m_policy not in ("pow2", "rect"):
-            raise ValueError("m_policy is 'pow2' or 'rect'")
+        if m_policy not in ("pow2", "rect", "smooth"):
+            raise ValueError("m_policy is 'pow2', 'rect' or 'smooth'")
         self.window, self.scale, self.slicing, self.m_policy = window, scale, slicing, m_policy
         self.fs, self.fmin, self.fmax, self.B = fs, fmin, fmax, B
         self.two_n, self.N, self.M = two_n, N, Mt
@@ -216,6 +229,12 @@ class OraclePlan:
             Mr = max(b.M for b in bands)
             for b in bands:
                 b.M = Mr
+        elif m_policy == "smooth":
+            # equation framecond1 asks only M_k >= |J_k| (integer); Algorithm 3
+            # places slice m at (m - 1) M_k / 2, so M_k is even: the smallest
+            # even number 2^a, 3 2^a or 5 2^a that holds the support
+            for b in bands:
+                b.M = smooth_even_at_least(b.length)
         # validity of the real-signal band layout
         for b in bands:
             if b.length == 0:

@@ -36,9 +36,10 @@ def test_blackman_harris_shape():
 
 
 @pytest.mark.parametrize("opts", [dict(window="blackman_harris"), dict(scale="mel"), dict(scale="bark"),
-                                  dict(slicing="sqrt_tukey"), dict(m_policy="rect"),
-                                  dict(window="blackman_harris", slicing="sqrt_tukey", scale="mel")],
-                         ids=["bh", "mel", "bark", "sqrt", "rect", "combined"])
+                                  dict(slicing="sqrt_tukey"), dict(m_policy="rect"), dict(m_policy="smooth"),
+                                  dict(window="blackman_harris", slicing="sqrt_tukey", scale="mel"),
+                                  dict(window="blackman_harris", m_policy="smooth", scale="bark")],
+                         ids=["bh", "mel", "bark", "sqrt", "rect", "smooth", "combined", "combined-smooth"])
 def test_variants_reconstruct_and_match_atoms(opts):
     # every variant is still a painless frame with a dual slicing window:
     # perfect reconstruction (Propositions 1-3), and the fast analysis equals
@@ -55,6 +56,43 @@ def test_variants_reconstruct_and_match_atoms(opts):
     for k in (0, 1, pl.K // 2, pl.K + 1):
         ref = brute.coefficients(pl, xm, [pl.bands[k]])[0]
         assert np.abs(ref - c[k][m]).max() < 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_smooth_policy_lattice():
+    # equation framecond1 with the even smooth numbers: M_k >= |J_k|, even,
+    # 2^a, 3 2^a or 5 2^a, and no smaller such number holds the support
+    # (brute enumeration); it never exceeds the power-of-two policy
+    def ok(m):
+        if m % 2:
+            return False
+        while m % 2 == 0:
+            m //= 2
+        return m in (1, 3, 5)
+    for kw in (SMALL, dict(fs=44100.0, fmin=32.7, fmax=22050.0, bins_per_octave=48, slice_len=65536,
+                           transition=8192)):
+        ps = OraclePlan(**kw, min_win=4, m_policy="smooth")
+        pp = OraclePlan(**kw, min_win=4)
+        for bs, bp in zip(ps.bands, pp.bands):
+            assert ok(bs.M) and bs.M >= max(bs.length, 2) and bs.M <= bp.M
+            assert not any(ok(m) for m in range(max(bs.length, 2), bs.M)), (bs.k, bs.length, bs.M)
+    assert sum(b.M for b in ps.bands) < 0.85 * sum(b.M for b in pp.bands)     # c2: 76,476 vs 94,416
+
+
+def test_smooth_policy_is_painless_with_fractional_hops():
+    # M_k need not divide 2N: the atoms are translated by a fraction of a
+    # sample (a_k = 2N / M_k), the frame operator stays diagonal in frequency
+    # with D = sum M_k g_k^2 (Proposition 2), and synthesis of coefficients
+    # equals the expansion in the dense canonical dual atoms
+    pl = OraclePlan(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=64, transition=16, min_win=4.0,
+                    m_policy="smooth")
+    assert any(pl.two_n % b.M for b in pl.bands)
+    S_op = brute.frame_operator(pl)
+    F = np.fft.fft(np.eye(pl.two_n)) / math.sqrt(pl.two_n)
+    Sf = F @ S_op @ F.conj().T
+    np.testing.assert_allclose(Sf, np.diag(pl.D), atol=1e-12)
+    duals = brute.dual_atoms(pl)
+    A = np.concatenate(brute.atoms(pl, window="gd"), axis=0)
+    np.testing.assert_allclose(A, np.concatenate(duals, axis=0), atol=1e-12)
 
 
 def test_sqrt_tukey_partition_of_squares():
