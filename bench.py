@@ -548,6 +548,34 @@ def _full_timing(fp, x, args):
     return out
 
 
+def _bench_smooth(prm, x, y, T, args, copy_gbs):
+    """The same c2 step with the smooth-number policy (M_k the smallest even
+    2^a, 3 2^a or 5 2^a >= |J_k|): fewer coefficients, mixed-radix band
+    kernels. Its own algorithmic bytes (smaller: fewer coefficients)."""
+    import torch
+    import paper_1210_0084_amd as sq
+    plan = sq.Plan(**prm, m_policy="smooth")
+    lay = plan.batch_layout([T, T])
+    coef = torch.empty(lay.coef_len, dtype=torch.complex64, device=x.device)
+
+    def step():
+        plan.analyze_batched(x, out=coef, layout=lay)
+        plan.synthesize_batched(coef, out=y, layout=lay)
+    ms = _time(step, args.steps, args.warmup)
+    err = float((y - x).abs().max().item())
+    S = lay.total_slices
+    stage_ms = time_stages(plan, S, x, coef, y, args.stage_reps, lay)
+    share = algorithmic_share(plan, S, 2 * T, 4)
+    path_bytes = 2 * 4 * 2 * T + 2 * 8 * S * plan.coefs_per_slice
+    return {"value": round(2 * T / (ms * 1e-3) / 1e6, 1), "unit": "Msamples/s", "ms_per_step": round(ms, 4),
+            "coefs_per_slice": plan.coefs_per_slice, "algorithmic_bytes_per_step": path_bytes,
+            "path": _frac(path_bytes, ms, copy_gbs), "reconstruction_max_abs_err": err,
+            "band_ana": {"ms": round(stage_ms["band_ana"], 4),
+                         "algorithmic_GBs": round(share["band_ana"] / (stage_ms["band_ana"] * 1e-3) / 1e9, 1)},
+            "band_syn": {"ms": round(stage_ms["band_syn"], 4),
+                         "algorithmic_GBs": round(share["band_syn"] / (stage_ms["band_syn"] * 1e-3) / 1e9, 1)}}
+
+
 def _form_summary(rec):
     """The key figures of a form's record, for the default line."""
     keep = {k: rec[k] for k in ("value", "unit", "ms_per_step") if k in rec}
@@ -685,6 +713,8 @@ def main():
                  "reconstruction_max_abs_err": err},
         "stages": stages,
     }
+    if not args.no_forms:
+        rec["smooth_M"] = _bench_smooth(prm, x, y, T, args, copy_gbs)
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)

@@ -87,7 +87,12 @@ typedef struct {
                                (the other design of Section 4.3) */
   int32_t m_policy;         /* coefficients per band: 0 the smallest power of two >= |J_k| (default),
                                1 one M for every band, the largest of those (the rectangular
-                               representation of Section 6) */
+                               representation of Section 6), 2 the smallest even 2^a, 3 2^a or
+                               5 2^a >= |J_k| (equation framecond1 asks only M_k >= |J_k|; Algorithm
+                               3's layers need M_k even): fewer coefficients (c2: 76,476 instead of
+                               94,416 per slice), hops 2N / M_k of a fraction of a sample where M_k
+                               does not divide 2N, band transforms with radix-3 and radix-5 steps,
+                               and never one workgroup per slice */
   int32_t fused;            /* 0 (default): the multi-kernel pipeline; 1: where a slice's half
                                spectrum and its largest band transform fit one workgroup's LDS,
                                each slice's analysis (and synthesis) runs in one workgroup with no

@@ -266,7 +266,7 @@ class Plan:
                   float(min_win), {"canonical": 0, "indicator": 1}[dual_slice], int(group_cap), int(lds_cap),
                   int(pass_cap), {"band": 0, "slice": 1}[layout],
                   {"hann": 0, "blackman_harris": 1}[window], {"cq": 0, "mel": 1, "bark": 2}[scale],
-                  {"tukey": 0, "sqrt_tukey": 1}[slicing], {"pow2": 0, "rect": 1}[m_policy], 1 if fused else 0)
+                  {"tukey": 0, "sqrt_tukey": 1}[slicing], {"pow2": 0, "rect": 1, "smooth": 2}[m_policy], 1 if fused else 0)
         h = ctypes.c_void_p()
         _check(lib.nsgt_plan_ex(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(256) k_layer_sum(const BandDev* __restrict__ b
   const int half = b.M >> 1, nl = ca.S * half;
   int pe = p + half;
   if (pe >= nl) pe -= nl;
-  const C2<T> s1 = coef[ca.at(b, 2 * (p / b.M) + 1, p & (b.M - 1))];
-  const C2<T> s0 = coef[ca.at(b, 2 * (pe / b.M), pe & (b.M - 1))];
+  const C2<T> s1 = coef[ca.at(b, 2 * (p / b.M) + 1, p % b.M)];
+  const C2<T> s0 = coef[ca.at(b, 2 * (pe / b.M), pe % b.M)];
   const C2<T> s = cadd(s0, s1);
   if constexpr (MODE == 0) static_cast<C2<T>*>(out)[i] = s;
   else static_cast<T*>(out)[i] = s.x * s.x + s.y * s.y;
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) k_mask_db(const BandDev* __restrict__ ban
   const int k = band_of(bands, nb, i, ca.S);
   const BandDev b = bands[k];
   const int q = (int)(i - (int64_t)ca.S * b.off);
-  const int m = q / b.M, n = q & (b.M - 1);
+  const int m = q / b.M, n = q - m * b.M;
   const int half = b.M >> 1, nl = ca.S * half;
   int p = (m - 1) * half + n;
   if (p < 0) p += nl;
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(256) k_transpose(const BandDev* __restrict__ b
   const int t = band_of(bands, nb, i, ca.S);
   const BandDev b = bands[t];
   const int q = (int)(i - (int64_t)ca.S * b.off);
-  const int m = q / b.M, n = q & (b.M - 1);
+  const int m = q / b.M, n = q - m * b.M;
   const int s = t - d, K = nb - 2;
   C2<T> v{T(0), T(0)};
   if (t >= 1 && t <= K && s >= 1 && s <= K) v = in[ca.at(bands[s], m, n)];

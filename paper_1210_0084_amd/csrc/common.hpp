@@ -103,6 +103,7 @@ struct TableLayout {
   uint64_t tw, tw8, h0, hd, g, gd, gdw, bands, ana, syn, runs;
   uint64_t ola_syn, ola_adj, ent_off, ent_pos, ent_wsyn, ent_wadj;
   uint64_t fana, fsyn, fola_syn, fola_adj, fent_off, fent_pos, fent_wsyn, fent_wadj;
+  uint64_t twmix, bsmod;     // mixed-radix plans: combination twiddles, (-start_k) mod M_k per band
   uint64_t total;
 };
 
@@ -177,6 +178,13 @@ struct FullLayout {
   size_t bands = 0, g = 0, ent_off = 0, ent_idx = 0, ent_w = 0, tw = 0, total = 0;
   FullRunSet sig, bandruns;
 };
+
+// Mixed-radix twiddle table: for R = 3 then R = 5, for logP = 1 .. L,
+// e^{-2 pi i k / M} for k < M = R 2^logP (entries from R (2^logP - 2) of the
+// R block; the R = 5 block starts after the 3 (2^(L+1) - 2) entries of R = 3).
+constexpr int64_t mix_tw_base(int R, int logP, int L) {
+  return (R == 3 ? 0 : 3 * ((int64_t(2) << L) - 2)) + R * ((int64_t(1) << logP) - 2);
+}
 
 // Complex values one block of the long-transform kernels holds in LDS (16
 // per thread of 256): transforms up to this length run in one block, longer

@@ -96,6 +96,10 @@ struct KArgs {
   const T* fent_w;
   int32_t fused, nfana, nfsyn, flogM;
   int32_t fcap, pad3_;
+  // mixed-radix band transforms (plans with M_k = 3 2^a or 5 2^a)
+  const C2<T>* twmix;     // combination twiddles (mix_tw_base)
+  const int32_t* bsmod;   // (-start_k) mod M_k per stored band
+  int32_t mixL, pad4_;    // largest logP of the twiddle table
 };
 
 // Byte offset, 16-byte aligned, just past `values` padded complex values in LDS.

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "bandmix.hpp"
 #include "fused.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -116,6 +117,9 @@ KArgs<T> make_args(const Plan& p, int dtype, bool adjoint, bool dual = false) {
   a.nfana = (int32_t)f.ana.size();
   a.nfsyn = (int32_t)f.syn.size();
   a.flogM = f.logM;
+  a.twmix = reinterpret_cast<const C2<T>*>(base + L.twmix);
+  a.bsmod = reinterpret_cast<const int32_t*>(base + L.bsmod);
+  a.mixL = p.mix_L;
   a.fcap = f.cap;
   return a;
 }
@@ -136,6 +140,12 @@ struct Geometry {
   // (bound kSynBigThreads)
   int gs, bs; size_t ss;
   int gsb, bsb; size_t ssb; bool tsb;
+  // plans with some M_k = 3 2^a or 5 2^a: every band item runs the
+  // mixed-radix kernels (bandmix.hpp), analysis items with bxa threads and
+  // exa values per thread, synthesis items with bxs threads and exs values
+  bool mixed;
+  int gxa, bxa, exa; size_t sxa;
+  int gxs, bxs, exs; size_t sxs;
   bool ok;                    // every block fits its kernel's launch bound
 };
 
@@ -181,6 +191,23 @@ Geometry<T> geometry(const Plan& p) {
   for (int i = p.syn_small; i < (int)p.syn.size(); ++i) big_maxM = std::max(big_maxM, p.syn[i].maxM);
   g.tsb = lds_twiddles_pay(g.ssb, (size_t)big_maxM * cb);
   g.ssb += g.tsb ? (size_t)big_maxM * cb : split_bytes(big_maxM, true);
+  g.mixed = p.mixed;
+  if (p.mixed) {
+    int32_t syn_max = 0;
+    for (const SynGroupDev& G : p.syn) syn_max = std::max(syn_max, G.total);
+    g.gxa = (int)p.ana.size();
+    g.exa = p.ana_cap <= 8 * kMixThreads ? 8 : 16;
+    g.bxa = threads_for(std::max(p.ana_cap, 1), g.exa);
+    g.sxa = lds_tail_offset<T>(p.ana_cap);
+    g.gxs = (int)p.syn.size();
+    g.exs = syn_max <= 8 * kMixThreads ? 8 : 16;
+    g.bxs = threads_for(std::max(syn_max, 1), g.exs);
+    g.sxs = lds_tail_offset<T>(syn_max);
+    g.ok = g.b1 <= kPassThreads && g.b2 <= kPassThreads && (int64_t)p.C * p.N2 <= (int64_t)kPassE * g.b1 &&
+           2LL * p.P * p.N1 <= (int64_t)kPassE * g.b2 && p.ana_cap <= g.exa * g.bxa && syn_max <= g.exs * g.bxs &&
+           g.gxs <= 65535 && std::max(std::max(g.s1, g.s2), std::max(g.sxa, g.sxs)) <= kMaxLdsBytes;
+    return g;
+  }
   size_t lds = std::max(std::max(g.s1, g.s2), std::max(g.sa, g.ss));
   if (g.gab) lds = std::max(lds, g.sab);
   if (g.gsb) lds = std::max(lds, g.ssb);
@@ -198,6 +225,11 @@ Geometry<T> geometry(const Plan& p) {
 template <class T, class Launch>
 void launch_band_ana(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* tasks, int64_t cnt,
                      const C2<T>* W2, C2<T>* coef, Launch& L) {
+  if (g.mixed) {
+    if (g.exa == 8) L.launch(k_band_ana_mx<T, 8>, cnt * g.gxa, g.bxa, g.sxa, a, tasks, W2, coef, 0, g.gxa);
+    else L.launch(k_band_ana_mx<T, 16>, cnt * g.gxa, g.bxa, g.sxa, a, tasks, W2, coef, 0, g.gxa);
+    return;
+  }
   if (g.ga)
     L.launch(k_band_ana<T, kSmallE, kAnaThreads, kSmallWaves, false>, cnt * g.ga, g.ba, g.sa, a, tasks, W2, coef, 0,
              g.ga);
@@ -222,6 +254,11 @@ void launch_band_syn(const KArgs<T>& a, const Geometry<T>& g, const SliceTask* t
   const int64_t tiles = std::min<int64_t>((cnt + kSynTile - 1) / kSynTile, 65535);
   const int64_t tx = tiles ? (cnt + tiles - 1) / tiles : 0;
   const int n = (int)cnt;
+  if (g.mixed) {
+    if (g.exs == 8) L.launch_xyz(k_band_syn_mx<T, 8>, tx, g.gxs, (int)tiles, g.bxs, g.sxs, a, tasks, coef, W2, y, 0, n);
+    else L.launch_xyz(k_band_syn_mx<T, 16>, tx, g.gxs, (int)tiles, g.bxs, g.sxs, a, tasks, coef, W2, y, 0, n);
+    return;
+  }
   if (g.gs)
     L.launch_xyz(k_band_syn<T, kSmallE, kSynThreads, kSynSmallWaves<T>, false>, tx, g.gs, (int)tiles, g.bs, g.ss, a,
                  tasks, coef, W2, y, 0, n);

@@ -34,6 +34,27 @@ int ilog2(int64_t n) {
   return l;
 }
 
+// log2 of the largest power of two dividing n > 0.
+int pow2_part_log(int64_t n) {
+  int l = 0;
+  while (!(n & 1)) {
+    n >>= 1;
+    ++l;
+  }
+  return l;
+}
+
+// The smallest even number 2^a, 3 2^a or 5 2^a (a >= 1) that is >= n.
+int64_t smooth_even(int64_t n) {
+  int64_t best = 0;
+  for (int64_t r : {1, 3, 5}) {
+    int64_t m = 2 * r;
+    while (m < n) m *= 2;
+    if (!best || m < best) best = m;
+  }
+  return best;
+}
+
 struct RawBand {
   int64_t start = 0;
   std::vector<double> g;
@@ -143,6 +164,7 @@ void build_fused(const Plan& p, int dtype, FusedPlan& f) {
   const int logN = ilog2(N);
   if (!p.prm.fused || N < 32 || N > 16384) return;
   if (!(logN == 5 || logN == 6 || (logN >= 12 && logN <= 14))) return;   // compiled slice lengths
+  if (p.mixed) return;                         // the per-slice kernels transform powers of two only
   const size_t cb = dtype ? 16 : 8;
   const int nb = (int)p.bands.size();
   f.logM = ilog2(p.max_M);
@@ -277,9 +299,9 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     return -1;
   }
   if (p.window < 0 || p.window > 1 || p.scale < 0 || p.scale > 2 || p.slicing < 0 || p.slicing > 1 ||
-      p.m_policy < 0 || p.m_policy > 1) {
+      p.m_policy < 0 || p.m_policy > 2) {
     err = "window (0 Hann, 1 Blackman-Harris), scale (0 cq, 1 mel, 2 Bark), slicing (0 Tukey, 1 root "
-          "Tukey) or m_policy (0 power of two, 1 rectangular) out of range";
+          "Tukey) or m_policy (0 power of two, 1 rectangular, 2 even smooth number) out of range";
     return -1;
   }
   if (p.group_cap < 16 || p.group_cap > 4096 || p.lds_cap < 64 || p.lds_cap > kSynMaxValues ||
@@ -339,6 +361,8 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     int64_t Mr = 0;
     for (const RawBand& r : raw) Mr = std::max(Mr, r.M);
     for (RawBand& r : raw) r.M = Mr;
+  } else if (p.m_policy == 2) {   // M_k >= |J_k| (equation framecond1), even for Algorithm 3's layers
+    for (RawBand& r : raw) r.M = smooth_even(std::max<int64_t>(2, (int64_t)r.g.size()));
   }
   for (int k = 0; k < K + 2; ++k) {
     if (raw[k].g.empty()) {
@@ -398,7 +422,7 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     b.start = r.start;
     b.len = (int32_t)r.g.size();
     b.M = (int32_t)r.M;
-    b.logM = ilog2(r.M);
+    b.logM = pow2_part_log(r.M);          // M_k = R 2^logM, R in {1, 3, 5}
     b.off = off;
     b.goff = goff;
     b.xi = r.xi;
@@ -417,6 +441,13 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     out.bands.push_back(b);
   }
   out.coefs_per_slice = off;
+  out.mixed = false;
+  out.mix_L = 1;
+  for (const BandInfo& b : out.bands)
+    if (b.M & (b.M - 1)) {
+      out.mixed = true;
+      out.mix_L = std::max(out.mix_L, b.logM);
+    }
   if (out.max_M > 8192) {
     std::snprintf(msg, sizeof msg, "a band needs M_k = %d coefficients per slice; "
                   "the single-workgroup band transforms support up to 8192", out.max_M);
@@ -569,7 +600,7 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
 
   // small work items first, then the large ones (each class is one launch)
   {
-    auto ana_big = [](const AnaGroupDev& G) { return (G.cnt << G.logM) > kAnaSmallValues; };
+    auto ana_big = [](const AnaGroupDev& G) { return G.cnt * G.M > kAnaSmallValues; };
     auto syn_big = [](const SynGroupDev& G) { return G.total > kSynSmallValues; };
     std::stable_partition(out.ana.begin(), out.ana.end(), [&](const AnaGroupDev& G) { return !ana_big(G); });
     std::stable_partition(out.syn.begin(), out.syn.end(), [&](const SynGroupDev& G) { return !syn_big(G); });
@@ -577,7 +608,7 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
     out.ana_cap_small = out.ana_cap_big = out.syn_cap_small = out.syn_cap_big = 0;
     out.ana_maxM_small = out.syn_maxM_small = 0;
     for (const AnaGroupDev& G : out.ana) {
-      const int32_t v = G.cnt << G.logM;
+      const int32_t v = G.cnt * G.M;
       if (ana_big(G)) {
         out.ana_cap_big = std::max(out.ana_cap_big, v);
       } else {
@@ -621,8 +652,12 @@ int build_plan(const PlanParams& p, Plan& out, std::string& err) {
         const int64_t lds = b.off - base;
         const int64_t t = j - b.start;
         const bool selfmirror = (k == 0 || k == K + 1);
-        const int32_t px = (int32_t)(lds + (j & (b.M - 1)));
-        const int32_t py = selfmirror ? (int32_t)(lds + ((-j) & (b.M - 1))) : -1;
+        // slot of bin j and, for the self-mirrored bands, of its mirror: the
+        // signed bins of J_k, -j around DC and 2N - j around Nyquist (the same
+        // slot modulo M_k when M_k divides 2N)
+        const int64_t jm = k == 0 ? -j : 2 * N - j;
+        const int32_t px = (int32_t)(lds + ((j % b.M) + b.M) % b.M);
+        const int32_t py = selfmirror ? (int32_t)(lds + ((jm % b.M) + b.M) % b.M) : -1;
         const double ws = (selfmirror ? 0.5 : 1.0) * out.gd[b.goff + t], wa = 0.5 * out.g[b.goff + t];
         if (slot < 2) {
           out.ent2_pos[4 * j + 2 * slot] = px;
@@ -775,6 +810,31 @@ void pack_tables(const Plan& p, int dtype, std::vector<unsigned char>& blob, Tab
       lay.fent_wadj = append(blob, wa.data(), wa.size());
     }
   }
+  // mixed-radix tables: combination twiddles e^{-2 pi i k / M}, M = R 2^l,
+  // and (-start_k) mod M_k per band
+  {
+    const int L = p.mix_L;
+    std::vector<double> tm(2 * (size_t)mix_tw_base(5, L + 1, L), 0.0);
+    if (p.mixed)
+      for (int R : {3, 5})
+        for (int l = 1; l <= L; ++l) {
+          const int64_t M = (int64_t)R << l, b0 = mix_tw_base(R, l, L);
+          for (int64_t k = 0; k < M; ++k) {
+            const double a = 2.0 * M_PI * (double)k / (double)M;
+            tm[2 * (b0 + k)] = std::cos(a);
+            tm[2 * (b0 + k) + 1] = -std::sin(a);
+          }
+        }
+    std::vector<int32_t> sm;
+    for (const BandInfo& b : p.bands) sm.push_back((int32_t)(((-b.start) % b.M + b.M) % b.M));
+    if (dtype == 0) {
+      std::vector<float> tf(tm.begin(), tm.end());
+      lay.twmix = append(blob, tf.data(), tf.size());
+    } else {
+      lay.twmix = append(blob, tm.data(), tm.size());
+    }
+    lay.bsmod = append(blob, sm.data(), sm.size());
+  }
   blob.resize((blob.size() + 255) & ~size_t(255));
   lay.total = blob.size();
 }
@@ -787,6 +847,11 @@ int build_full(const Plan& p, int64_t L, int lattice, FullPlan& out, std::string
   }
   if (L < p.two_n || (L & (L - 1)) || L > (int64_t(1) << (2 * kLongLog))) {
     err = "L must be a power of two, at least the slice length 2N and at most 2^24";
+    return -1;
+  }
+  if (lattice == 0 && p.mixed) {
+    err = "the sliCQ lattice of a plan with M_k = 3 2^a or 5 2^a needs mixed-radix transforms of length L; "
+          "use the painless lattice";
     return -1;
   }
   const int64_t r = L / p.two_n;

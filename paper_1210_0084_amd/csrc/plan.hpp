@@ -25,7 +25,8 @@ struct PlanParams {
   int32_t window = 0;           // band window: 0 Hann, 1 Blackman-Harris (4 terms)
   int32_t scale = 0;            // centres: 0 constant-Q (geometric), 1 mel, 2 Bark
   int32_t slicing = 0;          // 0 Tukey (sum_m h_m = 1), 1 square root of Tukey (sum_m h_m^2 = 1)
-  int32_t m_policy = 0;         // 0 smallest power of two >= |J_k|, 1 one M for every band (rectangular)
+  int32_t m_policy = 0;         // 0 smallest power of two >= |J_k|, 1 one M for every band (rectangular),
+                                // 2 smallest even 2^a, 3 2^a or 5 2^a >= |J_k|
 };
 
 // The fused per-slice schedule of one dtype (see FusedItemDev).
@@ -49,7 +50,7 @@ struct BandInfo {
   int64_t start = 0;   // signed first bin of J_k
   int32_t len = 0;     // |J_k|
   int32_t M = 0;       // M_k = 2N / a_k
-  int32_t logM = 0;
+  int32_t logM = 0;    // M_k = R 2^logM with R in {1, 3, 5}
   int64_t off = 0;     // sum_{k' < k} M_k'
   int64_t goff = 0;    // offset in the concatenated window tables
   int32_t hlo = 0, hhi = 0;   // bins of J_k inside [0, N]
@@ -75,6 +76,8 @@ struct Plan {
   std::vector<double> ent_wsyn, ent_wadj;
   int64_t coefs_per_slice = 0;
   int32_t max_M = 0;
+  bool mixed = false;                   // some M_k = 3 2^a or 5 2^a: band kernels for mixed radix
+  int32_t mix_L = 0;                    // largest logM among bands with M_k = 3 2^a or 5 2^a
 
   // kernel schedule
   std::vector<AnaGroupDev> ana;

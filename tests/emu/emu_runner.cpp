@@ -8,7 +8,7 @@
 // emulated LDS is filled with NaN before every block and its bytes past the
 // launch's dynamic size are checked after every block.
 //
-// usage: emu_runner OP DTYPE fs fmin fmax B 2N M min_win dual group_cap lds_cap pass_cap chunk layout fused IN OUT
+// usage: emu_runner OP DTYPE fs fmin fmax B 2N M min_win dual group_cap lds_cap pass_cap chunk layout fused m_policy IN OUT
 //   OP: ana | syn | adj       IN: T then T doubles (ana) / S*C complex doubles (syn, adj)
 //       bana | bsyn | badj    IN: nsig, lengths[nsig], then samples or coefficients, packed
 #include <cstdio>
@@ -176,8 +176,9 @@ int run(const std::string& op, slicq::Plan& p, int dt, int64_t chunk_req, const 
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 19) {
-    std::fprintf(stderr, "usage: %s OP DTYPE fs fmin fmax B 2N M min_win dual group_cap lds_cap pass_cap chunk layout fused IN OUT\n",
+  if (argc != 20) {
+    std::fprintf(stderr, "usage: %s OP DTYPE fs fmin fmax B 2N M min_win dual group_cap lds_cap pass_cap chunk layout fused "
+                 "m_policy IN OUT\n",
                  argv[0]);
     return 2;
   }
@@ -198,6 +199,7 @@ int main(int argc, char** argv) {
   const int64_t chunk = std::atoll(argv[14]);
   pp.coef_layout = std::atoi(argv[15]);
   pp.fused = std::atoi(argv[16]);
+  pp.m_policy = std::atoi(argv[17]);
   slicq::Plan plan;
   std::string err;
   if (slicq::build_plan(pp, plan, err)) {
@@ -208,6 +210,6 @@ int main(int argc, char** argv) {
     std::fprintf(stderr, "the fused schedule was asked for but does not fit this plan and dtype\n");
     return 19;
   }
-  const std::vector<double> in = read_all(argv[17]);
-  return dt == 0 ? run<float>(op, plan, dt, chunk, in, argv[18]) : run<double>(op, plan, dt, chunk, in, argv[18]);
+  const std::vector<double> in = read_all(argv[18]);
+  return dt == 0 ? run<float>(op, plan, dt, chunk, in, argv[19]) : run<double>(op, plan, dt, chunk, in, argv[19]);
 }

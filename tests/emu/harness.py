@@ -25,14 +25,14 @@ STREAM_EXE = os.path.join(BUILD, "stream_runner")
 FULL_EXE = os.path.join(BUILD, "full_runner")
 
 
-def _build(exe: str, main_src: str) -> str:
+def _build(exe: str, main_src: str, opt: str = "-O1") -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = [main_src, os.path.join(CSRC, "plan.cpp")]
     deps = srcs + HEADERS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")]
     if os.path.exists(exe) and os.path.getmtime(exe) > max(os.path.getmtime(d) for d in deps):
         return exe
     tmp = f"{exe}.{os.getpid()}.tmp"       # parallel test workers may build at once
-    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+    cmd = ["g++", "-std=c++20", opt, "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
            "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", *srcs, "-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, exe)
@@ -46,7 +46,8 @@ def build() -> str:
 def stream(plan: dict, signals, hop: int, dtype: int = 1, mode: int = 0, max_streams: int = 8,
            max_batch: int = 16, budget: int = 0):
     """Runs the streaming scenario of stream_runner.cpp; returns (outputs, stats)."""
-    exe = _build(STREAM_EXE, os.path.join(HERE, "stream_runner.cpp"))
+    # the streaming scenarios are tiny: an unoptimised build compiles several times faster
+    exe = _build(STREAM_EXE, os.path.join(HERE, "stream_runner.cpp"), "-O0")
     lens = [len(s) for s in signals]
     payload = np.concatenate([[len(signals)], lens] + [np.asarray(s, dtype=np.float64) for s in signals])
     with tempfile.TemporaryDirectory() as td:
@@ -81,7 +82,8 @@ def run(op: str, dtype: int, plan: dict, payload: np.ndarray, chunk: int = 0,
         args = [exe, op, str(dtype), repr(float(plan["fs"])), repr(float(plan["fmin"])), repr(float(plan["fmax"])),
                 str(plan["bins_per_octave"]), str(plan["slice_len"]), str(plan["transition"]),
                 repr(float(plan.get("min_win", 16.0))), str(plan.get("dual", 0)), str(group_cap), str(lds_cap),
-                str(pass_cap), str(chunk), str(layout), str(int(fused)), fin, fout]
+                str(pass_cap), str(chunk), str(layout), str(int(fused)),
+                str({"pow2": 0, "rect": 1, "smooth": 2}[plan.get("m_policy", "pow2")]), fin, fout]
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
         r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=900)
         if r.returncode != 0:

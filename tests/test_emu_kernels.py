@@ -22,7 +22,9 @@ def rel(a, b):
 
 @pytest.mark.parametrize("dtype", [1, 0])
 @pytest.mark.parametrize("kw,T,fused", [(TINY, 1, 0), (TINY, 100, 0), (TINY2, 300, 0), (SIXTEEN, 37, 0),
-                                        (TINY, 1, 1), (TINY, 100, 1), (TINY2, 300, 1)])
+                                        (TINY, 1, 1), (TINY, 100, 1), (TINY2, 300, 1),
+                                        (dict(TINY2, m_policy="smooth"), 300, 0),
+                                        (dict(TINY, m_policy="smooth"), 100, 0)])
 def test_emu_roundtrip_and_adjoint(kw, T, fused, dtype):
     # fused = 1: one workgroup per slice (half spectrum and band transforms in LDS)
     pl = OraclePlan(**kw)
@@ -87,6 +89,20 @@ def test_emu_preset_shapes(kw, fused):
     ref = pack(pl, analyze(pl, x))
     assert rel(H.analyze(kw, x, 0, fused=fused), ref) <= 1e-5
     assert rel(H.synthesize(kw, ref, T, 0, fused=fused), x) <= 1e-5
+
+
+@pytest.mark.parametrize("kw", [C4, C5], ids=["c4", "c5"])
+def test_emu_smooth_policy_presets(kw):
+    # M_k the smallest even 2^a, 3 2^a or 5 2^a: mixed-radix band kernels at
+    # full slice length (many M = 12, 20, 24, 40 ... bands in c5)
+    kw = dict(kw, m_policy="smooth")
+    pl = OraclePlan(**kw)
+    assert any(b.M % 3 == 0 for b in pl.bands) and any(b.M % 5 == 0 for b in pl.bands)
+    T = 9000
+    x = np.random.default_rng(4).standard_normal(T)
+    ref = pack(pl, analyze(pl, x))
+    assert rel(H.analyze(kw, x, 0), ref) <= 1e-5
+    assert rel(H.synthesize(kw, ref, T, 0), x) <= 1e-5
 
 
 def test_emu_slice_major_layout():

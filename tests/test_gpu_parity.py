@@ -129,6 +129,28 @@ def test_preset_shapes_f32(sq, dev, name, T, fused):
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("name,T", [("c2", 150000), ("c5", 60000), ("c3", 100000)])
+def test_smooth_policy_presets(sq, dev, name, T, dt):
+    # M_k the smallest even 2^a, 3 2^a or 5 2^a (radix-3/5 band transforms,
+    # fractional hops): coefficients per band, reconstruction, adjoint and
+    # synthesis of random coefficients against the oracle
+    p = PRESETS[name]
+    kw = dict(preset(name), m_policy="smooth")
+    plan, opl = gpu_plan(sq, kw)
+    assert any(m % 3 == 0 or m % 5 == 0 for m in plan.M)
+    x = pink_plus_tones(T, p.fs, 78)
+    check_roundtrip(sq, dev, kw, x, dt)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("T", [1, 63, 64, 65, 300, 1000])
+def test_smooth_policy_tiny(sq, dev, T, dt):
+    kw = dict(TINY2, m_policy="smooth")
+    x = np.random.default_rng(T + 7).standard_normal(T)
+    check_roundtrip(sq, dev, kw, x, dt, seed=T)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_fused_and_pipeline_agree(sq, dev, dt):
     # the two kernel paths compute the same transform (to rounding): 2N = 8192
     # fits one workgroup in both FP32 and FP64

@@ -45,6 +45,8 @@ VARIANTS = [
     (dict(C4, slicing="sqrt_tukey"), "sqrt"),
     (dict(fs=8000.0, fmin=200.0, fmax=3000.0, bins_per_octave=48, slice_len=4096, transition=1024, min_win=4.0,
           m_policy="rect"), "rect"),
+    (dict(C4, m_policy="smooth"), "smooth"),
+    (dict(C4, m_policy="smooth", scale="mel", window="blackman_harris"), "smooth-mel-bh"),
 ]
 
 

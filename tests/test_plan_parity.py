@@ -17,6 +17,12 @@ CASES += [
          slicing="sqrt_tukey"),
     dict(fs=8000.0, fmin=200.0, fmax=3000.0, bins_per_octave=48, slice_len=4096, transition=1024, min_win=4.0,
          m_policy="rect"),
+    dict(fs=44100.0, fmin=32.7, fmax=22050.0, bins_per_octave=48, slice_len=65536, transition=8192,
+         m_policy="smooth"),
+    dict(fs=48000.0, fmin=27.5, fmax=20000.0, bins_per_octave=96, slice_len=16384, transition=2048,
+         m_policy="smooth", window="blackman_harris"),
+    dict(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0,
+         m_policy="smooth"),
     dict(fs=64.0, fmin=4.0, fmax=16.0, bins_per_octave=3, slice_len=64, transition=8, min_win=0.0),
     dict(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0),
     dict(fs=44100.0, fmin=50.0, fmax=22000.0, bins_per_octave=48, slice_len=4096, transition=1024, min_win=8.0),
