@@ -90,7 +90,7 @@ def copy_rate(nbytes: int = 1 << 30, reps: int = 10) -> float:
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "fused.hpp", "coefops.hpp", "fft_device.hpp", "pipeline.hpp", "common.hpp",
+    for f in ("kernels.hpp", "fused.hpp", "bandmix.hpp", "coefops.hpp", "fft_device.hpp", "pipeline.hpp", "common.hpp",
               "plan.hpp", "plan.cpp"):
         with open(os.path.join(ROOT, "paper_1210_0084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
