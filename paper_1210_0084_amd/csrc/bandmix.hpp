@@ -65,49 +65,56 @@ __device__ __forceinline__ int mix_pos(int b, int m, int M, int R, int logP) {
   return b * M + ((m - q * R) << logP) + q;
 }
 
-// The radix-R combination of nseq bands of length M = R 2^logP at LDS base,
-// in place: for each p, the R values p + r P (subsequence DFTs) become the
-// outputs p + q P.
-template <class T, int DIR, int R>
-__device__ __forceinline__ void mix_combine(C2<T>* buf, int base, int nseq, int M, int logP,
-                                            const C2<T>* __restrict__ twmix, int mixL, int tid, int nthr) {
+// The radix-R combination of nseq bands of length M = R 2^logP at LDS base:
+// for each p, the R values p + r P (subsequence DFTs) become the outputs
+// p + q P, handed to out(b, n, value) (in place in LDS, or to global memory).
+template <class T, int DIR, int R, class OUT>
+__device__ __forceinline__ void mix_combine(const C2<T>* buf, int base, int nseq, int M, int logP,
+                                            const C2<T>* __restrict__ twmix, int mixL, int tid, int nthr, OUT out) {
   const int P = 1 << logP, units = nseq << logP;
   const C2<T>* __restrict__ tw = twmix + mix_tw_base(R, logP, mixL);   // e^{-2 pi i k / M}
   for (int u = tid; u < units; u += nthr) {
     const int b = u >> logP, p = u & (P - 1);
     const int p0 = base + b * M + p;
-    C2<T> y[R];
+    C2<T> y[R], w[R];
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r] = tw[r * p];
 #pragma unroll
     for (int r = 0; r < R; ++r) y[r] = buf[pidx(p0 + r * P)];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      C2<T> w = tw[r * p];
-      if constexpr (DIR > 0) w.y = -w.y;
-      y[r] = cmul(y[r], w);
+      if constexpr (DIR > 0) w[r].y = -w[r].y;
+      y[r] = cmul(y[r], w[r]);
     }
     dft_small<T, DIR, R>(y);
 #pragma unroll
-    for (int q = 0; q < R; ++q) buf[pidx(p0 + q * P)] = y[q];
+    for (int q = 0; q < R; ++q) out(b, p + q * P, y[q]);
   }
 }
 
-// Power-of-two FFTs of every subsequence, then the radix-R combination in
-// place (natural order out). nseq bands of length M at LDS base. Ends with a
-// barrier.
-template <class T, int DIR, int E, class TW>
-__device__ __forceinline__ void mix_fft(const KArgs<T>& a, C2<T>* buf, int base, int nseq, int M, int logP,
-                                        const TW& tws, int tid, int nthr) {
+// Power-of-two FFTs of every subsequence, then the radix-R combination
+// (natural order) handed to out(b, n, value); for R = 1 the caller reads the
+// result from LDS. nseq bands of length M at LDS base. Returns R; ends with
+// a barrier when the combination wrote LDS.
+template <class T, int DIR, int E, class TW, class OUT>
+__device__ __forceinline__ int mix_fft(const KArgs<T>& a, C2<T>* buf, int base, int nseq, int M, int logP,
+                                       const TW& tws, int tid, int nthr, OUT out) {
   const int R = M >> logP;
   lds_fft_contig<T, DIR, E, 8>(buf, base, logP, nseq * R, tws, tid, nthr);
   __syncthreads();
-  if (R == 3) mix_combine<T, DIR, 3>(buf, base, nseq, M, logP, a.twmix, a.mixL, tid, nthr);
-  else if (R == 5) mix_combine<T, DIR, 5>(buf, base, nseq, M, logP, a.twmix, a.mixL, tid, nthr);
-  if (R > 1) __syncthreads();
+  if (R == 3) mix_combine<T, DIR, 3>(buf, base, nseq, M, logP, a.twmix, a.mixL, tid, nthr, out);
+  else if (R == 5) mix_combine<T, DIR, 5>(buf, base, nseq, M, logP, a.twmix, a.mixL, tid, nthr, out);
+  return R;
 }
+
+// Values handled per batch of a loop over a work item: addresses first, then
+// every load of the batch in flight, then the uses.
+constexpr int kMixBatch = 8;
 
 // Band analysis of a group of equal-M bands of one slice (the work items and
 // grid of k_band_ana): gather X g_k wrapped modulo M (bins outside [0, N]
-// through conjugate symmetry), inverse DFT of length M, coefficient stores.
+// through conjugate symmetry) into the subsequence layout, inverse DFT of
+// length M, coefficient stores (from the combination directly when R > 1).
 template <class T, int E>
 __global__ void __launch_bounds__(kMixThreads) k_band_ana_mx(KArgs<T> a, const SliceTask* __restrict__ tasks,
                                                              const C2<T>* __restrict__ W2, C2<T>* __restrict__ coef,
@@ -121,38 +128,56 @@ __global__ void __launch_bounds__(kMixThreads) k_band_ana_mx(KArgs<T> a, const S
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int M = G.M, logP = G.logM, R = M >> logP, total = G.cnt * M;
   const C2<T>* __restrict__ X = W2 + (int64_t)task * a.ws2;
-  for (int i = tid; i < total; i += nthr) {
-    const int b = div_r(i >> logP, R), m = i - b * M;
-    const BandDev B = a.bands[G.k0 + b];
-    int t = m + a.bsmod[G.k0 + b];               // (m - start) mod M
-    if (t >= M) t -= M;
-    C2<T> v{T(0), T(0)};
-    if (t < B.len) {
+#pragma unroll
+  for (int e0 = 0; e0 < E; e0 += kMixBatch) {
+    int xi[kMixBatch], wi[kMixBatch], pos[kMixBatch];
+#pragma unroll
+    for (int e = 0; e < kMixBatch; ++e) {
+      const int i = tid + (e0 + e) * nthr;
+      const int ic = imin(i, total - 1);
+      const int b = div_r(ic >> logP, R), m = ic - b * M;
+      const BandDev B = a.bands[G.k0 + b];
+      int t = m + a.bsmod[G.k0 + b];             // (m - start) mod M
+      if (t >= M) t -= M;
+      const bool in = i < total && t < B.len;
       const int jb = B.start + t;                 // signed bin, -N < jb < 2N
-      const bool cj = jb < 0 || jb > a.N;
       const int jj = jb < 0 ? -jb : (jb > a.N ? 2 * a.N - jb : jb);
-      const C2<T> x = X[jj];
-      const T w = a.g[B.goff + t];
-      v = {x.x * w, (cj ? -x.y : x.y) * w};
+      xi[e] = in ? ((jb < 0 || jb > a.N) ? ~jj : jj) : 0;   // ~jj (< 0) marks a conjugate
+      wi[e] = in ? B.goff + t : -1;
+      pos[e] = i < total ? mix_pos(b, m, M, R, logP) : -1;
     }
-    buf[pidx(mix_pos(b, m, M, R, logP))] = v;
+    C2<T> v[kMixBatch];
+    T w[kMixBatch];
+#pragma unroll
+    for (int e = 0; e < kMixBatch; ++e) {
+      v[e] = X[xi[e] < 0 ? ~xi[e] : xi[e]];
+      w[e] = a.g[imax(wi[e], 0)];
+    }
+#pragma unroll
+    for (int e = 0; e < kMixBatch; ++e) {
+      if (pos[e] < 0) continue;
+      const T g = wi[e] < 0 ? T(0) : w[e];
+      buf[pidx(pos[e])] = {v[e].x * g, (xi[e] < 0 ? -v[e].y : v[e].y) * g};
+    }
   }
   __syncthreads();
-  mix_fft<T, 1, E>(a, buf, 0, G.cnt, M, logP, TwGlobal<T>{a.tw}, tid, nthr);
   C2<T>* __restrict__ cs = coef + tk.coef_base;
   const int off0 = a.bands[G.k0].off;
   const int cbase = a.slice_major ? tk.m * a.cps + off0 : tk.S * off0 + tk.m * M;
   const int bstride = a.slice_major ? M : tk.S * M;
-  for (int i = tid; i < total; i += nthr) {
-    const int b = div_r(i >> logP, R), n = i - b * M;
-    cs[cbase + b * bstride + n] = buf[pidx(i)];
+  auto store = [&](int b, int n, C2<T> v) { cs[cbase + b * bstride + n] = v; };
+  if (mix_fft<T, 1, E>(a, buf, 0, G.cnt, M, logP, TwGlobal<T>{a.tw}, tid, nthr, store) == 1) {
+    for (int i = tid; i < total; i += nthr) {
+      const int b = i >> logP, n = i - (b << logP);
+      store(b, n, buf[pidx(i)]);
+    }
   }
 }
 
 // Band synthesis of the owned bins [lo, hi) of one slice (the work items,
 // runs and grid of k_band_syn): coefficient loads into the subsequence
-// layout, DFTs of length M per run, then each owned bin's overlap-add
-// program over the natural-order spectra (LDS positions from the plan).
+// layout, DFTs of length M per run (natural order back in LDS), then each
+// owned bin's overlap-add program (LDS positions from the plan).
 template <class T, int E>
 __global__ void __launch_bounds__(kMixThreads) k_band_syn_mx(KArgs<T> a, const SliceTask* __restrict__ tasks,
                                                              const C2<T>* __restrict__ coef, C2<T>* __restrict__ W2,
@@ -166,17 +191,32 @@ __global__ void __launch_bounds__(kMixThreads) k_band_syn_mx(KArgs<T> a, const S
   if (tk.S == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const C2<T>* __restrict__ cs = coef + tk.coef_base;
-  for (int ri = 0; ri < G.nrun; ++ri) {
-    SynRunDev Rn;
-    if (ri == 0) Rn = G.r[0];
-    else if (ri == 1) Rn = G.r[1];
-    else Rn = a.runs[G.run0 + ri];
-    const int M = Rn.M, logP = Rn.logM, R = M >> logP, cnt = Rn.cnt * M;
-    for (int i = tid; i < cnt; i += nthr) {
-      const int b = div_r(i >> logP, R), n = i - b * M;
-      const int idx = a.slice_major ? tk.m * a.cps + Rn.off + b * M + n : tk.S * (Rn.off + b * M) + tk.m * M + n;
-      buf[pidx(Rn.lds_off + mix_pos(b, n, M, R, logP))] = cs[idx];
+  // all runs' loads as one flat range of G.total values (runs are contiguous in LDS)
+#pragma unroll
+  for (int e0 = 0; e0 < E; e0 += kMixBatch) {
+    int src[kMixBatch], dst[kMixBatch];
+#pragma unroll
+    for (int e = 0; e < kMixBatch; ++e) {
+      const int i = tid + (e0 + e) * nthr;
+      const int ic = imin(i, G.total - 1);
+      SynRunDev Rn = G.r[0];
+      if (G.nrun > 1 && ic >= G.r[1].lds_off) Rn = G.r[1];
+      for (int ri = 2; ri < G.nrun; ++ri) {
+        const SynRunDev Q = a.runs[G.run0 + ri];
+        if (ic >= Q.lds_off) Rn = Q;
+      }
+      const int M = Rn.M, logP = Rn.logM, R = M >> logP;
+      const int q = ic - Rn.lds_off;
+      const int b = div_r(q >> logP, R), n = q - b * M;
+      src[e] = a.slice_major ? tk.m * a.cps + Rn.off + b * M + n : tk.S * (Rn.off + b * M) + tk.m * M + n;
+      dst[e] = i < G.total ? Rn.lds_off + mix_pos(b, n, M, R, logP) : -1;
     }
+    C2<T> v[kMixBatch];
+#pragma unroll
+    for (int e = 0; e < kMixBatch; ++e) v[e] = cs[src[e]];
+#pragma unroll
+    for (int e = 0; e < kMixBatch; ++e)
+      if (dst[e] >= 0) buf[pidx(dst[e])] = v[e];
   }
   __syncthreads();
   for (int ri = 0; ri < G.nrun; ++ri) {
@@ -186,7 +226,9 @@ __global__ void __launch_bounds__(kMixThreads) k_band_syn_mx(KArgs<T> a, const S
     else Rn = a.runs[G.run0 + ri];
     int t = tid;
     asm volatile("" : "+v"(t));      // keeps each FFT length's address arithmetic inside the loop (registers)
-    mix_fft<T, -1, E>(a, buf, Rn.lds_off, Rn.cnt, Rn.M, Rn.logM, TwGlobal<T>{a.tw}, t, nthr);
+    auto back = [&](int b, int n, C2<T> v) { buf[pidx(Rn.lds_off + b * Rn.M + n)] = v; };
+    if (mix_fft<T, -1, E>(a, buf, Rn.lds_off, Rn.cnt, Rn.M, Rn.logM, TwGlobal<T>{a.tw}, t, nthr, back) > 1)
+      __syncthreads();
   }
   C2<T>* Z = W2 + (int64_t)task * a.ws2;
   for (int j = G.lo + tid; j < G.hi; j += nthr) {

@@ -20,23 +20,49 @@ BUILD = os.path.join(HERE, "_build")
 EXE = os.path.join(BUILD, "emu_runner")
 SOURCES = [os.path.join(HERE, "emu_runner.cpp"), os.path.join(CSRC, "plan.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "fft_device.hpp", "fused.hpp", "pipeline.hpp", "plan.hpp",
-                                            "common.hpp", "stream_server.hpp", "fullnsgt.hpp")]
+                                            "common.hpp", "stream_server.hpp", "fullnsgt.hpp", "bandmix.hpp", "coefops.hpp")]
 STREAM_EXE = os.path.join(BUILD, "stream_runner")
 FULL_EXE = os.path.join(BUILD, "full_runner")
 
 
-def _build(exe: str, main_src: str, opt: str = "-O1") -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = [main_src, os.path.join(CSRC, "plan.cpp")]
-    deps = srcs + HEADERS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")]
-    if os.path.exists(exe) and os.path.getmtime(exe) > max(os.path.getmtime(d) for d in deps):
-        return exe
+def _stale(exe: str, main_src: str) -> bool:
+    deps = [main_src, os.path.join(CSRC, "plan.cpp")] + HEADERS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")]
+    return not (os.path.exists(exe) and os.path.getmtime(exe) > max(os.path.getmtime(d) for d in deps))
+
+
+def _command(exe: str, main_src: str, opt: str):
     tmp = f"{exe}.{os.getpid()}.tmp"       # parallel test workers may build at once
     cmd = ["g++", "-std=c++20", opt, "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-           "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", *srcs, "-o", tmp]
+           "-pthread", f"-I{os.path.join(HERE, 'include')}", f"-I{CSRC}", main_src, os.path.join(CSRC, "plan.cpp"),
+           "-o", tmp]
+    return cmd, tmp
+
+
+def _build(exe: str, main_src: str, opt: str = "-O1") -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    if not _stale(exe, main_src):
+        return exe
+    cmd, tmp = _command(exe, main_src, opt)
     subprocess.check_call(cmd)
     os.replace(tmp, exe)
     return exe
+
+
+def build_all() -> None:
+    """Builds the stale runners side by side (a serial test run then waits for
+    the slowest compile only)."""
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = []
+    for exe, src, opt in ((EXE, "emu_runner.cpp", "-O1"), (STREAM_EXE, "stream_runner.cpp", "-O0"),
+                          (FULL_EXE, "full_runner.cpp", "-O1")):
+        src = os.path.join(HERE, src)
+        if _stale(exe, src):
+            cmd, tmp = _command(exe, src, opt)
+            jobs.append((subprocess.Popen(cmd), tmp, exe))
+    for proc, tmp, exe in jobs:
+        if proc.wait() != 0:
+            raise RuntimeError(f"building {exe} failed")
+        os.replace(tmp, exe)
 
 
 def build() -> str:

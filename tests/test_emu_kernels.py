@@ -8,6 +8,12 @@ import pytest
 from oracle import OraclePlan, analyze, synthesize, adjoint, pack, unpack, num_slices
 from tests.emu import harness as H
 
+
+@pytest.fixture(scope="module", autouse=True)
+def _runners():
+    H.build_all()
+
+
 TINY = dict(fs=64.0, fmin=4.0, fmax=16.0, bins_per_octave=3, slice_len=64, transition=8, min_win=0.0)
 TINY2 = dict(fs=100.0, fmin=6.0, fmax=40.0, bins_per_octave=4, slice_len=128, transition=16, min_win=4.0)
 SIXTEEN = dict(fs=16.0, fmin=2.0, fmax=6.0, bins_per_octave=2, slice_len=16, transition=2, min_win=1.0)
