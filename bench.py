@@ -25,6 +25,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -201,6 +202,15 @@ def cpu_baseline(xs):
         t_pool = _median_time(pooled)
         perr = float(np.abs(pooled() - x).max())
     rate = lambda n, t: n / t / 1e6
+    # the other FP32 configurations' plans, single process, on one signal each
+    from workloads import noise_plus_sines
+    side = {}
+    for name, T_s in (("c3", int(10 * 44100)), ("c4", 264600), ("c5", int(10 * 48000))):
+        pk = _preset(name)
+        ok = OraclePlan(**pk)
+        xk = noise_plus_sines(T_s, pk["fs"], 7)
+        tk = _median_time(lambda: synthesize(ok, analyze(ok, xk), T_s))
+        side[name] = {"Msamples_per_s": round(rate(T_s, tk), 3), "seconds": round(tk, 4), "samples": T_s}
     return {"value": round(rate(T, t_pool), 3), "unit": "Msamples/s", "cores": len(ranges), "kind": "oracle",
             "sample": f"FP64 numpy oracle, analysis+synthesis of a 10 s excerpt ({T} samples, {S} slices) of the "
                       f"benchmark's left channel, slices split over a pool of {len(ranges)} processes; median of 5 "
@@ -210,6 +220,7 @@ def cpu_baseline(xs):
             "fp64_2p16_workload": {"seconds": round(t_c1, 4), "Msamples_per_s": round(rate(len(x1), t_c1), 3),
                                    "cores": 1, "sample": "2^16 samples, B=12, 110-11025 Hz, 2N=8192, M=1024, "
                                                          "analysis then synthesis"},
+            "side_by_side_single_process": side,
             "nproc": os.cpu_count(), "cpu_affinity": avail, "cpu_model": _cpu_model()}
 
 
@@ -576,6 +587,36 @@ def _bench_smooth(prm, x, y, T, args, copy_gbs):
                          "algorithmic_GBs": round(share["band_syn"] / (stage_ms["band_syn"] * 1e-3) / 1e9, 1)}}
 
 
+def _bench_fp64(args, copy_gbs):
+    """The FP64 path on the GPU: the 2^16-sample workload of the CPU baseline
+    (B=12, 2N=8192; 16 slices, launch-bound) and the benchmark's 60 s stereo
+    in FP64, analysis + synthesis per step, with their FP64 algorithmic bytes."""
+    import torch
+    import paper_1210_0084_amd as sq
+    from workloads import make_c1, make_c2
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, sig in (("c1_2p16", make_c1()[None, :]), ("c2_60s_stereo", make_c2())):
+        plan = sq.Plan(**_preset("c1" if name.startswith("c1") else "c2"))
+        T = sig.shape[1]
+        lay = plan.batch_layout([T] * sig.shape[0])
+        x = torch.tensor(sig.reshape(-1), dtype=torch.float64, device=dev)
+        coef = torch.empty(lay.coef_len, dtype=torch.complex128, device=dev)
+        y = torch.empty_like(x)
+
+        def step():
+            plan.analyze_batched(x, out=coef, layout=lay)
+            plan.synthesize_batched(coef, out=y, layout=lay)
+        ms = _time(step, args.steps, args.warmup)
+        nbytes = 2 * 8 * x.numel() + 2 * 16 * lay.total_slices * plan.coefs_per_slice
+        out[name] = {"Msamples_per_s": round(x.numel() / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                     "algorithmic_bytes": nbytes, **_frac(nbytes, ms, copy_gbs),
+                     "reconstruction_max_abs_err": float((y - x).abs().max())}
+        del x, coef, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def _form_summary(rec):
     """The key figures of a form's record, for the default line."""
     keep = {k: rec[k] for k in ("value", "unit", "ms_per_step") if k in rec}
@@ -606,7 +647,7 @@ def main():
     ap.add_argument("--c3-signals", type=int, default=256)
     ap.add_argument("--no-c3-tune", dest="c3_tune", action="store_false",
                     help="skip the autotuner for the ragged batch (default: tune, cached per batch shape)")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "slicq_tune_cache.json"))
     ap.add_argument("--c4-batch", type=int, default=32)
     ap.add_argument("--fused", action="store_true",
                     help="batched, differentiable and streaming forms with one workgroup per slice where "
@@ -615,7 +656,7 @@ def main():
     ap.add_argument("--c5-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (slices would shard with a "
+        print("bench.py measures one GPU: the library has no multi-GPU path (slices would shard with a "
               "one-time overlap halo exchange). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
@@ -715,6 +756,7 @@ def main():
     }
     if not args.no_forms:
         rec["smooth_M"] = _bench_smooth(prm, x, y, T, args, copy_gbs)
+        rec["fp64"] = _bench_fp64(args, copy_gbs)
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)

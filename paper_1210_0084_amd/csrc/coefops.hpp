@@ -197,14 +197,28 @@ __global__ void __launch_bounds__(kLossThreads) k_logmag_loss(const C2<T>* __res
                                                               T* __restrict__ partial) {
   __shared__ T red[kLossThreads];
   T acc = T(0);
+  // four values per thread and round, all loads in flight before the arithmetic
+  constexpr int U = 4;
   const int64_t stride = (int64_t)gridDim.x * kLossThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kLossThreads + threadIdx.x; i < n; i += stride) {
-    const C2<T> v = c[i];
-    const T p = v.x * v.x + v.y * v.y;
-    const T d = log1p(p) - t[i];
-    acc += d * d;
-    const T s = T(4) * d / (T(1) + p);
-    grad[i] = {s * v.x, s * v.y};
+  for (int64_t i0 = (int64_t)blockIdx.x * kLossThreads + threadIdx.x; i0 < n; i0 += U * stride) {
+    C2<T> v[U];
+    T tv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = imin64(i0 + u * stride, n - 1);
+      v[u] = c[i];
+      tv[u] = t[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i >= n) break;
+      const T p = v[u].x * v[u].x + v[u].y * v[u].y;
+      const T d = log1p(p) - tv[u];
+      acc += d * d;
+      const T s = T(4) * d / (T(1) + p);
+      grad[i] = {s * v[u].x, s * v[u].y};
+    }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
