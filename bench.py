@@ -710,6 +710,19 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     samples = 2 * T
     value = samples / (ms * 1e-3) / 1e6
+    # each step timed on its own (median), and analysis and synthesis apart
+    per_step = []
+    for _ in range(max(args.steps, 20)):
+        a0, a1 = _events()
+        a0.record()
+        step()
+        a1.record()
+        torch.cuda.synchronize()
+        per_step.append(a0.elapsed_time(a1))
+    ms_ana = _time(lambda: plan.analyze_batched(x, out=coef, layout=lay), args.steps, 2)
+    ms_syn = _time(lambda: plan.synthesize_batched(coef, out=y, layout=lay), args.steps, 2)
+    step()
+    torch.cuda.synchronize()
 
     # per-kernel timing of the pipeline the last step launched (HIP events on the same stream)
     S = lay.total_slices
@@ -751,6 +764,8 @@ def main():
                  "frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "frac_of_copy": round(path_bytes / (ms * 1e-3) / 1e9 / copy_gbs, 4),
                  "host_wall_ms_per_step": round(t_host * 1e3 / args.steps, 4),
+                 "median_ms_per_step": round(float(np.median(per_step)), 4),
+                 "analysis_ms": round(ms_ana, 4), "synthesis_ms": round(ms_syn, 4),
                  "reconstruction_max_abs_err": err},
         "stages": stages,
     }

@@ -181,6 +181,34 @@ def test_layers_masks_transposition(sq, dev, layout):
         p2.transpose(c2, S, 8)
 
 
+@pytest.mark.parametrize("layout", ["band", "slice"])
+def test_layers_and_masks_smooth_policy(sq, dev, layout):
+    # layer sums, spectrogram and masks with M_k = 3 2^a and 5 2^a (layer
+    # positions and slice indices by general division)
+    import torch
+    kw = dict(fs=8000.0, fmin=200.0, fmax=3000.0, bins_per_octave=24, slice_len=4096, transition=1024, min_win=4.0,
+              m_policy="smooth")
+    plan = sq.Plan(**kw, layout=layout)
+    opl = OraclePlan(**kw)
+    assert any(b.M % 3 == 0 for b in opl.bands) and any(b.M % 5 == 0 for b in opl.bands)
+    T = 40000
+    x = pink_plus_tones(T, 8000.0, 6)
+    c_ref = analyze(opl, x)
+    S = num_slices(T, opl.two_n)
+    c = plan.analyze(torch.tensor(x, dtype=torch.float64, device=dev))
+    assert rel(plan.to_band_major(c, S).cpu().numpy(), pack(opl, c_ref)) <= 1e-12
+    ls = plan.layers(c, S).cpu().numpy()
+    sp = plan.layers(c, S, spectrogram=True).cpu().numpy()
+    lay = layers(opl, c_ref)
+    assert rel(ls, np.concatenate([a + b for a, b in lay])) <= 1e-12
+    assert rel(sp, np.concatenate(spectrogram(opl, c_ref))) <= 1e-12
+    g = np.random.default_rng(5)
+    masks = [g.uniform(0, 1, S * b.M // 2) for b in opl.bands]
+    cm = c.clone()
+    plan.mask_db(cm, S, torch.tensor(np.concatenate(masks), dtype=torch.float64, device=dev))
+    assert rel(plan.to_band_major(cm, S).cpu().numpy(), pack(opl, apply_mask(opl, c_ref, masks))) <= 1e-12
+
+
 def test_approximation_study_point(sq, dev):
     # Section 5.3 on the GPU: a random complex 2^17-sample signal, Blackman-
     # Harris bands, minimal filter length 16: s^0 + s^1 from the GPU sliCQ
