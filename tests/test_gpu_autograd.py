@@ -168,3 +168,36 @@ def test_gradient_through_loss_kernel_fd(sq, dev, plan):
         e[i] = h
         fd = (f(x0 + e) - f(x0 - e)) / (2 * h)
         assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, grad[i])
+
+
+def test_full_c4_batch_sampled_against_oracle(sq, dev, plan):
+    # the differentiable workload at full size (32 x 264600 samples, 1088
+    # slices) through SliCQFunction as the bench runs it: the coefficients and
+    # the input gradient of a linear loss of three sampled signals (first,
+    # middle, last) against the FP64 oracle, band by band
+    import torch
+    from oracle import analyze, pack
+    from workloads import make_c4
+    xb = make_c4(32)
+    B, T = xb.shape
+    x = torch.tensor(xb, dtype=torch.float32, device=dev, requires_grad=True)
+    c = sq.slicq(x, plan)
+    g = np.random.default_rng(61)
+    w = torch.tensor(g.standard_normal(tuple(c.shape)) + 1j * g.standard_normal(tuple(c.shape)),
+                     dtype=torch.complex64, device=dev)
+    (c.real * w.real + c.imag * w.imag).sum().backward()
+    torch.cuda.synchronize()
+    opl = OraclePlan(**c4_kw())
+    S = num_slices(T, opl.two_n)
+    for b in (0, 16, 31):
+        print(f"case c4 full batch, signal {b}", flush=True)
+        ref = pack(opl, analyze(opl, xb[b]))
+        got = c[b].detach().cpu().numpy()
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+        for k in range(opl.K + 2):
+            o, M = int(plan.offsets[k]) * S, int(plan.M[k])
+            r = ref[o:o + S * M]
+            assert np.linalg.norm(got[o:o + S * M] - r) <= 1e-4 * np.linalg.norm(r), (b, k)
+        gref = adjoint(opl, unpack(opl, w[b].cpu().numpy().astype(np.complex128), S), T)
+        gg = x.grad[b].cpu().numpy()
+        assert np.linalg.norm(gg - gref) <= 1e-5 * np.linalg.norm(gref), b

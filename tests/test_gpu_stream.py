@@ -269,3 +269,21 @@ def test_churn_alone_equals_in_a_large_mix_bitwise(sq, plan):
             for m in caps_a:
                 assert np.array_equal(caps_a[m], caps_mix[m])
     assert rel(np.concatenate(outs[n0 + 5])[:lens[n0 + 5]], sigs[n0 + 5]) <= 1e-5
+
+
+def test_full_size_service_sampled(sq, plan):
+    # the bench's service configuration (512 streams, 576 slots, batches of up
+    # to 1024 slices), every stream fed 0.5 s: every stream reconstructs its
+    # input, and one stream's coefficients match the oracle's linear analysis
+    srv = sq.StreamServer(plan, "f32", max_streams=576, max_batch=1024)
+    sigs = [pink_plus_tones(24000, 48000.0, 5_000_000 + i) for i in range(512)]
+    ids = [srv.open() for _ in sigs]
+    outs, caps = feed(srv, ids, sigs, coefs_of=ids[300])
+    worst = max(rel(outs[i], s) for i, s in zip(ids, sigs))
+    print(f"512 streams: worst reconstruction rel-L2 {worst:.2e}", flush=True)
+    assert worst <= 1e-5
+    opl = OraclePlan(**c5_kw())
+    ref = analyze_stream(opl, sigs[300], max(caps) + 1)
+    for m, c in caps.items():
+        r = np.concatenate([ck[m] for ck in ref])
+        assert rel(c, r) <= 1e-5, m
